@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs shared by the HIP path's callers and by the tests.
+
+This module holds no part of the method: it only produces nodal sample arrays
+(initial data, coefficient fields, node coordinates) with numpy's PCG64
+generator.  The same arrays are handed to the HIP library and to the CPU
+oracle.
+
+Layout of every nodal array: [ny, nx, N+1 (iy), N+1 (ix)], element e = ey*nx + ex,
+node (ix, iy) of element e at flat offset e*(N+1)^2 + iy*(N+1) + ix.  Nodes on
+element faces are duplicated (one copy per element).
+
+Workloads (all periodic on [0,1]^2):
+  * standing wave  u0 = sin(2 pi x) sin(2 pi y), v0 = 0; exact
+    u = u0 cos(2 sqrt(2) pi c t).
+  * Fourier superposition: for m = 1..8, k_m uniform on {k in Z^2 \\ 0 : |k| <= 16},
+    a_m ~ N(0,1)/|k_m|^2, theta_m ~ U[0, 2 pi); u0 = sum a_m cos(2 pi k_m.x + theta_m),
+    v0 = 0; exact u = sum a_m cos(2 pi |k_m| c t) cos(2 pi k_m.x + theta_m).
+  * smooth periodic Gaussian random field g (length scale 0.1): a random cosine
+    series over wave vectors 0 < |k| <= 10 (one half-plane) with amplitudes
+    N(0, exp(-2 pi^2 l^2 |k|^2)), normalised to unit variance, clipped to [-0.9, 0.9];
+    c^2 = 1 + 0.5 g.
+  * mapped mesh: X = x + eps s, Y = y + eps s with s = sin(2 pi x) sin(2 pi y),
+    eps = 0.05 (the identity on the boundary of the unit square).
+"""
+import numpy as np
+
+
+def node_coords(nx, ny, N, Lx=1.0, Ly=1.0, x0=0.0, y0=0.0):
+    """Cartesian node coordinates X, Y ([ny, nx, N+1, N+1]).
+
+    Coordinates are computed from the global node index so that the two copies of a
+    face node (one per element) are bitwise identical.
+    """
+    n1 = N + 1
+    gx = np.arange(nx)[:, None] * N + np.arange(n1)[None, :]          # [nx, n1]
+    gy = np.arange(ny)[:, None] * N + np.arange(n1)[None, :]          # [ny, n1]
+    xs = x0 + gx * (Lx / (nx * N))
+    ys = y0 + gy * (Ly / (ny * N))
+    X = np.broadcast_to(xs[None, :, None, :], (ny, nx, n1, n1)).copy()
+    Y = np.broadcast_to(ys[:, None, :, None], (ny, nx, n1, n1)).copy()
+    return X, Y
+
+
+def standing_wave(X, Y):
+    return np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+
+
+def fourier_modes(seed, n_modes=8, kmax=16):
+    """Draw (kx, ky, a, theta) for `n_modes` modes, |k| <= kmax, k != 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = [(i, j) for i in range(-kmax, kmax + 1) for j in range(-kmax, kmax + 1)
+          if 0 < i * i + j * j <= kmax * kmax]
+    out = []
+    for _ in range(n_modes):
+        kx, ky = ks[int(rng.integers(len(ks)))]
+        k2 = float(kx * kx + ky * ky)
+        a = float(rng.standard_normal()) / k2
+        th = float(rng.uniform(0.0, 2 * np.pi))
+        out.append((kx, ky, a, th))
+    return out
+
+
+def fourier_field(modes, X, Y, t=0.0, c=1.0):
+    """sum_m a_m cos(2 pi |k_m| c t) cos(2 pi k_m . x + theta_m)."""
+    u = np.zeros(np.broadcast(X, Y).shape)
+    for kx, ky, a, th in modes:
+        kn = np.hypot(kx, ky)
+        u += a * np.cos(2 * np.pi * kn * c * t) * np.cos(2 * np.pi * (kx * X + ky * Y) + th)
+    return u
+
+
+def grf(seed, X, Y, ell=0.1, kmax=10, clip=0.9):
+    """Clipped smooth periodic Gaussian random field sampled at (X, Y)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = [(i, j) for i in range(-kmax, kmax + 1) for j in range(0, kmax + 1)
+          if 0 < i * i + j * j <= kmax * kmax and (j > 0 or i > 0)]
+    var = np.array([np.exp(-2 * np.pi ** 2 * ell ** 2 * (i * i + j * j)) for i, j in ks])
+    amp = rng.standard_normal(len(ks)) * np.sqrt(var)
+    th = rng.uniform(0.0, 2 * np.pi, len(ks))
+    Z = np.sqrt(0.5 * var.sum())
+    g = np.zeros(np.broadcast(X, Y).shape)
+    for (i, j), a, t in zip(ks, amp, th):
+        g += a * np.cos(2 * np.pi * (i * X + j * Y) + t)
+    return np.clip(g / Z, -clip, clip)
+
+
+def c2_field(seed, X, Y):
+    """c^2 = 1 + 0.5 g with g the clipped field above (values in [0.55, 1.45])."""
+    return 1.0 + 0.5 * grf(seed, X, Y)
+
+
+def mapped_coords(X, Y, eps=0.05):
+    s = np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    return X + eps * s, Y + eps * s
+
+
+def cfl_dt(N, n, cfl=0.5, L=1.0):
+    """dt = CFL * h with h = L / (n N) the cell width."""
+    return cfl * L / (n * N)
