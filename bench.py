@@ -1,0 +1,153 @@
+"""Throughput benchmark of the hot path on one MI355X.
+
+Workload (the constant-coefficient Cartesian case): u_tt = Laplace(u) on the periodic
+unit square, 256 x 256 elements of 16 x 16 GD cells (N + 1 = 17 nodes per direction),
+degree p = 5, upwind flux (xi = c = 1), simultaneous-diagonalisation local solves,
+classical RK4 with dt = 0.15 h (h = 1/4096; CFL 0.5 is outside RK4's stability
+region for the upwind flux at p = 5), initial data a seeded superposition of 8
+Fourier modes (|k| <= 16, amplitude N(0,1)/|k|^2), v0 = 0.  One "step" is one full
+RK4 step (4 fused stage kernels) over all 18,939,904 DOF per field.
+
+Printed: ONE JSON line.  `value` = DOF-updates/s in FP64 (nx*ny*(N+1)^2 * steps /
+time; inputs resident in HBM).  Also reported: the FP32-storage mode, the error of
+both against the exact solution, the roofline of the stage kernel (algorithmic HBM
+bytes per launch / measured average launch time) and the FP64 CPU oracle timed on a
+bounded sample on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
+
+
+def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
+    from paper_2105_01722_amd import inputs
+    X, Y = inputs.node_coords(n, n, N)
+    modes = inputs.fourier_modes(seed)
+    U0 = inputs.fourier_field(modes, X, Y)
+    return dict(n=n, N=N, p=p, modes=modes, X=X, Y=Y, U0=U0, dt=cfl / (n * N))
+
+
+def _time_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_2105_01722_amd import gdw
+    n, N, p = w["n"], w["N"], w["p"]
+    s = gdw.Solver(n, n, N, p, c2=1.0, flux="upwind", xi=1.0, precision=precision)
+    U0 = torch.from_numpy(w["U0"]).cuda()
+    s.set_state(U0, torch.zeros_like(U0))
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.run(w["dt"], warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(w["dt"], steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    U, _ = s.get_state()
+    st = s.stats()
+    s.close()
+    from paper_2105_01722_amd import inputs
+    T = w["dt"] * (steps + warmup)
+    exact = inputs.fourier_field(w["modes"], w["X"], w["Y"], t=T)
+    Uh = U.cpu().numpy()
+    err = float(np.linalg.norm(Uh - exact) / np.linalg.norm(exact))
+    return ms, err, st
+
+
+def _cpu_baseline(w, n_patch=32, steps=10):
+    """The FP64 oracle, as it is, on a bounded sample: a 32 x 32-element periodic patch
+    of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps."""
+    from oracle import dg2d
+    from paper_2105_01722_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    N, p = w["N"], w["p"]
+    prob = dg2d.CartProblem(nx=n_patch, ny=n_patch, N=N, p=p, flux="upwind")
+    ops = dg2d.CartOps(prob)
+    X, Y = inputs.node_coords(n_patch, n_patch, N)
+    U = inputs.fourier_field(w["modes"], X, Y)
+    V = np.zeros_like(U)
+    t0 = time.perf_counter()
+    dg2d.run(U, V, ops, w["dt"], steps)
+    dt = time.perf_counter() - t0
+    return {"value": n_patch * n_patch * (N + 1) ** 2 * steps / dt, "unit": "DOF-updates/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": "%dx%d-element periodic patch, N=%d, p=%d, upwind, %d RK4 steps, FP64 "
+                      "(numpy/scipy dense Cholesky element solves)" % (n_patch, n_patch, N, p, steps),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path "
+              "(the element grid would shard by blocks with one face-trace exchange per "
+              "RK stage, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    w = _workload()
+    n, N = w["n"], w["N"]
+    ndof = n * n * (N + 1) ** 2
+    print("bench: workload ready, %d DOF per field" % ndof, file=sys.stderr, flush=True)
+    ms64, err64, st = _time_gpu(w, "fp64", args.steps, args.warmup)
+    print("bench: fp64 %.3f ms/step" % (ms64 / args.steps), file=sys.stderr, flush=True)
+    value = ndof * args.steps / (ms64 * 1e-3)
+    launches = 4 * args.steps
+    # algorithmic HBM bytes of a step: 12 field accesses per DOF per field (RK4 in the
+    # y / Y / accumulator form of the stage kernels), 2 fields
+    alg_bytes_step = 24 * 8 * ndof
+    achieved = alg_bytes_step * args.steps / (ms64 * 1e-3)
+    out = {
+        "metric": "DOF-updates/s per time step + mean PCG iters; FP64 plain vs mixed/learned @ fixed err",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms64 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D wave, periodic unit square, 256x256 Cartesian elements, "
+                               "16x16 GD cells (N+1=17), p=5, upwind, FDM mass solve, RK4 dt=0.15h, "
+                               "8 seeded Fourier modes",
+                   "elements": n * n, "N": N, "p": w["p"], "dof_per_field": ndof,
+                   "parallelism": "single GPU"},
+        "rel_err_vs_exact": err64,
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                     "kernel": "k_stage<double,*,17,4> (4 stage variants)",
+                     "avg_launch_us": ms64 * 1e3 / launches,
+                     "alg_bytes_per_launch": alg_bytes_step / 4},
+    }
+    if not args.no_fp32:
+        ms32, err32, _ = _time_gpu(w, "fp32", args.steps, args.warmup)
+        print("bench: fp32 %.3f ms/step" % (ms32 / args.steps), file=sys.stderr, flush=True)
+        out["fp32"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
+                       "rel_err_vs_exact": err32,
+                       "roofline_frac": 24 * 4 * ndof * args.steps / (ms32 * 1e-3) / HBM_PEAK}
+    if not args.no_cpu:
+        out["cpu_baseline"] = _cpu_baseline(w)
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

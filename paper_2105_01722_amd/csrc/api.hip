@@ -1,0 +1,388 @@
+// C ABI of libgdw (declared in include/gdw.h): context management, table set-up and
+// the RK4 time loop of the constant-coefficient path.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fdm.h"
+#include "gdw_internal.h"
+
+namespace gdw {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace gdw
+
+using namespace gdw;
+
+#define GDW_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (call);                                                               \
+    if (_e != hipSuccess) {                                                               \
+      set_error(std::string(#call) + ": " + hipGetErrorString(_e));                       \
+      return _e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;                           \
+    }                                                                                     \
+  } while (0)
+
+struct gdw_ctx {
+  gdw_desc d{};
+  int n1 = 0;
+  long nel = 0;
+  size_t elem_bytes = 0;       // sizeof(T) of the time-loop arithmetic
+  double alpha = 0, beta = 0, tau = 0;
+  // device buffers (time-loop type T)
+  void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void* tr[2] = {nullptr, nullptr};
+  void* invL = nullptr;
+  void* lam = nullptr;
+  void* gh = nullptr;
+  // device FP64 tables for the nodal <-> modal maps
+  double* Psx = nullptr;
+  double* Psy = nullptr;
+  double* Px = nullptr;
+  double* Py = nullptr;
+  double* epart = nullptr;     // energy partial sums + result
+  unsigned int* nonfinite = nullptr;
+  int npart = 1024;
+  int trc = 0;                 // trace buffer holding the traces of y
+  long long steps_taken = 0;
+  int have_state = 0;
+};
+
+static void free_all(gdw_ctx* c) {
+  auto F = [](void* p) { if (p) (void)hipFree(p); };
+  for (auto& r : c->Y) for (auto& p : r) F(p);
+  F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh);
+  F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
+}
+
+extern "C" const char* gdw_version(void) { return "gdw 0.1 (gfx950)"; }
+
+extern "C" const char* gdw_last_error(void) { return g_last_error.c_str(); }
+
+static gdw_status validate(const gdw_desc* d) {
+  if (!d) { set_error("desc is NULL"); return GDW_EINVAL; }
+  if (d->p < 1 || d->p % 2 == 0) { set_error("p must be odd and >= 1"); return GDW_EINVAL; }
+  if (d->p > 31) { set_error("p > 31 is not supported"); return GDW_EINVAL; }
+  if (d->N < d->p) { set_error("N must be >= p"); return GDW_EINVAL; }
+  if (d->N + 1 > 48) { set_error("N + 1 must be <= 48"); return GDW_EINVAL; }
+  if (d->nx < 1 || d->ny < 1) { set_error("nx, ny must be >= 1"); return GDW_EINVAL; }
+  if (!(d->Lx > 0) || !(d->Ly > 0) || !std::isfinite(d->Lx) || !std::isfinite(d->Ly)) {
+    set_error("Lx, Ly must be finite and > 0"); return GDW_EINVAL;
+  }
+  if (!(d->c2 > 0) || !std::isfinite(d->c2)) { set_error("c2 must be finite and > 0"); return GDW_EINVAL; }
+  if (d->flux != GDW_FLUX_CENTRAL && d->flux != GDW_FLUX_UPWIND) { set_error("unknown flux"); return GDW_EINVAL; }
+  if (d->flux == GDW_FLUX_UPWIND && (!(d->xi > 0) || !std::isfinite(d->xi))) {
+    set_error("xi must be finite and > 0 for the upwind flux"); return GDW_EINVAL;
+  }
+  if (d->precision != GDW_FP64 && d->precision != GDW_MIXED_FP32) { set_error("unknown precision"); return GDW_EINVAL; }
+  if (d->solver != GDW_SOLVE_AUTO && d->solver != GDW_SOLVE_FDM && d->solver != GDW_SOLVE_PCG) {
+    set_error("unknown solver"); return GDW_EINVAL;
+  }
+  if (d->solver == GDW_SOLVE_PCG) { set_error("the PCG solver is not available in this build"); return GDW_EUNSUPPORTED; }
+  const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
+  if (nel > 4.0e9) { set_error("problem too large"); return GDW_EINVAL; }
+  return GDW_OK;
+}
+
+// Eigenbasis of one direction on the device (FP64) -> host copies of Psi and lambda.
+static gdw_status eigen_dir(int N, int p, double H, std::vector<double>& Psi,
+                            std::vector<double>& lam, std::vector<double>& M,
+                            std::vector<double>& dL, std::vector<double>& dR) {
+  const int n1 = N + 1;
+  std::vector<double> Mh(n1 * n1), Sh(n1 * n1), dLh(n1), dRh(n1);
+  gd1d_unit(N, p, Mh.data(), Sh.data(), dLh.data(), dRh.data());
+  const double h = H / N;
+  M.resize(n1 * n1);
+  std::vector<double> S(n1 * n1);
+  for (int i = 0; i < n1 * n1; ++i) { M[i] = h * Mh[i]; S[i] = Sh[i] / h; }
+  dL.resize(n1); dR.resize(n1);
+  for (int i = 0; i < n1; ++i) { dL[i] = dLh[i] / h; dR[i] = dRh[i] / h; }
+  double *dM = nullptr, *dS = nullptr, *work = nullptr, *dPsi = nullptr, *dlam = nullptr;
+  int* dinfo = nullptr;
+  gdw_status st = GDW_OK;
+  auto cleanup = [&]() {
+    if (dM) (void)hipFree(dM); if (dS) (void)hipFree(dS); if (work) (void)hipFree(work);
+    if (dPsi) (void)hipFree(dPsi); if (dlam) (void)hipFree(dlam); if (dinfo) (void)hipFree(dinfo);
+  };
+  hipError_t e = hipSuccess;
+  do {
+    if ((e = hipMalloc(&dM, n1 * n1 * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&dS, n1 * n1 * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&work, (3 * n1 * n1 + n1) * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&dPsi, n1 * n1 * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&dlam, n1 * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&dinfo, (1 + n1) * sizeof(int))) != hipSuccess) break;
+    if ((e = hipMemcpy(dM, M.data(), n1 * n1 * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = hipMemcpy(dS, S.data(), n1 * n1 * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = launch_eig(dM, dS, n1, work, dPsi, dlam, dinfo, nullptr)) != hipSuccess) break;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) break;
+    Psi.resize(n1 * n1); lam.resize(n1);
+    int info = 0;
+    if ((e = hipMemcpy(Psi.data(), dPsi, n1 * n1 * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) break;
+    if ((e = hipMemcpy(lam.data(), dlam, n1 * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) break;
+    if ((e = hipMemcpy(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) break;
+    if (!info) { set_error("mass matrix is not positive definite"); st = GDW_EINVAL; }
+  } while (0);
+  cleanup();
+  if (e != hipSuccess) {
+    set_error(std::string("eigenbasis set-up: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;
+  }
+  return st;
+}
+
+template <typename T>
+static gdw_status upload_as(void** dst, const std::vector<double>& src) {
+  std::vector<T> tmp(src.begin(), src.end());
+  GDW_HIP(hipMalloc(dst, tmp.size() * sizeof(T)));
+  GDW_HIP(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GDW_OK;
+}
+
+static gdw_status upload_tables(gdw_ctx* c, const std::vector<double>& gh,
+                                const std::vector<double>& invL, const std::vector<double>& lam) {
+  gdw_status s;
+  if (c->elem_bytes == 8) {
+    if ((s = upload_as<double>(&c->gh, gh)) != GDW_OK) return s;
+    if ((s = upload_as<double>(&c->invL, invL)) != GDW_OK) return s;
+    return upload_as<double>(&c->lam, lam);
+  }
+  if ((s = upload_as<float>(&c->gh, gh)) != GDW_OK) return s;
+  if ((s = upload_as<float>(&c->invL, invL)) != GDW_OK) return s;
+  return upload_as<float>(&c->lam, lam);
+}
+
+static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
+  c->d = *d;
+  const int N = d->N, p = d->p, n1 = N + 1, nn = n1 * n1;
+  c->n1 = n1;
+  c->nel = (long)d->nx * d->ny;
+  c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
+  c->alpha = 0.5;
+  c->beta = d->flux == GDW_FLUX_UPWIND ? 0.5 * d->xi : 0.0;
+  c->tau = d->flux == GDW_FLUX_UPWIND ? 0.5 / d->xi : 0.0;
+
+  std::vector<double> Psx, lx, Mx, dLx, dRx, Psy, ly, My, dLy, dRy;
+  gdw_status s;
+  if ((s = eigen_dir(N, p, d->Lx / d->nx, Psx, lx, Mx, dLx, dRx)) != GDW_OK) return s;
+  if ((s = eigen_dir(N, p, d->Ly / d->ny, Psy, ly, My, dLy, dRy)) != GDW_OK) return s;
+
+  // face tables: g = Psi^T dR (east/north), -Psi^T dL (west/south); h = rows N / 0 of Psi
+  std::vector<double> gh(8 * n1), invL(nn), lam(nn), Px(nn), Py(nn);
+  for (int k = 0; k < n1; ++k) {
+    double gE = 0, gW = 0, gN = 0, gS = 0;
+    for (int i = 0; i < n1; ++i) {
+      gE += dRx[i] * Psx[i * n1 + k];
+      gW -= dLx[i] * Psx[i * n1 + k];
+      gN += dRy[i] * Psy[i * n1 + k];
+      gS -= dLy[i] * Psy[i * n1 + k];
+    }
+    gh[0 * n1 + k] = gE; gh[1 * n1 + k] = Psx[N * n1 + k];
+    gh[2 * n1 + k] = gW; gh[3 * n1 + k] = Psx[0 * n1 + k];
+    gh[4 * n1 + k] = gN; gh[5 * n1 + k] = Psy[N * n1 + k];
+    gh[6 * n1 + k] = gS; gh[7 * n1 + k] = Psy[0 * n1 + k];
+  }
+  // Lambda_hat = c^2 (lambda_x + lambda_y), (0,0) entry kappa = c^2 (DG1_extra); the
+  // stage kernel uses c^2 / Lambda_hat.
+  for (int ky = 0; ky < n1; ++ky)
+    for (int kx = 0; kx < n1; ++kx) {
+      const double l = lx[kx] + ly[ky];
+      lam[ky * n1 + kx] = l;
+      invL[ky * n1 + kx] = (kx == 0 && ky == 0) ? 1.0 : 1.0 / l;
+    }
+  // Psi^{-1} = Psi^T M per direction
+  for (int k = 0; k < n1; ++k)
+    for (int i = 0; i < n1; ++i) {
+      double sx = 0, sy = 0;
+      for (int j = 0; j < n1; ++j) {
+        sx += Psx[j * n1 + k] * Mx[j * n1 + i];
+        sy += Psy[j * n1 + k] * My[j * n1 + i];
+      }
+      Px[k * n1 + i] = sx;
+      Py[k * n1 + i] = sy;
+    }
+  if ((s = upload_tables(c, gh, invL, lam)) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Psx, Psx)) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Psy, Psy)) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Px, Px)) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Py, Py)) != GDW_OK) return s;
+
+  const size_t field = (size_t)c->nel * nn * c->elem_bytes;
+  for (auto& r : c->Y)
+    for (auto& ptr : r) {
+      GDW_HIP(hipMalloc(&ptr, field));
+      GDW_HIP(hipMemset(ptr, 0, field));
+    }
+  const size_t trb = (size_t)c->nel * 8 * n1 * c->elem_bytes;
+  for (auto& t : c->tr) {
+    GDW_HIP(hipMalloc(&t, trb));
+    GDW_HIP(hipMemset(t, 0, trb));
+  }
+  GDW_HIP(hipMalloc(&c->epart, (c->npart + 1) * sizeof(double)));
+  GDW_HIP(hipMalloc(&c->nonfinite, sizeof(unsigned int)));
+  GDW_HIP(hipDeviceSynchronize());
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out) {
+  if (!out) { set_error("out is NULL"); return GDW_EINVAL; }
+  *out = nullptr;
+  gdw_status s = validate(desc);
+  if (s != GDW_OK) return s;
+  gdw_ctx* c = new (std::nothrow) gdw_ctx();
+  if (!c) { set_error("host allocation failed"); return GDW_ENOMEM; }
+  s = create_impl(desc, c);
+  if (s != GDW_OK) {
+    free_all(c);
+    delete c;
+    return s;
+  }
+  *out = c;
+  return GDW_OK;
+}
+
+template <typename T>
+static hipError_t set_state_t(gdw_ctx* c, const double* U, const double* V, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_to_modal<T>(U, (T*)c->Y[0][0], c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
+  if ((e = launch_to_modal<T>(V, (T*)c->Y[0][1], c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
+  c->trc = 0;
+  return launch_traces<T>((const T*)c->Y[0][0], (const T*)c->Y[0][1], (const T*)c->gh,
+                          (T*)c->tr[0], c->n1, c->nel, st);
+}
+
+extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V, void* stream) {
+  if (!c || !U || !V) { set_error("NULL argument"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  GDW_HIP(c->elem_bytes == 8 ? set_state_t<double>(c, U, V, st) : set_state_t<float>(c, U, V, st));
+  c->have_state = 1;
+  return GDW_OK;
+}
+
+template <typename T>
+static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+  StageArgs<T> a{};
+  a.nel = c->nel;
+  a.nx = c->d.nx;
+  a.ny = c->d.ny;
+  a.n1 = c->n1;
+  a.dt = (T)dt;
+  a.c2 = (T)c->d.c2;
+  a.alpha = (T)c->alpha;
+  a.beta = (T)c->beta;
+  a.tau = (T)c->tau;
+  a.invL = (const T*)c->invL;
+  a.lam = (const T*)c->lam;
+  a.gh = (const T*)c->gh;
+  T* y_u = (T*)c->Y[0][0];
+  T* y_v = (T*)c->Y[0][1];
+  T* Y_u = (T*)c->Y[1][0];
+  T* Y_v = (T*)c->Y[1][1];
+  T* A_u = (T*)c->Y[2][0];
+  T* A_v = (T*)c->Y[2][1];
+  T* t0 = (T*)c->tr[c->trc];
+  T* t1 = (T*)c->tr[c->trc ^ 1];
+  hipError_t e;
+  for (int s = 0; s < steps; ++s) {
+    // stage 1: Y <- y + dt/2 L(y)
+    a.in_u = y_u; a.in_v = y_v; a.aux_u = nullptr; a.aux_v = nullptr;
+    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = nullptr; a.acc_v = nullptr;
+    a.tr_in = t0; a.tr_out = t1;
+    if ((e = launch_stage<T>(1, a, st)) != hipSuccess) return e;
+    // stage 2: Y <- y + dt/2 L(Y), A <- Yin + 2 Ynew - y
+    a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
+    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = A_u; a.acc_v = A_v;
+    a.tr_in = t1; a.tr_out = t0;
+    if ((e = launch_stage<T>(2, a, st)) != hipSuccess) return e;
+    // stage 3: Y <- y + dt L(Y)
+    a.acc_u = nullptr; a.acc_v = nullptr;
+    a.tr_in = t0; a.tr_out = t1;
+    if ((e = launch_stage<T>(3, a, st)) != hipSuccess) return e;
+    // stage 4: y <- (A + Yin)/3 + dt/6 L(Y)
+    a.aux_u = A_u; a.aux_v = A_v;
+    a.out_u = y_u; a.out_v = y_v;
+    a.tr_in = t1; a.tr_out = t0;
+    if ((e = launch_stage<T>(4, a, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+extern "C" gdw_status gdw_run(gdw_ctx* c, double dt, int steps, void* stream) {
+  if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
+  if (!(dt > 0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return GDW_EINVAL; }
+  if (steps < 0) { set_error("steps must be >= 0"); return GDW_EINVAL; }
+  if (!c->have_state) { set_error("no state: call gdw_set_state first"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  GDW_HIP(c->elem_bytes == 8 ? run_t<double>(c, dt, steps, st) : run_t<float>(c, dt, steps, st));
+  c->steps_taken += steps;
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_get_state(gdw_ctx* c, double* U, double* V, void* stream) {
+  if (!c || !U || !V) { set_error("NULL argument"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  if (c->elem_bytes == 8) {
+    GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
+    GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
+  } else {
+    GDW_HIP(launch_to_nodal<float>((const float*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
+    GDW_HIP(launch_to_nodal<float>((const float*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
+  }
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_energy(gdw_ctx* c, double* E_host, void* stream) {
+  if (!c || !E_host) { set_error("NULL argument"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  double* out = c->epart + c->npart;
+  if (c->elem_bytes == 8)
+    GDW_HIP(launch_energy<double>((const double*)c->Y[0][0], (const double*)c->Y[0][1],
+                                  (const double*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
+                                  c->npart, out, st));
+  else
+    GDW_HIP(launch_energy<float>((const float*)c->Y[0][0], (const float*)c->Y[0][1],
+                                 (const float*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
+                                 c->npart, out, st));
+  GDW_HIP(hipMemcpyAsync(E_host, out, sizeof(double), hipMemcpyDeviceToHost, st));
+  GDW_HIP(hipStreamSynchronize(st));
+  if (!std::isfinite(*E_host)) { set_error("energy is not finite"); return GDW_ENONFINITE; }
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
+  if (!c || !out) { set_error("NULL argument"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  std::memset(out, 0, sizeof(*out));
+  out->steps_taken = c->steps_taken;
+  out->dof_updates = c->steps_taken * c->nel * (long long)c->n1 * c->n1;
+  out->n1 = c->n1;
+  out->precision = c->d.precision;
+  out->solver = GDW_SOLVE_FDM;
+  out->fail_elem = -1;
+  const long n = c->nel * (long)c->n1 * c->n1;
+  GDW_HIP(hipMemsetAsync(c->nonfinite, 0, sizeof(unsigned int), st));
+  for (int f = 0; f < 2; ++f) {
+    if (c->elem_bytes == 8)
+      GDW_HIP(launch_count_nonfinite<double>((const double*)c->Y[0][f], n, c->nonfinite, st));
+    else
+      GDW_HIP(launch_count_nonfinite<float>((const float*)c->Y[0][f], n, c->nonfinite, st));
+  }
+  unsigned int cnt = 0;
+  GDW_HIP(hipMemcpyAsync(&cnt, c->nonfinite, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  GDW_HIP(hipStreamSynchronize(st));
+  if (cnt) { set_error("state holds NaN or Inf"); return GDW_ENONFINITE; }
+  return GDW_OK;
+}
+
+extern "C" void gdw_destroy(gdw_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+}

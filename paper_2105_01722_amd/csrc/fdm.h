@@ -1,0 +1,48 @@
+// Kernel launchers of the constant-coefficient (simultaneous diagonalisation) path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gdw {
+
+// Arguments of one fused RK stage (see fdm.hip for the stage-by-stage roles).
+template <typename T>
+struct StageArgs {
+  const T* in_u;       // stage input, modal
+  const T* in_v;
+  const T* aux_u;      // y (stages 2, 3) or the accumulator (stage 4); unused in stage 1
+  const T* aux_v;
+  T* out_u;            // new stage value (may alias in_u for stages 2, 3)
+  T* out_v;
+  T* acc_u;            // stage 2 only: accumulator Yin + 2 Ynew - y
+  T* acc_v;
+  const T* tr_in;      // modal traces of the stage input, [nel][8][n1]
+  T* tr_out;           // modal traces of the new stage value
+  const T* invL;       // [n1*n1]: 1 / (lambda_x + lambda_y), entry (0,0) = 1
+  const T* lam;        // [n1*n1]: lambda_x + lambda_y
+  const T* gh;         // [8][n1]: gE hE gW hW gN hN gS hS
+  long nel;
+  int nx, ny, n1;
+  T dt, c2, alpha, beta, tau;
+};
+
+hipError_t launch_eig(const double* M, const double* S, int n, double* work, double* Psi,
+                      double* lam, int* info, hipStream_t st);
+template <typename T>
+hipError_t launch_to_modal(const double* U, T* Ub, const double* Px, const double* Py, int n1,
+                           long nel, hipStream_t st);
+template <typename T>
+hipError_t launch_to_nodal(const T* Ub, double* U, const double* Psx, const double* Psy, int n1,
+                           long nel, hipStream_t st);
+template <typename T>
+hipError_t launch_traces(const T* Ub, const T* Vb, const T* gh, T* tr, int n1, long nel,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_stage(int stage, const StageArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int n1, long nel,
+                         double* part, int npart, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStream_t st);
+
+}  // namespace gdw

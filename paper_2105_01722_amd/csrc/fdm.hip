@@ -1,0 +1,527 @@
+// Constant-coefficient Cartesian path: the energy-DG right-hand side of
+// DG1 + DG1_extra, DG2 (Sec. 2.2) fused with the local solves by simultaneous
+// diagonalisation (Sec. 3.2) and the classical RK4 stage update, one kernel per
+// RK stage.
+//
+// State representation (Sec. 3.2): U = Psi Ubar, V = Psi Vbar with
+// Psi = Psi_x (x) Psi_y, S_j psi = lambda M_j psi, psi^T M_j psi = 1.  In that basis
+//   dUbar/dt = Vbar + Lambda_hat^{-1} Psi^T F_u      (DG1_sparse; mode (0,0) from DG1_extra)
+//   dVbar/dt = -c^2 Lambda Ubar + Psi^T F_v          (DG2_sparse)
+// with Lambda = lambda_x (+) lambda_y.  The face terms are rank one per face
+// (Sec. 3.2, B/C/D/E-tilde): on the east face F_u = c^2 dR_x (x) M_y sigma_u, so
+// Psi^T F_u = c^2 (Psi_x^T dR_x) (x) (Psi_y^T M_y sigma_u); and because every trace along
+// the face is a GD function in the face coordinate, Psi_y^T M_y sigma_u is the same
+// combination of the modal face coefficients of the traces (Psi_y^T M_y Psi_y = I).
+// So a stage needs, per element, only 8 modal trace vectors of length N+1 of
+// itself and of its neighbours, which the previous stage wrote.
+//
+// Arithmetic per DOF and stage: 8 MACs of lifts + the diagonal solve, plus 8 (N+1)
+// MACs per element row for the traces of the new state: the kernel is bound by
+// HBM bandwidth.
+//
+// Layout in HBM: modal arrays are element-major, [e][ky][kx] (kx fastest), one
+// array per field.  Traces: [e][8][N+1], slot f2 = 0 aE, 1 vE, 2 aW, 3 vW, 4 aN,
+// 5 vN, 6 aS, 7 vS, where a = outward normal derivative and v = value on the face.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "fdm.h"
+
+namespace gdw {
+
+// ---------------------------------------------------------------------------------
+// FP64 generalised symmetric eigensolver S psi = lambda M psi for one (N+1)^2 pencil:
+// Cholesky M = L L^T, C = L^{-1} S L^{-T}, cyclic Jacobi on C, Psi = L^{-T} Q.
+// Runs on a single lane; setup only.  work: 3 n^2 + n doubles; info: 1 + n ints.
+// ---------------------------------------------------------------------------------
+__global__ void k_eig_pencil(const double* __restrict__ M, const double* __restrict__ S, int n,
+                             double* __restrict__ work, double* __restrict__ Psi,
+                             double* __restrict__ lam, int* __restrict__ info) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double* L = work;
+  double* C = work + n * n;
+  double* Q = work + 2 * n * n;
+  int ok = 1;
+  // Cholesky (lower)
+  for (int j = 0; j < n; ++j) {
+    double d = M[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) { ok = 0; d = 1.0; }
+    const double ljj = sqrt(d);
+    L[j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double s = M[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = s / ljj;
+    }
+    for (int i = 0; i < j; ++i) L[i * n + j] = 0.0;
+  }
+  // Q <- L^{-1} S   (column by column forward substitution)
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double s = S[i * n + c];
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * Q[k * n + c];
+      Q[i * n + c] = s / L[i * n + i];
+    }
+  // C <- L^{-1} Q^T  (= L^{-1} S L^{-T} as S is symmetric)
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double s = Q[c * n + i];
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * C[k * n + c];
+      C[i * n + c] = s / L[i * n + i];
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double a = 0.5 * (C[i * n + j] + C[j * n + i]);
+      C[i * n + j] = C[j * n + i] = a;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Q[i * n + j] = (i == j) ? 1.0 : 0.0;
+  // cyclic Jacobi
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += C[i * n + i] * C[i * n + i];
+      for (int j = i + 1; j < n; ++j) off += C[i * n + j] * C[i * n + j];
+    }
+    if (off <= 1e-34 * diag) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = C[p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double ckp = C[k * n + p], ckq = C[k * n + q];
+          C[k * n + p] = c * ckp - s * ckq;
+          C[k * n + q] = s * ckp + c * ckq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double cpk = C[p * n + k], cqk = C[q * n + k];
+          C[p * n + k] = c * cpk - s * cqk;
+          C[q * n + k] = s * cpk + c * cqk;
+        }
+        C[p * n + q] = C[q * n + p] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double qkp = Q[k * n + p], qkq = Q[k * n + q];
+          Q[k * n + p] = c * qkp - s * qkq;
+          Q[k * n + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+  // eigenvalues = diagonal of the converged C
+  double* D = work + 3 * n * n;
+  for (int i = 0; i < n; ++i) D[i] = C[i * n + i];
+  // Psi <- L^{-T} Q (back substitution), unsorted, into C's storage
+  for (int c = 0; c < n; ++c)
+    for (int i = n - 1; i >= 0; --i) {
+      double s = Q[i * n + c];
+      for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * C[k * n + c];
+      C[i * n + c] = s / L[i * n + i];
+    }
+  // sort ascending (selection); Psi[i*n + k] = psi_k(i); sign: largest entry positive
+  int* used = info + 1;
+  for (int k = 0; k < n; ++k) used[k] = 0;
+  for (int k = 0; k < n; ++k) {
+    int best = -1;
+    for (int j = 0; j < n; ++j)
+      if (!used[j] && (best < 0 || D[j] < D[best])) best = j;
+    used[best] = 1;
+    int imax = 0;
+    double vmax = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (fabs(C[i * n + best]) > vmax * (1.0 + 1e-12)) { vmax = fabs(C[i * n + best]); imax = i; }
+    const double sg = C[imax * n + best] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) Psi[i * n + k] = sg * C[i * n + best];
+    lam[k] = (k == 0) ? 0.0 : D[best];   // the constant mode has lambda = 0 exactly
+  }
+  info[0] = ok;
+}
+
+// ---------------------------------------------------------------------------------
+// nodal (FP64) -> modal (T):  Ubar[ky][kx] = sum Py[ky][iy] Px[kx][ix] U[iy][ix],
+// P = Psi^T M = Psi^{-1}.  One workgroup per element.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_to_modal(const double* __restrict__ U, T* __restrict__ Ub,
+                           const double* __restrict__ Px, const double* __restrict__ Py,
+                           int n1, long nel) {
+  extern __shared__ double sh[];
+  const int nn = n1 * n1;
+  double* u = sh;
+  double* tmp = sh + nn;
+  const long e = blockIdx.x;
+  if (e >= nel) return;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) u[i] = U[e * nn + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const int iy = i / n1, kx = i - iy * n1;
+    double s = 0.0;
+    for (int ix = 0; ix < n1; ++ix) s += Px[kx * n1 + ix] * u[iy * n1 + ix];
+    tmp[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const int ky = i / n1, kx = i - ky * n1;
+    double s = 0.0;
+    for (int iy = 0; iy < n1; ++iy) s += Py[ky * n1 + iy] * tmp[iy * n1 + kx];
+    Ub[e * nn + i] = (T)s;
+  }
+}
+
+// modal (T) -> nodal (FP64):  U[iy][ix] = sum Psi_y[iy][ky] Psi_x[ix][kx] Ubar[ky][kx]
+template <typename T>
+__global__ void k_to_nodal(const T* __restrict__ Ub, double* __restrict__ U,
+                           const double* __restrict__ Psx, const double* __restrict__ Psy,
+                           int n1, long nel) {
+  extern __shared__ double sh[];
+  const int nn = n1 * n1;
+  double* u = sh;
+  double* tmp = sh + nn;
+  const long e = blockIdx.x;
+  if (e >= nel) return;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) u[i] = (double)Ub[e * nn + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const int ky = i / n1, ix = i - ky * n1;
+    double s = 0.0;
+    for (int kx = 0; kx < n1; ++kx) s += Psx[ix * n1 + kx] * u[ky * n1 + kx];
+    tmp[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const int iy = i / n1, ix = i - iy * n1;
+    double s = 0.0;
+    for (int ky = 0; ky < n1; ++ky) s += Psy[iy * n1 + ky] * tmp[ky * n1 + ix];
+    U[e * nn + i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Modal face traces of a state (used once after set_state; every stage kernel
+// writes the traces of its output itself).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_traces(const T* __restrict__ Ub, const T* __restrict__ Vb,
+                         const T* __restrict__ gh, T* __restrict__ tr, int n1, long nel) {
+  const int nn = n1 * n1;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nel * 8 * n1) return;
+  const long e = i / (8 * n1);
+  const int r = (int)(i - e * 8 * n1);
+  const int f2 = r / n1, j = r - f2 * n1;
+  const T* F = ((f2 & 1) ? Vb : Ub) + e * nn;
+  const T* g = gh + f2 * n1;
+  T acc = 0;
+  if (f2 < 4)
+    for (int k = 0; k < n1; ++k) acc += g[k] * F[j * n1 + k];
+  else
+    for (int k = 0; k < n1; ++k) acc += g[k] * F[k * n1 + j];
+  tr[i] = acc;
+}
+
+// sum_k g[k] F[j][k] (contraction along kx) and sum_k g[k] F[k][j] (along ky)
+template <typename T, int N1C>
+__device__ inline T dot_row(const T* g, const T* F, int j, int n1) {
+  T acc = 0;
+  if constexpr (N1C > 0) {
+#pragma unroll
+    for (int k = 0; k < N1C; ++k) acc += g[k] * F[j * N1C + k];
+  } else {
+    for (int k = 0; k < n1; ++k) acc += g[k] * F[j * n1 + k];
+  }
+  return acc;
+}
+
+template <typename T, int N1C>
+__device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
+  T acc = 0;
+  if constexpr (N1C > 0) {
+#pragma unroll
+    for (int k = 0; k < N1C; ++k) acc += g[k] * F[k * N1C + j];
+  } else {
+    for (int k = 0; k < n1; ++k) acc += g[k] * F[k * n1 + j];
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------------
+// The fused RK stage.
+//   STAGE 1: in = y;      out = Y  <- y + dt/2 k1
+//   STAGE 2: in = Y, y;   out = Y  <- y + dt/2 k2 (in place),  Tacc <- Yin + 2 Ynew - y
+//   STAGE 3: in = Y, y;   out = Y  <- y + dt k3 (in place)
+//   STAGE 4: in = Y, Tacc; out = y <- (Tacc + Yin)/3 + dt/6 k4
+// Classical RK4 (y_{n+1} = y + dt/6 (k1 + 2k2 + 2k3 + k4)) with Y2 = y + dt/2 k1,
+// Y3 = y + dt/2 k2, Y4 = y + dt k3, because
+// (Y2 + 2 Y3 + Y4 - y)/3 = y + dt/6 k1 + dt/3 k2 + dt/3 k3.  12 field accesses per
+// DOF per step instead of the 16 of the textbook three-register form.
+// ---------------------------------------------------------------------------------
+template <typename T, int STAGE, int N1C, int EPB>
+__global__ __launch_bounds__(256) void k_stage(StageArgs<T> a) {
+  const int n1 = N1C > 0 ? N1C : a.n1;
+  const int nn = n1 * n1;
+  extern __shared__ unsigned char smem_raw[];
+  T* sgh = reinterpret_cast<T*>(smem_raw);       // [8][n1] face tables
+  T* sig = sgh + 8 * n1;                         // [EPB][8][n1] modal face fluxes
+  T* snew = sig + EPB * 8 * n1;                  // [EPB][2][nn] new stage values
+  const long e0 = (long)blockIdx.x * EPB;
+  const int ne = (int)min((long)EPB, a.nel - e0);
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < 8 * n1; i += blockDim.x) sgh[i] = a.gh[i];
+
+  // Phase A: modal face fluxes sigma_u = (1-alpha)(v_nb - v) - beta (a + a_nb),
+  // sigma_v = (1-alpha) a - alpha a_nb + tau (v_nb - v)  (Sec. 2.2.1)
+  const T alpha = a.alpha, beta = a.beta, tau = a.tau;
+  for (int i = tid; i < ne * 4 * n1; i += blockDim.x) {
+    const int el = i / (4 * n1);
+    const int r = i - el * 4 * n1;
+    const int f = r / n1, j = r - f * n1;
+    const long e = e0 + el;
+    const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
+    long enb;
+    int fnb;
+    if (f == 0) { enb = (long)ey * a.nx + (ex + 1 == a.nx ? 0 : ex + 1); fnb = 1; }
+    else if (f == 1) { enb = (long)ey * a.nx + (ex == 0 ? a.nx - 1 : ex - 1); fnb = 0; }
+    else if (f == 2) { enb = (long)(ey + 1 == a.ny ? 0 : ey + 1) * a.nx + ex; fnb = 3; }
+    else { enb = (long)(ey == 0 ? a.ny - 1 : ey - 1) * a.nx + ex; fnb = 2; }
+    const T* ts = a.tr_in + e * 8 * n1 + 2 * f * n1;
+    const T* tn = a.tr_in + enb * 8 * n1 + 2 * fnb * n1;
+    const T as = ts[j], vs = ts[n1 + j], an = tn[j], vn = tn[n1 + j];
+    const T jv = vn - vs;
+    sig[(el * 8 + 2 * f) * n1 + j] = (T(1) - alpha) * jv - beta * (as + an);
+    sig[(el * 8 + 2 * f + 1) * n1 + j] = (T(1) - alpha) * as - alpha * an + tau * jv;
+  }
+  __syncthreads();
+
+  // Phase B: modal right-hand side and the RK stage update
+  const T dt = a.dt, c2 = a.c2;
+  const long g0 = e0 * nn;
+  for (int i = tid; i < ne * nn; i += blockDim.x) {
+    const int el = i / nn;
+    const int idx = i - el * nn;
+    const int ky = idx / n1, kx = idx - ky * n1;
+    const long g = g0 + i;
+    const T ub = a.in_u[g], vb = a.in_v[g];
+    const T* s = sig + el * 8 * n1;
+    const T Lu = sgh[0 * n1 + kx] * s[0 * n1 + ky] + sgh[2 * n1 + kx] * s[2 * n1 + ky] +
+                 sgh[4 * n1 + ky] * s[4 * n1 + kx] + sgh[6 * n1 + ky] * s[6 * n1 + kx];
+    const T Lv = sgh[1 * n1 + kx] * s[1 * n1 + ky] + sgh[3 * n1 + kx] * s[3 * n1 + ky] +
+                 sgh[5 * n1 + ky] * s[5 * n1 + kx] + sgh[7 * n1 + ky] * s[7 * n1 + kx];
+    const T ku = vb + a.invL[idx] * Lu;
+    const T kv = c2 * (Lv - a.lam[idx] * ub);
+    T nu, nv;
+    if (STAGE == 1) {
+      nu = ub + T(0.5) * dt * ku;
+      nv = vb + T(0.5) * dt * kv;
+      a.out_u[g] = nu;
+      a.out_v[g] = nv;
+    } else if (STAGE == 2) {
+      const T yu = a.aux_u[g], yv = a.aux_v[g];
+      nu = yu + T(0.5) * dt * ku;
+      nv = yv + T(0.5) * dt * kv;
+      a.out_u[g] = nu;
+      a.out_v[g] = nv;
+      a.acc_u[g] = ub + T(2) * nu - yu;
+      a.acc_v[g] = vb + T(2) * nv - yv;
+    } else if (STAGE == 3) {
+      const T yu = a.aux_u[g], yv = a.aux_v[g];
+      nu = yu + dt * ku;
+      nv = yv + dt * kv;
+      a.out_u[g] = nu;
+      a.out_v[g] = nv;
+    } else {
+      const T tu = a.aux_u[g], tv = a.aux_v[g];
+      nu = (tu + ub) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * ku;
+      nv = (tv + vb) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * kv;
+      a.out_u[g] = nu;
+      a.out_v[g] = nv;
+    }
+    snew[(el * 2) * nn + idx] = nu;
+    snew[(el * 2 + 1) * nn + idx] = nv;
+  }
+  __syncthreads();
+
+  // Phase C: modal face traces of the new state for the next stage
+  for (int i = tid; i < ne * 8 * n1; i += blockDim.x) {
+    const int el = i / (8 * n1);
+    const int r = i - el * 8 * n1;
+    const int f2 = r / n1, j = r - f2 * n1;
+    const T* F = snew + (el * 2 + (f2 & 1)) * nn;
+    const T* gg = sgh + f2 * n1;
+    const T acc = (f2 < 4) ? dot_row<T, N1C>(gg, F, j, n1) : dot_col<T, N1C>(gg, F, j, n1);
+    a.tr_out[e0 * 8 * n1 + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Energy 1/2 sum (Vbar^2 + c^2 Lambda Ubar^2) (Psi^T M Psi = I, Psi^T S Psi = Lambda),
+// FP64, two passes with a fixed reduction tree (deterministic).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_partial(const T* __restrict__ Ub,
+                                                        const T* __restrict__ Vb,
+                                                        const T* __restrict__ lam, double c2,
+                                                        int nn, long total,
+                                                        double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int idx = (int)(i % nn);
+    const double u = (double)Ub[i], v = (double)Vb[i];
+    s += v * v + c2 * (double)lam[idx] * u * u;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_fixed(const double* __restrict__ part, int n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 0.5 * red[0];
+}
+
+// count of non-finite entries (end-of-run check)
+template <typename T>
+__global__ void k_count_nonfinite(const T* __restrict__ a, long n, unsigned int* __restrict__ cnt) {
+  unsigned int c = 0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    if (!isfinite((double)a[i])) ++c;
+  if (c) atomicAdd(cnt, c);
+}
+
+// ---------------------------------------------------------------------------------
+// host launch wrappers
+// ---------------------------------------------------------------------------------
+hipError_t launch_eig(const double* M, const double* S, int n, double* work, double* Psi,
+                      double* lam, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_eig_pencil, dim3(1), dim3(1), 0, st, M, S, n, work, Psi, lam, info);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_to_modal(const double* U, T* Ub, const double* Px, const double* Py, int n1,
+                           long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  size_t sh = 2 * n1 * n1 * sizeof(double);
+  hipLaunchKernelGGL(k_to_modal<T>, dim3((unsigned)nel), dim3(256), sh, st, U, Ub, Px, Py, n1, nel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_to_nodal(const T* Ub, double* U, const double* Psx, const double* Psy, int n1,
+                           long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  size_t sh = 2 * n1 * n1 * sizeof(double);
+  hipLaunchKernelGGL(k_to_nodal<T>, dim3((unsigned)nel), dim3(256), sh, st, Ub, U, Psx, Psy, n1, nel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_traces(const T* Ub, const T* Vb, const T* gh, T* tr, int n1, long nel,
+                         hipStream_t st) {
+  const long total = nel * 8 * n1;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_traces<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Ub, Vb,
+                     gh, tr, n1, nel);
+  return hipGetLastError();
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
+  const int n1 = a.n1;
+  const size_t sh = (size_t)(8 * n1 + EPB * 8 * n1 + EPB * 2 * n1 * n1) * sizeof(T);
+  const unsigned nblk = (unsigned)((a.nel + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB>), dim3(nblk), dim3(256), sh, st, a);
+  return hipGetLastError();
+}
+
+// Elements per workgroup: as many as fit 64 KiB of LDS (4 in FP64, 8 in FP32 for the
+// common sizes).
+template <typename T, int STAGE, int N1C>
+static hipError_t dispatch_epb(const StageArgs<T>& a, hipStream_t st) {
+  auto bytes = [&](int epb) {
+    return (size_t)(8 * a.n1 + epb * 8 * a.n1 + epb * 2 * a.n1 * a.n1) * sizeof(T);
+  };
+  constexpr int E0 = sizeof(T) == 8 ? 4 : 8;
+  if (bytes(E0) <= 65536) return launch_stage_t<T, STAGE, N1C, E0>(a, st);
+  if (bytes(2) <= 65536) return launch_stage_t<T, STAGE, N1C, 2>(a, st);
+  if (bytes(1) <= 65536) return launch_stage_t<T, STAGE, N1C, 1>(a, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int STAGE>
+static hipError_t dispatch_n1(const StageArgs<T>& a, hipStream_t st) {
+  switch (a.n1) {
+    case 9: return dispatch_epb<T, STAGE, 9>(a, st);
+    case 13: return dispatch_epb<T, STAGE, 13>(a, st);
+    case 17: return dispatch_epb<T, STAGE, 17>(a, st);
+    default: return dispatch_epb<T, STAGE, 0>(a, st);
+  }
+}
+
+template <typename T>
+hipError_t launch_stage(int stage, const StageArgs<T>& a, hipStream_t st) {
+  if (a.nel == 0) return hipSuccess;
+  switch (stage) {
+    case 1: return dispatch_n1<T, 1>(a, st);
+    case 2: return dispatch_n1<T, 2>(a, st);
+    case 3: return dispatch_n1<T, 3>(a, st);
+    default: return dispatch_n1<T, 4>(a, st);
+  }
+}
+
+template <typename T>
+hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int n1, long nel,
+                         double* part, int npart, double* out, hipStream_t st) {
+  const long total = nel * (long)n1 * n1;
+  hipLaunchKernelGGL(k_energy_partial<T>, dim3(npart), dim3(256), 0, st, Ub, Vb, lam, c2, n1 * n1,
+                     total, part);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, part, npart, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  long nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_count_nonfinite<T>, dim3((unsigned)nb), dim3(256), 0, st, a, n, cnt);
+  return hipGetLastError();
+}
+
+#define GDW_INST(T)                                                                              \
+  template hipError_t launch_to_modal<T>(const double*, T*, const double*, const double*, int,    \
+                                         long, hipStream_t);                                     \
+  template hipError_t launch_to_nodal<T>(const T*, double*, const double*, const double*, int,    \
+                                         long, hipStream_t);                                     \
+  template hipError_t launch_traces<T>(const T*, const T*, const T*, T*, int, long, hipStream_t); \
+  template hipError_t launch_stage<T>(int, const StageArgs<T>&, hipStream_t);                    \
+  template hipError_t launch_energy<T>(const T*, const T*, const T*, double, int, long, double*,  \
+                                       int, double*, hipStream_t);                               \
+  template hipError_t launch_count_nonfinite<T>(const T*, long, unsigned int*, hipStream_t);
+
+GDW_INST(double)
+GDW_INST(float)
+
+}  // namespace gdw

@@ -1,0 +1,192 @@
+"""ctypes binding of libgdw (the C ABI in include/gdw.h).
+
+Argument marshalling only: every step of the time loop runs in the HIP kernels of
+libgdw.so.  Torch is used for device memory and for the current HIP stream.  If
+the library has not been built this module raises at import time -- there is no
+CPU fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdw.so")
+
+GDW_OK, GDW_EINVAL, GDW_ENOMEM, GDW_EHIP, GDW_ENOCONV, GDW_ENONFINITE, GDW_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+GDW_FLUX_CENTRAL, GDW_FLUX_UPWIND = 0, 1
+GDW_FP64, GDW_MIXED_FP32 = 0, 1
+GDW_SOLVE_AUTO, GDW_SOLVE_FDM, GDW_SOLVE_PCG = 0, 1, 2
+
+_STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV",
+                 -5: "ENONFINITE", -6: "EUNSUPPORTED"}
+
+
+class gdw_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("N", ctypes.c_int),
+                ("p", ctypes.c_int), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("c2", ctypes.c_double),
+                ("flux", ctypes.c_int), ("xi", ctypes.c_double), ("precision", ctypes.c_int),
+                ("solver", ctypes.c_int)]
+
+
+class gdw_stats(ctypes.Structure):
+    _fields_ = [("steps_taken", ctypes.c_longlong), ("dof_updates", ctypes.c_longlong),
+                ("n1", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
+                ("fail_elem", ctypes.c_int)]
+
+
+class GdwError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__("%s: %s (%s)" % (where, _STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgdw.so is not built (run `python -m paper_2105_01722_amd.build`); "
+                          "there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, None
+    sig = {
+        "gdw_version": (ctypes.c_char_p, []),
+        "gdw_last_error": (ctypes.c_char_p, []),
+        "gdw_create": (I, [ctypes.POINTER(gdw_desc), ctypes.POINTER(P)]),
+        "gdw_set_state": (I, [P, P, P, P]),
+        "gdw_run": (I, [P, D, I, P]),
+        "gdw_get_state": (I, [P, P, P, P]),
+        "gdw_energy": (I, [P, ctypes.POINTER(D), P]),
+        "gdw_get_stats": (I, [P, ctypes.POINTER(gdw_stats), P]),
+        "gdw_destroy": (V, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status, where):
+    if status != GDW_OK:
+        raise GdwError(status, where, lib.gdw_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous float64 tensor with %d entries" % (name, n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --- thin wrappers with the C names ---------------------------------------------------
+def gdw_version():
+    return lib.gdw_version().decode()
+
+
+def gdw_create(desc):
+    ctx = ctypes.c_void_p()
+    _check(lib.gdw_create(ctypes.byref(desc), ctypes.byref(ctx)), "gdw_create")
+    return ctx
+
+
+def gdw_set_state(ctx, U_ptr, V_ptr, stream=None):
+    _check(lib.gdw_set_state(ctx, U_ptr, V_ptr, _stream(stream)), "gdw_set_state")
+
+
+def gdw_run(ctx, dt, steps, stream=None):
+    _check(lib.gdw_run(ctx, float(dt), int(steps), _stream(stream)), "gdw_run")
+
+
+def gdw_get_state(ctx, U_ptr, V_ptr, stream=None):
+    _check(lib.gdw_get_state(ctx, U_ptr, V_ptr, _stream(stream)), "gdw_get_state")
+
+
+def gdw_energy(ctx, stream=None):
+    e = ctypes.c_double()
+    _check(lib.gdw_energy(ctx, ctypes.byref(e), _stream(stream)), "gdw_energy")
+    return e.value
+
+
+def gdw_get_stats(ctx, stream=None):
+    s = gdw_stats()
+    _check(lib.gdw_get_stats(ctx, ctypes.byref(s), _stream(stream)), "gdw_get_stats")
+    return {f: getattr(s, f) for f, _ in gdw_stats._fields_}
+
+
+def gdw_destroy(ctx):
+    lib.gdw_destroy(ctx)
+
+
+# --- convenience wrapper -----------------------------------------------------------------
+class Solver:
+    """One problem: nx x ny periodic elements, N cells, odd degree p (see include/gdw.h)."""
+
+    def __init__(self, nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64",
+                 solver="auto", Lx=1.0, Ly=1.0, x0=0.0, y0=0.0):
+        d = gdw_desc()
+        d.nx, d.ny, d.N, d.p = nx, ny, N, p
+        d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
+        d.c2 = c2
+        d.flux = {"central": GDW_FLUX_CENTRAL, "upwind": GDW_FLUX_UPWIND}[flux]
+        d.xi = xi
+        d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32}[precision]
+        d.solver = {"auto": GDW_SOLVE_AUTO, "fdm": GDW_SOLVE_FDM, "pcg": GDW_SOLVE_PCG}[solver]
+        self.desc = d
+        self.shape = (ny, nx, N + 1, N + 1)
+        self.n = nx * ny * (N + 1) ** 2
+        self.ctx = gdw_create(d)
+
+    def set_state(self, U, V, stream=None):
+        import torch
+        U = torch.as_tensor(U, dtype=torch.float64, device="cuda").contiguous()
+        V = torch.as_tensor(V, dtype=torch.float64, device="cuda").contiguous()
+        gdw_set_state(self.ctx, _dptr(U, self.n, "U"), _dptr(V, self.n, "V"), stream)
+        self._keep = (U, V)  # alive until the queued copy has run
+
+    def run(self, dt, steps, stream=None):
+        gdw_run(self.ctx, dt, steps, stream)
+
+    def get_state(self, stream=None):
+        import torch
+        U = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        V = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        gdw_get_state(self.ctx, _dptr(U, self.n, "U"), _dptr(V, self.n, "V"), stream)
+        return U, V
+
+    def energy(self, stream=None):
+        return gdw_energy(self.ctx, stream)
+
+    def stats(self, stream=None):
+        return gdw_get_stats(self.ctx, stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            gdw_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def header_symbols(header_path=None):
+    """Names of the functions declared in include/gdw.h (for the export test)."""
+    import re
+    header_path = header_path or os.path.join(os.path.dirname(_HERE), "include", "gdw.h")
+    src = open(header_path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gdw_[a-z_0-9]+)\s*\(", src)))
+

@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and rejects invalid descriptors before touching the device."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2105_01722_amd import gdw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_header_symbol_is_exported():
+    names = gdw.header_symbols()
+    assert "gdw_create" in names and "gdw_run" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", gdw.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(gdw.lib, n)
+
+
+def test_version_and_no_error():
+    assert "gfx950" in gdw.gdw_version()
+    assert isinstance(gdw.lib.gdw_last_error(), bytes)
+
+
+def _desc(**kw):
+    d = gdw.gdw_desc()
+    d.nx, d.ny, d.N, d.p = 4, 4, 8, 3
+    d.x0 = d.y0 = 0.0
+    d.Lx = d.Ly = 1.0
+    d.c2 = 1.0
+    d.flux = gdw.GDW_FLUX_CENTRAL
+    d.xi = 1.0
+    d.precision = gdw.GDW_FP64
+    d.solver = gdw.GDW_SOLVE_AUTO
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(p=4), gdw.GDW_EINVAL),
+    (dict(p=0), gdw.GDW_EINVAL),
+    (dict(N=2, p=3), gdw.GDW_EINVAL),
+    (dict(nx=0), gdw.GDW_EINVAL),
+    (dict(Lx=-1.0), gdw.GDW_EINVAL),
+    (dict(c2=0.0), gdw.GDW_EINVAL),
+    (dict(c2=float("nan")), gdw.GDW_EINVAL),
+    (dict(flux=7), gdw.GDW_EINVAL),
+    (dict(flux=gdw.GDW_FLUX_UPWIND, xi=0.0), gdw.GDW_EINVAL),
+    (dict(precision=9), gdw.GDW_EINVAL),
+    (dict(N=48), gdw.GDW_EINVAL),
+])
+def test_invalid_descriptors_rejected_on_host(kw, status):
+    """Validation happens before any device call, so it runs without a GPU."""
+    ctx = ctypes.c_void_p()
+    st = gdw.lib.gdw_create(ctypes.byref(_desc(**kw)), ctypes.byref(ctx))
+    assert st == status
+    assert ctx.value is None
+    assert gdw.lib.gdw_last_error()
+
+
+def test_null_arguments_rejected():
+    assert gdw.lib.gdw_create(None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_run(None, 0.1, 1, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_set_state(None, None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_get_state(None, None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_energy(None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_get_stats(None, None, None) == gdw.GDW_EINVAL
+    gdw.lib.gdw_destroy(None)
+
+
+def test_product_path_does_not_import_oracle():
+    """The package never imports the oracle (the oracle is test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_2105_01722_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
