@@ -82,7 +82,7 @@ const char* gdw_last_error(void);
 /* Validate `desc` and build the element tables: 1D GD mass / stiffness / face
  * vectors (Sec. 3.1, Sec. 3.2) on the host, the generalised eigenbasis
  * S_j psi = lambda M_j psi with psi^T M_j psi = 1 (Sec. 3.2) in FP64 on the device.
- * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 48, nx or ny < 1, a
+ * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
  * non-positive length, c2 or xi, an unknown enum; EUNSUPPORTED for solver PCG;
  * ENOMEM / EHIP from the device.  Uses the current HIP device; synchronous. */
 gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out);

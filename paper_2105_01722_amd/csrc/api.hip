@@ -70,7 +70,7 @@ static gdw_status validate(const gdw_desc* d) {
   if (d->p < 1 || d->p % 2 == 0) { set_error("p must be odd and >= 1"); return GDW_EINVAL; }
   if (d->p > 31) { set_error("p > 31 is not supported"); return GDW_EINVAL; }
   if (d->N < d->p) { set_error("N must be >= p"); return GDW_EINVAL; }
-  if (d->N + 1 > 48) { set_error("N + 1 must be <= 48"); return GDW_EINVAL; }
+  if (d->N + 1 > 32) { set_error("N + 1 must be <= 32"); return GDW_EINVAL; }
   if (d->nx < 1 || d->ny < 1) { set_error("nx, ny must be >= 1"); return GDW_EINVAL; }
   if (!(d->Lx > 0) || !(d->Ly > 0) || !std::isfinite(d->Lx) || !std::isfinite(d->Ly)) {
     set_error("Lx, Ly must be finite and > 0"); return GDW_EINVAL;

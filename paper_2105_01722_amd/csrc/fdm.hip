@@ -261,18 +261,48 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 // (Y2 + 2 Y3 + Y4 - y)/3 = y + dt/6 k1 + dt/3 k2 + dt/3 k3.  12 field accesses per
 // DOF per step instead of the 16 of the textbook three-register form.
 // ---------------------------------------------------------------------------------
+// Thread map: one workgroup of (N+1)^2 threads handles EPB consecutive elements;
+// thread t owns the modal index (kx, ky) = (t mod (N+1), t div (N+1)) in every one of
+// them.  So the per-index tables (the diagonal solve and the face vectors at kx and
+// ky) sit in registers for the whole kernel, and the element loop is uniform across
+// the workgroup: state addresses are a scalar element base plus the thread's fixed
+// offset.
 template <typename T, int STAGE, int N1C, int EPB>
-__global__ __launch_bounds__(256) void k_stage(StageArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   const int n1 = N1C > 0 ? N1C : a.n1;
   const int nn = n1 * n1;
+  const int tid = threadIdx.x;                   // blockDim.x == nn
+  const int ky = tid / n1, kx = tid - ky * n1;
   extern __shared__ unsigned char smem_raw[];
   T* sgh = reinterpret_cast<T*>(smem_raw);       // [8][n1] face tables
   T* sig = sgh + 8 * n1;                         // [EPB][8][n1] modal face fluxes
   T* snew = sig + EPB * 8 * n1;                  // [EPB][2][nn] new stage values
   const long e0 = (long)blockIdx.x * EPB;
   const int ne = (int)min((long)EPB, a.nel - e0);
-  const int tid = threadIdx.x;
 
+  // Issue the state loads of all EPB elements first, so that their HBM latency
+  // overlaps the trace loads and the flux computation.  An element's state is read
+  // and written only by this workgroup, so loading it all before the (in-place)
+  // stores is safe.
+  T ru[EPB], rv[EPB], xu[EPB], xv[EPB];
+#pragma unroll
+  for (int l = 0; l < EPB; ++l) {
+    ru[l] = rv[l] = xu[l] = xv[l] = T(0);
+    if (l < ne) {
+      const long g = (e0 + l) * nn + tid;
+      ru[l] = a.in_u[g];
+      rv[l] = a.in_v[g];
+      if (STAGE > 1) {
+        xu[l] = a.aux_u[g];
+        xv[l] = a.aux_v[g];
+      }
+    }
+  }
+  const T il = a.invL[tid], lm = a.lam[tid];
+  const T gEk = a.gh[0 * n1 + kx], hEk = a.gh[1 * n1 + kx];
+  const T gWk = a.gh[2 * n1 + kx], hWk = a.gh[3 * n1 + kx];
+  const T gNk = a.gh[4 * n1 + ky], hNk = a.gh[5 * n1 + ky];
+  const T gSk = a.gh[6 * n1 + ky], hSk = a.gh[7 * n1 + ky];
   for (int i = tid; i < 8 * n1; i += blockDim.x) sgh[i] = a.gh[i];
 
   // Phase A: modal face fluxes sigma_u = (1-alpha)(v_nb - v) - beta (a + a_nb),
@@ -301,49 +331,38 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs<T> a) {
 
   // Phase B: modal right-hand side and the RK stage update
   const T dt = a.dt, c2 = a.c2;
-  const long g0 = e0 * nn;
-  for (int i = tid; i < ne * nn; i += blockDim.x) {
-    const int el = i / nn;
-    const int idx = i - el * nn;
-    const int ky = idx / n1, kx = idx - ky * n1;
-    const long g = g0 + i;
-    const T ub = a.in_u[g], vb = a.in_v[g];
-    const T* s = sig + el * 8 * n1;
-    const T Lu = sgh[0 * n1 + kx] * s[0 * n1 + ky] + sgh[2 * n1 + kx] * s[2 * n1 + ky] +
-                 sgh[4 * n1 + ky] * s[4 * n1 + kx] + sgh[6 * n1 + ky] * s[6 * n1 + kx];
-    const T Lv = sgh[1 * n1 + kx] * s[1 * n1 + ky] + sgh[3 * n1 + kx] * s[3 * n1 + ky] +
-                 sgh[5 * n1 + ky] * s[5 * n1 + kx] + sgh[7 * n1 + ky] * s[7 * n1 + kx];
-    const T ku = vb + a.invL[idx] * Lu;
-    const T kv = c2 * (Lv - a.lam[idx] * ub);
+#pragma unroll
+  for (int l = 0; l < EPB; ++l) {
+    if (l >= ne) break;
+    const T* s = sig + l * 8 * n1;
+    const T ub = ru[l], vb = rv[l], yu = xu[l], yv = xv[l];
+    const T Lu = gEk * s[0 * n1 + ky] + gWk * s[2 * n1 + ky] + gNk * s[4 * n1 + kx] +
+                 gSk * s[6 * n1 + kx];
+    const T Lv = hEk * s[1 * n1 + ky] + hWk * s[3 * n1 + ky] + hNk * s[5 * n1 + kx] +
+                 hSk * s[7 * n1 + kx];
+    const T ku = vb + il * Lu;
+    const T kv = c2 * (Lv - lm * ub);
+    const long g = (e0 + l) * nn + tid;
     T nu, nv;
-    if (STAGE == 1) {
+    if (STAGE == 1) {          // the input is y itself
       nu = ub + T(0.5) * dt * ku;
       nv = vb + T(0.5) * dt * kv;
-      a.out_u[g] = nu;
-      a.out_v[g] = nv;
-    } else if (STAGE == 2) {
-      const T yu = a.aux_u[g], yv = a.aux_v[g];
+    } else if (STAGE == 2) {   // yu, yv = y
       nu = yu + T(0.5) * dt * ku;
       nv = yv + T(0.5) * dt * kv;
-      a.out_u[g] = nu;
-      a.out_v[g] = nv;
       a.acc_u[g] = ub + T(2) * nu - yu;
       a.acc_v[g] = vb + T(2) * nv - yv;
-    } else if (STAGE == 3) {
-      const T yu = a.aux_u[g], yv = a.aux_v[g];
+    } else if (STAGE == 3) {   // yu, yv = y
       nu = yu + dt * ku;
       nv = yv + dt * kv;
-      a.out_u[g] = nu;
-      a.out_v[g] = nv;
-    } else {
-      const T tu = a.aux_u[g], tv = a.aux_v[g];
-      nu = (tu + ub) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * ku;
-      nv = (tv + vb) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * kv;
-      a.out_u[g] = nu;
-      a.out_v[g] = nv;
+    } else {                   // yu, yv = accumulator
+      nu = (yu + ub) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * ku;
+      nv = (yv + vb) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * kv;
     }
-    snew[(el * 2) * nn + idx] = nu;
-    snew[(el * 2 + 1) * nn + idx] = nv;
+    a.out_u[g] = nu;
+    a.out_v[g] = nv;
+    snew[(l * 2) * nn + tid] = nu;
+    snew[(l * 2 + 1) * nn + tid] = nv;
   }
   __syncthreads();
 
@@ -354,8 +373,8 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs<T> a) {
     const int f2 = r / n1, j = r - f2 * n1;
     const T* F = snew + (el * 2 + (f2 & 1)) * nn;
     const T* gg = sgh + f2 * n1;
-    const T acc = (f2 < 4) ? dot_row<T, N1C>(gg, F, j, n1) : dot_col<T, N1C>(gg, F, j, n1);
-    a.tr_out[e0 * 8 * n1 + i] = acc;
+    a.tr_out[e0 * 8 * n1 + i] =
+        (f2 < 4) ? dot_row<T, N1C>(gg, F, j, n1) : dot_col<T, N1C>(gg, F, j, n1);
   }
 }
 
@@ -452,17 +471,17 @@ static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   const int n1 = a.n1;
   const size_t sh = (size_t)(8 * n1 + EPB * 8 * n1 + EPB * 2 * n1 * n1) * sizeof(T);
   const unsigned nblk = (unsigned)((a.nel + EPB - 1) / EPB);
-  hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB>), dim3(nblk), dim3(256), sh, st, a);
+  hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB>), dim3(nblk), dim3(n1 * n1), sh, st, a);
   return hipGetLastError();
 }
 
-// Elements per workgroup: as many as fit 64 KiB of LDS (4 in FP64, 8 in FP32 for the
-// common sizes).
+// Elements per workgroup: 4 (FP64) or 8 (FP32) when they fit 64 KiB of LDS, else fewer.
 template <typename T, int STAGE, int N1C>
 static hipError_t dispatch_epb(const StageArgs<T>& a, hipStream_t st) {
   auto bytes = [&](int epb) {
     return (size_t)(8 * a.n1 + epb * 8 * a.n1 + epb * 2 * a.n1 * a.n1) * sizeof(T);
   };
+  if (a.n1 * a.n1 > 1024) return hipErrorInvalidValue;
   constexpr int E0 = sizeof(T) == 8 ? 4 : 8;
   if (bytes(E0) <= 65536) return launch_stage_t<T, STAGE, N1C, E0>(a, st);
   if (bytes(2) <= 65536) return launch_stage_t<T, STAGE, N1C, 2>(a, st);

@@ -9,7 +9,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgdw.so")
+LIB_PATH = os.environ.get("GDW_LIB") or os.path.join(_HERE, "libgdw.so")
 
 GDW_OK, GDW_EINVAL, GDW_ENOMEM, GDW_EHIP, GDW_ENOCONV, GDW_ENONFINITE, GDW_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6

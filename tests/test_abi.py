@@ -54,7 +54,7 @@ def _desc(**kw):
     (dict(flux=7), gdw.GDW_EINVAL),
     (dict(flux=gdw.GDW_FLUX_UPWIND, xi=0.0), gdw.GDW_EINVAL),
     (dict(precision=9), gdw.GDW_EINVAL),
-    (dict(N=48), gdw.GDW_EINVAL),
+    (dict(N=32), gdw.GDW_EINVAL),
 ])
 def test_invalid_descriptors_rejected_on_host(kw, status):
     """Validation happens before any device call, so it runs without a GPU."""
