@@ -55,7 +55,9 @@ typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1 } gdw_flux;
 typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1 } gdw_precision;
 
 /* Local solve.  FDM: simultaneous diagonalisation (Sec. 3.2), constant c^2 on
- * Cartesian elements only.  AUTO picks FDM when it applies. */
+ * Cartesian elements only.  PCG: preconditioned conjugate gradients per element
+ * (Sec. 7.1) with the tensor-product preconditioner built from element averages;
+ * required for variable c^2 or mapped elements.  AUTO picks FDM when it applies. */
 typedef enum { GDW_SOLVE_AUTO = 0, GDW_SOLVE_FDM = 1, GDW_SOLVE_PCG = 2 } gdw_solver;
 
 typedef struct {
@@ -64,11 +66,15 @@ typedef struct {
   int p;               /* odd GD degree                                              Sec. 2   */
   double x0, y0;       /* lower-left corner of the periodic rectangle                          */
   double Lx, Ly;       /* its side lengths (> 0)                                               */
-  double c2;           /* constant c^2 > 0 (variable c^2 is not offered by this build)          */
+  double c2;           /* constant c^2 > 0 (used when coeff_variable = 0)                      */
   int flux;            /* gdw_flux                                                   Sec. 2.2.1 */
   double xi;           /* upwind splitting speed xi > 0 (paper: xi = c)              Sec. 2.2.1 */
   int precision;       /* gdw_precision                                                       */
   int solver;          /* gdw_solver                                                          */
+  int coeff_variable;  /* 1: c^2 given at the nodes by gdw_set_coeff (PCG path)      Sec. 7.1 */
+  int mapped;          /* 1: element node coordinates given by gdw_set_coeff (PCG path)        */
+  double pcg_rtol;     /* PCG stop: ||b - A x||_2 <= pcg_rtol ||b||_2 (<= 0: 1e-12)   Sec. 7.1 */
+  int pcg_maxit;       /* PCG iteration limit per element solve (<= 0: 200)                   */
 } gdw_desc;
 
 typedef struct gdw_ctx gdw_ctx;   /* opaque; owns every device workspace */
@@ -83,26 +89,45 @@ const char* gdw_last_error(void);
  * vectors (Sec. 3.1, Sec. 3.2) on the host, the generalised eigenbasis
  * S_j psi = lambda M_j psi with psi^T M_j psi = 1 (Sec. 3.2) in FP64 on the device.
  * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
- * non-positive length, c2 or xi, an unknown enum; EUNSUPPORTED for solver PCG;
- * ENOMEM / EHIP from the device.  Uses the current HIP device; synchronous. */
+ * non-positive length, c2 or xi, an unknown enum, solver FDM with a variable
+ * coefficient or a mapped mesh; EUNSUPPORTED for the PCG path with p > 7 or an element
+ * operator that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path
+ * in GDW_MIXED_FP32; ENOMEM / EHIP from the device.  Uses the current HIP device;
+ * synchronous. */
 gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out);
 
-/* Load the state (u, v) from nodal values U, V (device FP64, layout above).  The
- * state is kept in the simultaneously diagonalised basis of Sec. 3.2
- * (U = Psi Ubar), so this call applies Psi^{-1} = Psi^T M per element and computes
- * the face traces of the new state.  Errors: EINVAL on NULL arguments. */
+/* PCG path only: element geometry and coefficient, then assembly (Sec. 7.1).
+ * c2_nodal: c^2 at every node (device FP64, layout above), NULL = desc.c2 everywhere;
+ * X_nodal, Y_nodal: physical coordinates of every node, NULL = the Cartesian node
+ * positions of the descriptor.  Both copies of a face node must carry the same
+ * coordinates and c^2 (a conforming mesh); every element map must have a positive
+ * Jacobian (not checked).  Each element is the isoparametric GD image of the
+ * reference square; S_K, M_J, w and the face metric are integrated with (p+1)^2
+ * Gauss points per cell and p+1 per face cell.  Must precede gdw_set_state.
+ * Errors: EINVAL on the FDM path, on NULL ctx, or when only one of X, Y is given. */
+gdw_status gdw_set_coeff(gdw_ctx* ctx, const double* c2_nodal, const double* X_nodal,
+                         const double* Y_nodal, void* stream);
+
+/* Load the state (u, v) from nodal values U, V (device FP64, layout above).  On the
+ * FDM path the state is kept in the simultaneously diagonalised basis of Sec. 3.2
+ * (U = Psi Ubar), so this call applies Psi^{-1} = Psi^T M per element; on the PCG path
+ * it is kept nodal and the PCG warm starts are reset to zero.  Either way the face
+ * traces of the new state are computed.  Errors: EINVAL on NULL arguments, or on the
+ * PCG path before gdw_set_coeff. */
 gdw_status gdw_set_state(gdw_ctx* ctx, const double* U, const double* V, void* stream);
 
 /* Advance `steps` classical RK4 steps of size dt (> 0) on `stream` (asynchronous).
  * Each stage evaluates DG1 + DG1_extra, DG2 element by element with the face
- * fluxes and the local solves of Sec. 3.2, fused in one kernel per stage.
+ * fluxes and the local solves (Sec. 3.2 FDM, or Sec. 7.1 PCG warm-started from the
+ * previous stage), fused in one kernel per stage.  A PCG solve that reaches
+ * pcg_maxit is reported by gdw_get_stats (ENOCONV), not here.
  * steps = 0 is a no-op.  Errors: EINVAL for dt <= 0 or not finite, steps < 0. */
 gdw_status gdw_run(gdw_ctx* ctx, double dt, int steps, void* stream);
 
 /* Write the nodal values of the current state to U, V (device FP64). */
 gdw_status gdw_get_state(gdw_ctx* ctx, double* U, double* V, void* stream);
 
-/* Discrete energy sum_k 1/2 V^T M V + 1/2 c^2 U^T S U (Sec. 2.2; conserved by the
+/* Discrete energy sum_k 1/2 V^T M V + 1/2 U^T S_{c^2} U (Sec. 2.2; conserved by the
  * central flux), accumulated in FP64 in a fixed order (deterministic).  Synchronises
  * `stream`; *E_host receives the value.  Returns ENONFINITE if it is not finite. */
 gdw_status gdw_energy(gdw_ctx* ctx, double* E_host, void* stream);
@@ -113,10 +138,16 @@ typedef struct {
   int n1;                    /* N + 1                                              */
   int precision;             /* gdw_precision in use                               */
   int solver;                /* gdw_solver in use (FDM or PCG)                     */
-  int fail_elem;             /* first element with a failure, -1 if none           */
+  int fail_elem;             /* first element whose PCG hit pcg_maxit, -1 if none  */
+  double mean_it_S;          /* PCG: mean iterations per S_hat solve (dU/dt)        */
+  double mean_it_M;          /* PCG: mean iterations per M_J solve (dV/dt)          */
+  int max_it_S, max_it_M;    /* PCG: largest single-solve counts                   */
+  long long solves;          /* PCG: element solves of each kind since set_state   */
 } gdw_stats;
 
-/* Counters of the context.  Synchronises `stream`. */
+/* Counters of the context.  Synchronises `stream`.  Returns ENOCONV (with
+ * fail_elem set) if a PCG solve reached pcg_maxit, ENONFINITE if the state holds
+ * NaN or Inf; *out is filled in either case. */
 gdw_status gdw_get_stats(gdw_ctx* ctx, gdw_stats* out, void* stream);
 
 /* Free every device workspace of the context (NULL is ignored).  Synchronises the

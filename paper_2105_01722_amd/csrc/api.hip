@@ -2,6 +2,8 @@
 // the RK4 time loop of the constant-coefficient path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -10,6 +12,8 @@
 
 #include "fdm.h"
 #include "gdw_internal.h"
+#include "pcg.h"
+#include "stencil.h"
 
 namespace gdw {
 
@@ -28,6 +32,9 @@ using namespace gdw;
       return _e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;                           \
     }                                                                                     \
   } while (0)
+
+// "no failure" value of the PCG failure slot (hipMemset byte 0x7f); element ids are smaller
+static constexpr int kFailNone = 0x7f7f7f7f;
 
 struct gdw_ctx {
   gdw_desc d{};
@@ -52,6 +59,20 @@ struct gdw_ctx {
   int trc = 0;                 // trace buffer holding the traces of y
   long long steps_taken = 0;
   int have_state = 0;
+  int solver = GDW_SOLVE_FDM;  // resolved solver
+  // ---- PCG path ----
+  PcgGeom g{};
+  PcgElem el{};
+  void* own[16] = {};          // device tables of g (freed with the context)
+  double* xS = nullptr;
+  double* xM = nullptr;
+  int* its = nullptr;
+  int* fail = nullptr;
+  double* coords = nullptr;    // Cartesian X, Y, constant c^2 when not given
+  int have_coeff = 0;
+  long long stages_since_state = 0;
+  double rtol = 1e-12;
+  int maxit = 200;
 };
 
 static void free_all(gdw_ctx* c) {
@@ -59,6 +80,9 @@ static void free_all(gdw_ctx* c) {
   for (auto& r : c->Y) for (auto& p : r) F(p);
   F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh);
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
+  for (auto& p : c->own) F(p);
+  F(c->el.S); F(c->el.M); F(c->el.S32); F(c->el.M32); F(c->el.w); F(c->el.sc); F(c->el.face);
+  F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords);
 }
 
 extern "C" const char* gdw_version(void) { return "gdw 0.1 (gfx950)"; }
@@ -84,7 +108,14 @@ static gdw_status validate(const gdw_desc* d) {
   if (d->solver != GDW_SOLVE_AUTO && d->solver != GDW_SOLVE_FDM && d->solver != GDW_SOLVE_PCG) {
     set_error("unknown solver"); return GDW_EINVAL;
   }
-  if (d->solver == GDW_SOLVE_PCG) { set_error("the PCG solver is not available in this build"); return GDW_EUNSUPPORTED; }
+  const bool general = d->coeff_variable || d->mapped;
+  if (d->solver == GDW_SOLVE_FDM && general) {
+    set_error("the FDM solve needs a constant c^2 on Cartesian elements"); return GDW_EINVAL;
+  }
+  const bool pcg = d->solver == GDW_SOLVE_PCG || general;
+  if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
+  if (pcg && d->precision != GDW_FP64) { set_error("the PCG path runs in FP64 in this build"); return GDW_EUNSUPPORTED; }
+  if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
   if (nel > 4.0e9) { set_error("problem too large"); return GDW_EINVAL; }
   return GDW_OK;
@@ -158,15 +189,8 @@ static gdw_status upload_tables(gdw_ctx* c, const std::vector<double>& gh,
   return upload_as<float>(&c->lam, lam);
 }
 
-static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
-  c->d = *d;
+static gdw_status create_fdm(const gdw_desc* d, gdw_ctx* c) {
   const int N = d->N, p = d->p, n1 = N + 1, nn = n1 * n1;
-  c->n1 = n1;
-  c->nel = (long)d->nx * d->ny;
-  c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
-  c->alpha = 0.5;
-  c->beta = d->flux == GDW_FLUX_UPWIND ? 0.5 * d->xi : 0.0;
-  c->tau = d->flux == GDW_FLUX_UPWIND ? 0.5 / d->xi : 0.0;
 
   std::vector<double> Psx, lx, Mx, dLx, dRx, Psy, ly, My, dLy, dRy;
   gdw_status s;
@@ -230,6 +254,120 @@ static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
   return GDW_OK;
 }
 
+
+// ---------------------------------------------------------------------------------
+// PCG path set-up
+// ---------------------------------------------------------------------------------
+template <typename V>
+static gdw_status own_upload(gdw_ctx* c, int slot, const std::vector<V>& v, const V** dst) {
+  void* p = nullptr;
+  GDW_HIP(hipMalloc(&p, v.size() * sizeof(V)));
+  c->own[slot] = p;
+  GDW_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
+  *dst = (const V*)p;
+  return GDW_OK;
+}
+
+static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
+  const int N = d->N, p = d->p, n1 = N + 1, nn = n1 * n1, m = p + 1;
+  PcgGeom& g = c->g;
+  g.N = N; g.p = p; g.n1 = n1; g.nn = nn; g.m = m; g.nq = N * m;
+  std::vector<int> rowoff(nn + 1, 0), cs(N), ck0(n1, N), ck1(n1, -1);
+  for (int i = 0; i < nn; ++i) rowoff[i + 1] = rowoff[i] + st_count(i % n1, i / n1, p, N);
+  g.nst = rowoff[nn];
+  for (int k = 0; k < N; ++k) {
+    cs[k] = gd_window_start(k, N, p);
+    for (int j = 0; j < m; ++j) {
+      ck0[cs[k] + j] = std::min(ck0[cs[k] + j], k);
+      ck1[cs[k] + j] = std::max(ck1[cs[k] + j], k);
+    }
+  }
+  std::vector<double> xg(m), gw(m), cb((size_t)N * m * m), cd((size_t)N * m * m), val(n1), der(n1);
+  gauss_legendre01(m, xg.data(), gw.data());
+  for (int k = 0; k < N; ++k)
+    for (int a = 0; a < m; ++a) {
+      gd1d_eval_cell(N, p, k, k + xg[a], val.data(), der.data());
+      for (int j = 0; j < m; ++j) {
+        cb[(k * m + a) * m + j] = val[cs[k] + j];
+        cd[(k * m + a) * m + j] = der[cs[k] + j] * N;
+      }
+    }
+  // reference interval [0, 1]: element_1d with H = 1 gives M_ref, S_ref and d/dr vectors
+  std::vector<double> Psi, lam, Mref, dL, dR;
+  gdw_status s;
+  if ((s = eigen_dir(N, p, 1.0, Psi, lam, Mref, dL, dR)) != GDW_OK) return s;
+  if ((s = own_upload<int>(c, 0, rowoff, &g.rowoff)) != GDW_OK) return s;
+  if ((s = own_upload<int>(c, 1, cs, &g.cs)) != GDW_OK) return s;
+  if ((s = own_upload<int>(c, 2, ck0, &g.ck0)) != GDW_OK) return s;
+  if ((s = own_upload<int>(c, 3, ck1, &g.ck1)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 4, cb, &g.cb)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 5, cd, &g.cd)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 6, gw, &g.gw)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 7, dL, &g.dL)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 8, dR, &g.dR)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 9, Psi, &g.Psi)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 10, lam, &g.lamr)) != GDW_OK) return s;
+  if ((s = own_upload<double>(c, 11, Mref, &g.Mref)) != GDW_OK) return s;
+  if (pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
+    set_error("element operator does not fit the LDS of a workgroup (reduce N or p)");
+    return GDW_EUNSUPPORTED;
+  }
+  const long nel = c->nel;
+  const size_t nodal = (size_t)nel * nn * sizeof(double);
+  GDW_HIP(hipMalloc(&c->el.S, (size_t)nel * g.nst * sizeof(double)));
+  if (d->mapped) GDW_HIP(hipMalloc(&c->el.M, (size_t)nel * g.nst * sizeof(double)));
+  GDW_HIP(hipMalloc(&c->el.w, nodal));
+  GDW_HIP(hipMalloc(&c->el.sc, (size_t)nel * 8 * sizeof(double)));
+  GDW_HIP(hipMalloc(&c->el.face, (size_t)nel * 4 * g.nq * 3 * sizeof(double)));
+  for (auto& r : c->Y)
+    for (auto& ptr : r) {
+      GDW_HIP(hipMalloc(&ptr, nodal));
+      GDW_HIP(hipMemset(ptr, 0, nodal));
+    }
+  const size_t trb = (size_t)nel * 4 * g.nq * 2 * sizeof(double);
+  for (auto& t : c->tr) {
+    GDW_HIP(hipMalloc(&t, trb));
+    GDW_HIP(hipMemset(t, 0, trb));
+  }
+  GDW_HIP(hipMalloc(&c->xS, nodal));
+  GDW_HIP(hipMalloc(&c->xM, nodal));
+  GDW_HIP(hipMalloc(&c->its, (size_t)nel * 4 * sizeof(int)));
+  GDW_HIP(hipMalloc(&c->fail, sizeof(int)));
+  GDW_HIP(hipMalloc(&c->epart, (size_t)(nel + 1) * sizeof(double)));
+  GDW_HIP(hipMalloc(&c->nonfinite, sizeof(unsigned int)));
+  // Cartesian node coordinates (from the global node index, so that both copies of a
+  // face node are bitwise equal) and the constant c^2, used when set_coeff gets NULL
+  std::vector<double> xyz((size_t)3 * nel * nn);
+  for (int ey = 0; ey < d->ny; ++ey)
+    for (int ex = 0; ex < d->nx; ++ex)
+      for (int iy = 0; iy < n1; ++iy)
+        for (int ix = 0; ix < n1; ++ix) {
+          const size_t k = ((size_t)(ey * d->nx + ex) * n1 + iy) * n1 + ix;
+          xyz[k] = d->x0 + (double)(ex * N + ix) * (d->Lx / ((double)d->nx * N));
+          xyz[(size_t)nel * nn + k] = d->y0 + (double)(ey * N + iy) * (d->Ly / ((double)d->ny * N));
+          xyz[(size_t)2 * nel * nn + k] = d->c2;
+        }
+  GDW_HIP(hipMalloc(&c->coords, xyz.size() * sizeof(double)));
+  GDW_HIP(hipMemcpy(c->coords, xyz.data(), xyz.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->rtol = d->pcg_rtol > 0 ? d->pcg_rtol : 1e-12;
+  c->maxit = d->pcg_maxit > 0 ? d->pcg_maxit : 200;
+  GDW_HIP(hipDeviceSynchronize());
+  return GDW_OK;
+}
+
+static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
+  c->d = *d;
+  c->n1 = d->N + 1;
+  c->nel = (long)d->nx * d->ny;
+  c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
+  c->alpha = 0.5;
+  c->beta = d->flux == GDW_FLUX_UPWIND ? 0.5 * d->xi : 0.0;
+  c->tau = d->flux == GDW_FLUX_UPWIND ? 0.5 / d->xi : 0.0;
+  const bool pcg = d->solver == GDW_SOLVE_PCG || d->coeff_variable || d->mapped;
+  c->solver = pcg ? GDW_SOLVE_PCG : GDW_SOLVE_FDM;
+  return pcg ? create_pcg(d, c) : create_fdm(d, c);
+}
+
 extern "C" gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out) {
   if (!out) { set_error("out is NULL"); return GDW_EINVAL; }
   *out = nullptr;
@@ -247,6 +385,22 @@ extern "C" gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out) {
   return GDW_OK;
 }
 
+extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* X, const double* Y,
+                                    void* stream) {
+  if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
+  if (c->solver != GDW_SOLVE_PCG) { set_error("gdw_set_coeff applies to the PCG path only"); return GDW_EINVAL; }
+  if ((X == nullptr) != (Y == nullptr)) { set_error("give both X and Y or neither"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nn = (size_t)c->g.nn;
+  const double* Xd = X ? X : c->coords;
+  const double* Yd = Y ? Y : c->coords + (size_t)c->nel * nn;
+  const double* Cd = c2 ? c2 : c->coords + (size_t)2 * c->nel * nn;
+  GDW_HIP(launch_assemble(c->g, Xd, Yd, Cd, c->el, c->nel, st));
+  GDW_HIP(launch_face_geom(c->g, Xd, Yd, Cd, c->el, c->nel, st));
+  c->have_coeff = 1;
+  return GDW_OK;
+}
+
 template <typename T>
 static hipError_t set_state_t(gdw_ctx* c, const double* U, const double* V, hipStream_t st) {
   hipError_t e;
@@ -260,7 +414,22 @@ static hipError_t set_state_t(gdw_ctx* c, const double* U, const double* V, hipS
 extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V, void* stream) {
   if (!c || !U || !V) { set_error("NULL argument"); return GDW_EINVAL; }
   hipStream_t st = (hipStream_t)stream;
-  GDW_HIP(c->elem_bytes == 8 ? set_state_t<double>(c, U, V, st) : set_state_t<float>(c, U, V, st));
+  if (c->solver == GDW_SOLVE_PCG) {
+    if (!c->have_coeff) { set_error("call gdw_set_coeff before gdw_set_state"); return GDW_EINVAL; }
+    const size_t nodal = (size_t)c->nel * c->g.nn * sizeof(double);
+    GDW_HIP(hipMemcpyAsync(c->Y[0][0], U, nodal, hipMemcpyDeviceToDevice, st));
+    GDW_HIP(hipMemcpyAsync(c->Y[0][1], V, nodal, hipMemcpyDeviceToDevice, st));
+    GDW_HIP(hipMemsetAsync(c->xS, 0, nodal, st));
+    GDW_HIP(hipMemsetAsync(c->xM, 0, nodal, st));
+    GDW_HIP(hipMemsetAsync(c->its, 0, (size_t)c->nel * 4 * sizeof(int), st));
+    GDW_HIP(hipMemsetAsync(c->fail, 0x7f, sizeof(int), st));
+    c->trc = 0;
+    c->stages_since_state = 0;
+    GDW_HIP(launch_pcg_traces(c->g, c->el, (const double*)c->Y[0][0], (const double*)c->Y[0][1],
+                              (double*)c->tr[0], c->nel, st));
+  } else {
+    GDW_HIP(c->elem_bytes == 8 ? set_state_t<double>(c, U, V, st) : set_state_t<float>(c, U, V, st));
+  }
   c->have_state = 1;
   return GDW_OK;
 }
@@ -313,13 +482,66 @@ static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   return hipSuccess;
 }
 
+static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+  PcgStageArgs a{};
+  a.g = c->g;
+  a.el = c->el;
+  a.xS = c->xS;
+  a.xM = c->xM;
+  a.its = c->its;
+  a.fail = c->fail;
+  a.nel = c->nel;
+  a.nx = c->d.nx;
+  a.ny = c->d.ny;
+  a.mapped = c->d.mapped;
+  a.dt = dt;
+  a.alpha = c->alpha;
+  a.beta = c->beta;
+  a.tau = c->tau;
+  a.rtol = c->rtol;
+  a.rtol_inner = 1e-6;
+  a.maxit = c->maxit;
+  a.mixed = 0;
+  double* y_u = (double*)c->Y[0][0];
+  double* y_v = (double*)c->Y[0][1];
+  double* Y_u = (double*)c->Y[1][0];
+  double* Y_v = (double*)c->Y[1][1];
+  double* A_u = (double*)c->Y[2][0];
+  double* A_v = (double*)c->Y[2][1];
+  double* t0 = (double*)c->tr[c->trc];
+  double* t1 = (double*)c->tr[c->trc ^ 1];
+  hipError_t e;
+  for (int s = 0; s < steps; ++s) {
+    a.in_u = y_u; a.in_v = y_v; a.aux_u = nullptr; a.aux_v = nullptr;
+    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = nullptr; a.acc_v = nullptr;
+    a.tr_in = t0; a.tr_out = t1;
+    if ((e = launch_pcg_stage(1, a, st)) != hipSuccess) return e;
+    a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
+    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = A_u; a.acc_v = A_v;
+    a.tr_in = t1; a.tr_out = t0;
+    if ((e = launch_pcg_stage(2, a, st)) != hipSuccess) return e;
+    a.acc_u = nullptr; a.acc_v = nullptr;
+    a.tr_in = t0; a.tr_out = t1;
+    if ((e = launch_pcg_stage(3, a, st)) != hipSuccess) return e;
+    a.aux_u = A_u; a.aux_v = A_v;
+    a.out_u = y_u; a.out_v = y_v;
+    a.tr_in = t1; a.tr_out = t0;
+    if ((e = launch_pcg_stage(4, a, st)) != hipSuccess) return e;
+  }
+  c->stages_since_state += 4LL * steps;
+  return hipSuccess;
+}
+
 extern "C" gdw_status gdw_run(gdw_ctx* c, double dt, int steps, void* stream) {
   if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
   if (!(dt > 0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return GDW_EINVAL; }
   if (steps < 0) { set_error("steps must be >= 0"); return GDW_EINVAL; }
   if (!c->have_state) { set_error("no state: call gdw_set_state first"); return GDW_EINVAL; }
   hipStream_t st = (hipStream_t)stream;
-  GDW_HIP(c->elem_bytes == 8 ? run_t<double>(c, dt, steps, st) : run_t<float>(c, dt, steps, st));
+  if (c->solver == GDW_SOLVE_PCG)
+    GDW_HIP(run_pcg(c, dt, steps, st));
+  else
+    GDW_HIP(c->elem_bytes == 8 ? run_t<double>(c, dt, steps, st) : run_t<float>(c, dt, steps, st));
   c->steps_taken += steps;
   return GDW_OK;
 }
@@ -327,7 +549,11 @@ extern "C" gdw_status gdw_run(gdw_ctx* c, double dt, int steps, void* stream) {
 extern "C" gdw_status gdw_get_state(gdw_ctx* c, double* U, double* V, void* stream) {
   if (!c || !U || !V) { set_error("NULL argument"); return GDW_EINVAL; }
   hipStream_t st = (hipStream_t)stream;
-  if (c->elem_bytes == 8) {
+  if (c->solver == GDW_SOLVE_PCG) {
+    const size_t nodal = (size_t)c->nel * c->g.nn * sizeof(double);
+    GDW_HIP(hipMemcpyAsync(U, c->Y[0][0], nodal, hipMemcpyDeviceToDevice, st));
+    GDW_HIP(hipMemcpyAsync(V, c->Y[0][1], nodal, hipMemcpyDeviceToDevice, st));
+  } else if (c->elem_bytes == 8) {
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
   } else {
@@ -340,15 +566,22 @@ extern "C" gdw_status gdw_get_state(gdw_ctx* c, double* U, double* V, void* stre
 extern "C" gdw_status gdw_energy(gdw_ctx* c, double* E_host, void* stream) {
   if (!c || !E_host) { set_error("NULL argument"); return GDW_EINVAL; }
   hipStream_t st = (hipStream_t)stream;
-  double* out = c->epart + c->npart;
-  if (c->elem_bytes == 8)
-    GDW_HIP(launch_energy<double>((const double*)c->Y[0][0], (const double*)c->Y[0][1],
-                                  (const double*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
-                                  c->npart, out, st));
-  else
-    GDW_HIP(launch_energy<float>((const float*)c->Y[0][0], (const float*)c->Y[0][1],
-                                 (const float*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
-                                 c->npart, out, st));
+  double* out;
+  if (c->solver == GDW_SOLVE_PCG) {
+    out = c->epart + c->nel;
+    GDW_HIP(launch_pcg_energy(c->g, c->el, (const double*)c->Y[0][0], (const double*)c->Y[0][1],
+                              c->nel, c->epart, (int)c->nel, out, st));
+  } else {
+    out = c->epart + c->npart;
+    if (c->elem_bytes == 8)
+      GDW_HIP(launch_energy<double>((const double*)c->Y[0][0], (const double*)c->Y[0][1],
+                                    (const double*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
+                                    c->npart, out, st));
+    else
+      GDW_HIP(launch_energy<float>((const float*)c->Y[0][0], (const float*)c->Y[0][1],
+                                   (const float*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
+                                   c->npart, out, st));
+  }
   GDW_HIP(hipMemcpyAsync(E_host, out, sizeof(double), hipMemcpyDeviceToHost, st));
   GDW_HIP(hipStreamSynchronize(st));
   if (!std::isfinite(*E_host)) { set_error("energy is not finite"); return GDW_ENONFINITE; }
@@ -363,19 +596,47 @@ extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
   out->dof_updates = c->steps_taken * c->nel * (long long)c->n1 * c->n1;
   out->n1 = c->n1;
   out->precision = c->d.precision;
-  out->solver = GDW_SOLVE_FDM;
+  out->solver = c->solver;
   out->fail_elem = -1;
   const long n = c->nel * (long)c->n1 * c->n1;
   GDW_HIP(hipMemsetAsync(c->nonfinite, 0, sizeof(unsigned int), st));
   for (int f = 0; f < 2; ++f) {
-    if (c->elem_bytes == 8)
+    if (c->solver == GDW_SOLVE_PCG || c->elem_bytes == 8)
       GDW_HIP(launch_count_nonfinite<double>((const double*)c->Y[0][f], n, c->nonfinite, st));
     else
       GDW_HIP(launch_count_nonfinite<float>((const float*)c->Y[0][f], n, c->nonfinite, st));
   }
   unsigned int cnt = 0;
   GDW_HIP(hipMemcpyAsync(&cnt, c->nonfinite, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  int fail = kFailNone;
+  std::vector<int> its;
+  if (c->solver == GDW_SOLVE_PCG) {
+    its.resize((size_t)c->nel * 4);
+    GDW_HIP(hipMemcpyAsync(its.data(), c->its, its.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    GDW_HIP(hipMemcpyAsync(&fail, c->fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
   GDW_HIP(hipStreamSynchronize(st));
+  if (c->solver == GDW_SOLVE_PCG) {
+    long long sS = 0, sM = 0;
+    int mS = 0, mM = 0;
+    for (long e = 0; e < c->nel; ++e) {
+      sS += its[e * 4];
+      sM += its[e * 4 + 1];
+      mS = std::max(mS, its[e * 4 + 2]);
+      mM = std::max(mM, its[e * 4 + 3]);
+    }
+    const long long solves = c->stages_since_state * c->nel;
+    out->solves = solves;
+    out->mean_it_S = solves ? (double)sS / solves : 0.0;
+    out->mean_it_M = solves ? (double)sM / solves : 0.0;
+    out->max_it_S = mS;
+    out->max_it_M = mM;
+    if (fail != kFailNone) {
+      out->fail_elem = fail;
+      set_error("a PCG element solve reached pcg_maxit");
+      return GDW_ENOCONV;
+    }
+  }
   if (cnt) { set_error("state holds NaN or Inf"); return GDW_ENONFINITE; }
   return GDW_OK;
 }

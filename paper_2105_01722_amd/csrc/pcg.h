@@ -1,0 +1,75 @@
+// Variable-coefficient / mapped-element path: element assembly by quadrature and the
+// fused RK stage with PCG element solves (Sec. 7.1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gdw {
+
+// Tables shared by every element of a problem (device pointers).
+struct PcgGeom {
+  int N, p, n1, nn, m, nq, nst;
+  const int* rowoff;    // [nn+1] start of each row's upper part (stencil.h)
+  const int* cs;        // [N] first node of cell k's window
+  const int* ck0;       // [n1] first cell whose window holds node i
+  const int* ck1;       // [n1] last such cell
+  const double* cb;     // [N][m][m] window function j at Gauss point a of cell k
+  const double* cd;     // [N][m][m] its derivative d/dr (reference spacing 1/N)
+  const double* gw;     // [m] Gauss weights on [0, 1]
+  const double* dL;     // [n1] d/dr of the basis at r = 0
+  const double* dR;     // [n1] d/dr of the basis at r = 1
+  const double* Psi;    // [n1*n1] reference eigenbasis, Psi[i*n1 + k], Psi^T M_ref Psi = I
+  const double* lamr;   // [n1] reference eigenvalues (lamr[0] = 0)
+  const double* Mref;   // [n1*n1] 1D mass matrix on [0, 1] (Cartesian M_J = area Mref (x) Mref)
+};
+
+// Per-element data (device pointers).
+struct PcgElem {
+  double* S;            // [nel][nst] upper half of S_K
+  double* M;            // [nel][nst] upper half of M_J (mapped meshes only)
+  float* S32;           // [nel][nst] FP32 copy of S_K (mixed precision)
+  float* M32;           // [nel][nst] FP32 copy of M_J (mixed precision, mapped)
+  double* w;            // [nel][nn] int phi_i J
+  double* sc;           // [nel][8]: kappa/area, kbar_rr, kbar_ss, kappa*area, area, int c^2 J
+  double* face;         // [nel][4][nq][3]: (K Nh)_r, (K Nh)_s, c^2 s_J at face points
+  float* dlog;          // [nel][nn] log-scale of the S preconditioner diagonal (NULL: plain)
+};
+
+struct PcgStageArgs {
+  PcgGeom g;
+  PcgElem el;
+  const double* in_u;   // stage input (nodal)
+  const double* in_v;
+  const double* aux_u;  // y (stages 2, 3) or the accumulator (stage 4)
+  const double* aux_v;
+  double* out_u;
+  double* out_v;
+  double* acc_u;        // stage 2 only
+  double* acc_v;
+  const double* tr_in;  // [nel][4][nq][2] (a, v) at face points of the stage input
+  double* tr_out;
+  double* xS;           // [nel][nn] warm start / solution of S_hat y = F_u
+  double* xM;           // [nel][nn] warm start / solution of M_J z = r
+  int* its;             // [nel][4]: sum S iterations, sum M iterations, max S, max M
+  int* fail;            // smallest element id that hit maxit (0x7f7f7f7f if none)
+  long nel;
+  int nx, ny;
+  int mapped;
+  double dt, alpha, beta, tau, rtol, rtol_inner;
+  int maxit;
+  int mixed;            // 1: FP32 inner PCG with FP64 residual refinement
+};
+
+hipError_t launch_assemble(const PcgGeom& g, const double* X, const double* Y, const double* C2,
+                           const PcgElem& el, long nel, hipStream_t st);
+hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, const double* C2,
+                            const PcgElem& el, long nel, hipStream_t st);
+hipError_t launch_to_f32(const double* a, float* b, long n, hipStream_t st);
+hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
+                             double* tr, long nel, hipStream_t st);
+hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st);
+size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);
+hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
+                             long nel, double* part, int npart, double* out, hipStream_t st);
+
+}  // namespace gdw

@@ -1,0 +1,728 @@
+// Variable-coefficient and mapped-element path (Sec. 7, Sec. 7.1).
+//
+// Elements are images of the reference square under an isoparametric GD map
+// (X, Y)(r, s); c^2 is a GD function too.  With A = d(X,Y)/d(r,s), J = det A and
+// K = c^2 J A^{-1} A^{-T}, the element matrices of DG1 / DG2 are
+//   M_J = int phi phi J,  S_K = int grad_r phi^T K grad_r phi,  w = int phi J,
+// integrated with (p+1)^2 Gauss points per cell, and the face terms use (p+1) Gauss
+// points per face cell with c^2 (n . grad phi) dS = Nh^T K grad_r phi ds and
+// dS = s_J ds.  The extra equation DG1_extra enters as S_hat = S_K + (kappa/|Omega|) w w^T.
+//
+// Every RK stage is one kernel, one workgroup per element:
+//   face fluxes from the (a, v) traces at the face points of the element and its
+//   neighbours -> lifts F_u, F_v -> r = -S_K U + F_v -> PCG for S_hat y = F_u and
+//   M_J z = r (tensor-product preconditioner from element averages, warm start from
+//   the previous stage) -> dU/dt = V + y, dV/dt = z -> RK stage update -> traces
+//   of the new value for the next stage.
+// The element operator of the running solve sits in LDS (upper half, stencil.h);
+// on Cartesian meshes M_J = |Omega| M_ref (x) M_ref is inverted exactly by the
+// preconditioner itself and is not stored.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "pcg.h"
+#include "stencil.h"
+
+namespace gdw {
+
+// ---------------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic workgroup sum of two values (fixed wave order); red: 2*16 doubles.
+__device__ inline void block_sum2(double& a, double& b, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    red[w] = a;
+    red[16 + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int k = 0; k < nw; ++k) {
+    sa += red[k];
+    sb += red[16 + k];
+  }
+  a = sa;
+  b = sb;
+  __syncthreads();
+}
+
+// Row i = (ix, iy) of a symmetric element operator stored as its upper half.
+template <typename TA, typename TX, typename TACC>
+__device__ inline TACC sym_row(const TA* A, const int* rowoff, const TX* x, int ix, int iy, int p,
+                               int N, int n1) {
+  const int xl = st_lo(ix, p), xh = st_hi(ix, p, N), yh = st_hi(iy, p, N);
+  TACC acc = 0;
+  const TA* r = A + rowoff[iy * n1 + ix];
+  int k = 0;
+  for (int jx = ix; jx <= xh; ++jx) acc += (TACC)r[k++] * (TACC)x[iy * n1 + jx];
+  for (int jy = iy + 1; jy <= yh; ++jy)
+    for (int jx = xl; jx <= xh; ++jx) acc += (TACC)r[k++] * (TACC)x[jy * n1 + jx];
+  for (int jx = xl; jx < ix; ++jx)
+    acc += (TACC)A[rowoff[iy * n1 + jx] + (ix - jx)] * (TACC)x[iy * n1 + jx];
+  for (int jy = st_lo(iy, p); jy < iy; ++jy)
+    for (int jx = xl; jx <= xh; ++jx)
+      acc += (TACC)A[rowoff[jy * n1 + jx] + st_pos(jx, jy, ix, iy, p, N)] * (TACC)x[jy * n1 + jx];
+  return acc;
+}
+
+// Z = Psi diag(dinv) Psi^T R on the (N+1)^2 grid (thread t owns index t); tmp is scratch.
+template <typename T>
+__device__ inline void pinv_apply(const T* R, T* tmp, T* Z, const T* Psi, T dinv, int n1, int nn) {
+  const int t = threadIdx.x;
+  const int a = t / n1, b = t - (t / n1) * n1;    // t = a*n1 + b
+  if (t < nn) {                                   // tmp[ky][ix] = sum_iy Psi[iy][ky] R[iy][ix]
+    T s = 0;
+    for (int iy = 0; iy < n1; ++iy) s += Psi[iy * n1 + a] * R[iy * n1 + b];
+    tmp[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {                                   // Z[ky][kx] = dinv sum_ix tmp[ky][ix] Psi[ix][kx]
+    T s = 0;
+    for (int ix = 0; ix < n1; ++ix) s += tmp[a * n1 + ix] * Psi[ix * n1 + b];
+    Z[t] = s * dinv;
+  }
+  __syncthreads();
+  if (t < nn) {                                   // tmp[iy][kx] = sum_ky Psi[iy][ky] Z[ky][kx]
+    T s = 0;
+    for (int ky = 0; ky < n1; ++ky) s += Psi[a * n1 + ky] * Z[ky * n1 + b];
+    tmp[t] = s;
+  }
+  __syncthreads();
+  if (t < nn) {                                   // Z[iy][ix] = sum_kx tmp[iy][kx] Psi[ix][kx]
+    T s = 0;
+    for (int kx = 0; kx < n1; ++kx) s += tmp[a * n1 + kx] * Psi[b * n1 + kx];
+    Z[t] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------
+// Assembly of S_K, M_J (upper halves), w and the element averages.  One workgroup
+// per element, cells in sequence; each stored entry is updated by one thread per
+// cell, and the cells are separated by barriers.
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_assemble(PcgGeom g, const double* __restrict__ X,
+                                                  const double* __restrict__ Y,
+                                                  const double* __restrict__ C2, PcgElem el,
+                                                  long nel) {
+  const long e = blockIdx.x;
+  if (e >= nel) return;
+  const int t = threadIdx.x, N = g.N, p = g.p, n1 = g.n1, nn = g.nn, m = g.m, mm = m * m;
+  __shared__ double qJ[64], qrr[64], qss[64], qrs[64];
+  __shared__ double Bx[64], Dx[64], By[64], Dy[64];
+  __shared__ double red[32];
+  double* S = el.S + e * g.nst;
+  double* M = el.M ? el.M + e * g.nst : nullptr;
+  double* w = el.w + e * nn;
+  for (int i = t; i < g.nst; i += blockDim.x) {
+    S[i] = 0.0;
+    if (M) M[i] = 0.0;
+  }
+  for (int i = t; i < nn; i += blockDim.x) w[i] = 0.0;
+  const double* Xe = X + e * nn;
+  const double* Ye = Y + e * nn;
+  const double* Ce = C2 + e * nn;
+  double iKrr = 0, iKss = 0, icJ = 0, iA = 0;
+  __syncthreads();
+  for (int kx = 0; kx < N; ++kx) {
+    for (int ky = 0; ky < N; ++ky) {
+      const int sx = g.cs[kx], sy = g.cs[ky];
+      if (t < mm) {
+        Bx[t] = g.cb[kx * mm + t];
+        Dx[t] = g.cd[kx * mm + t];
+        By[t] = g.cb[ky * mm + t];
+        Dy[t] = g.cd[ky * mm + t];
+      }
+      __syncthreads();
+      if (t < mm) {      // geometry at Gauss point (qa, qb) of the cell
+        const int qa = t % m, qb = t / m;
+        double xr = 0, xs = 0, yr = 0, ys = 0, cq = 0;
+        for (int jy = 0; jy < m; ++jy)
+          for (int jx = 0; jx < m; ++jx) {
+            const int nd = (sy + jy) * n1 + sx + jx;
+            const double br = Dx[qa * m + jx] * By[qb * m + jy];
+            const double bs = Bx[qa * m + jx] * Dy[qb * m + jy];
+            const double bv = Bx[qa * m + jx] * By[qb * m + jy];
+            xr += br * Xe[nd];
+            xs += bs * Xe[nd];
+            yr += br * Ye[nd];
+            ys += bs * Ye[nd];
+            cq += bv * Ce[nd];
+          }
+        const double J = xr * ys - xs * yr;
+        const double wq = g.gw[qa] * g.gw[qb] / ((double)N * N);
+        const double krr = cq * (xs * xs + ys * ys) / J;
+        const double kss = cq * (xr * xr + yr * yr) / J;
+        const double krs = -cq * (xr * xs + yr * ys) / J;
+        qJ[t] = wq * J;
+        qrr[t] = wq * krr;
+        qss[t] = wq * kss;
+        qrs[t] = wq * krs;
+        iKrr += wq * krr;
+        iKss += wq * kss;
+        icJ += wq * cq * J;
+        iA += wq * J;
+      }
+      __syncthreads();
+      // local pairs (a, b) of the cell's (p+1)^2 functions, upper half only
+      for (int pr = t; pr < mm * mm; pr += blockDim.x) {
+        const int a = pr / mm, b = pr - (pr / mm) * mm;
+        const int ax = a % m, ay = a / m, bx = b % m, by = b / m;
+        const int ix = sx + ax, iy = sy + ay, jx = sx + bx, jy = sy + by;
+        const int i = iy * n1 + ix, j = jy * n1 + jx;
+        if (i > j) continue;
+        double ss = 0, ms = 0;
+        for (int qb = 0; qb < m; ++qb)
+          for (int qa = 0; qa < m; ++qa) {
+            const int q = qb * m + qa;
+            const double pa = Bx[qa * m + ax] * By[qb * m + ay];
+            const double pb = Bx[qa * m + bx] * By[qb * m + by];
+            const double ra = Dx[qa * m + ax] * By[qb * m + ay];
+            const double rb = Dx[qa * m + bx] * By[qb * m + by];
+            const double sa = Bx[qa * m + ax] * Dy[qb * m + ay];
+            const double sb = Bx[qa * m + bx] * Dy[qb * m + by];
+            ms += qJ[q] * pa * pb;
+            ss += qrr[q] * ra * rb + qss[q] * sa * sb + qrs[q] * (ra * sb + sa * rb);
+          }
+        const int pos = g.rowoff[i] + st_pos(ix, iy, jx, jy, p, N);
+        S[pos] += ss;
+        if (M) M[pos] += ms;
+      }
+      if (t < mm) {
+        const int ax = t % m, ay = t / m;
+        double ws = 0;
+        for (int qb = 0; qb < m; ++qb)
+          for (int qa = 0; qa < m; ++qa)
+            ws += qJ[qb * m + qa] * Bx[qa * m + ax] * By[qb * m + ay];
+        w[(sy + ay) * n1 + sx + ax] += ws;
+      }
+      __syncthreads();
+    }
+  }
+  block_sum2(iKrr, iKss, red);
+  block_sum2(icJ, iA, red);
+  if (t == 0) {
+    double* sc = el.sc + e * 8;
+    const double kappa = icJ / iA;
+    sc[0] = kappa / iA;
+    sc[1] = iKrr;
+    sc[2] = iKss;
+    sc[3] = kappa * iA;
+    sc[4] = iA;
+    sc[5] = icJ;
+    sc[6] = 0.0;
+    sc[7] = 0.0;
+  }
+}
+
+// Geometry at the face points: (K Nh)_r, (K Nh)_s and c^2 s_J.  Faces E (r = 1), W (r = 0),
+// N (s = 1), S (s = 0); point q = k*m + a is Gauss point a of face cell k.
+__global__ void k_face_geom(PcgGeom g, const double* __restrict__ X, const double* __restrict__ Y,
+                            const double* __restrict__ C2, PcgElem el, long nel) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nel * 4 * g.nq) return;
+  const long e = id / (4 * g.nq);
+  const int r = (int)(id - e * 4 * g.nq);
+  const int f = r / g.nq, q = r - f * g.nq;
+  const int k = q / g.m, a = q - k * g.m, m = g.m, n1 = g.n1, N = g.N;
+  const int s0 = g.cs[k];
+  const double* cb = g.cb + (k * m + a) * m;
+  const double* cd = g.cd + (k * m + a) * m;
+  const double* dn = (f == 0 || f == 2) ? g.dR : g.dL;
+  const int node = (f == 0 || f == 2) ? N : 0;
+  const double* Xe = X + e * g.nn;
+  const double* Ye = Y + e * g.nn;
+  const double* Ce = C2 + e * g.nn;
+  double xn = 0, yn = 0, xt = 0, yt = 0, cq = 0;   // normal / tangential derivatives
+  for (int j = 0; j < m; ++j) {
+    const int l = s0 + j;   // node index along the face
+    double gx = 0, gy = 0;
+    for (int i = 0; i < n1; ++i) {
+      const int nd = (f < 2) ? l * n1 + i : i * n1 + l;
+      gx += dn[i] * Xe[nd];
+      gy += dn[i] * Ye[nd];
+    }
+    const int fnd = (f < 2) ? l * n1 + node : node * n1 + l;
+    xn += cb[j] * gx;
+    yn += cb[j] * gy;
+    xt += cd[j] * Xe[fnd];
+    yt += cd[j] * Ye[fnd];
+    cq += cb[j] * Ce[fnd];
+  }
+  double xr, xs, yr, ys, nr, ns;
+  if (f < 2) {              // E / W: normal coordinate r, tangent s
+    xr = xn; yr = yn; xs = xt; ys = yt;
+    nr = f == 0 ? 1.0 : -1.0; ns = 0.0;
+  } else {                  // N / S: normal coordinate s, tangent r
+    xs = xn; ys = yn; xr = xt; yr = yt;
+    nr = 0.0; ns = f == 2 ? 1.0 : -1.0;
+  }
+  const double J = xr * ys - xs * yr;
+  const double krr = cq * (xs * xs + ys * ys) / J;
+  const double kss = cq * (xr * xr + yr * yr) / J;
+  const double krs = -cq * (xr * xs + yr * ys) / J;
+  double* out = el.face + id * 3;
+  out[0] = krr * nr + krs * ns;
+  out[1] = krs * nr + kss * ns;
+  out[2] = cq * sqrt(xt * xt + yt * yt);
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ---------------------------------------------------------------------------------
+// (a, v) traces at the face points of a nodal state held in LDS (U, V), written to
+// tr[4][nq][2].  G: 4*n1 doubles of scratch.
+// ---------------------------------------------------------------------------------
+__device__ void face_traces(const PcgGeom& g, const double* fc, const double* U, const double* V,
+                            double* G, double* tr) {
+  const int t = threadIdx.x, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
+  if (t < 4 * n1) {       // normal-derivative line of each face
+    const int f = t / n1, l = t - (t / n1) * n1;
+    const double* dn = (f == 0 || f == 2) ? g.dR : g.dL;
+    double s = 0;
+    if (f < 2)
+      for (int i = 0; i < n1; ++i) s += dn[i] * U[l * n1 + i];
+    else
+      for (int i = 0; i < n1; ++i) s += dn[i] * U[i * n1 + l];
+    G[t] = s;
+  }
+  __syncthreads();
+  for (int id = t; id < 4 * nq; id += blockDim.x) {
+    const int f = id / nq, q = id - (id / nq) * nq;
+    const int k = q / m, a = q - (q / m) * m, s0 = g.cs[k];
+    const double* cb = g.cb + (k * m + a) * m;
+    const double* cd = g.cd + (k * m + a) * m;
+    const int node = (f == 0 || f == 2) ? N : 0;
+    double un = 0, ut = 0, vv = 0;
+    for (int j = 0; j < m; ++j) {
+      const int l = s0 + j;
+      const int fnd = (f < 2) ? l * n1 + node : node * n1 + l;
+      un += cb[j] * G[f * n1 + l];
+      ut += cd[j] * U[fnd];
+      vv += cb[j] * V[fnd];
+    }
+    const double* F = fc + id * 3;
+    const double ur = f < 2 ? un : ut, us = f < 2 ? ut : un;
+    tr[id * 2] = (F[0] * ur + F[1] * us) / F[2];
+    tr[id * 2 + 1] = vv;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_pcg_traces(PcgGeom g, PcgElem el,
+                                                     const double* __restrict__ U,
+                                                     const double* __restrict__ V,
+                                                     double* __restrict__ tr, long nel) {
+  extern __shared__ double shd[];
+  const long e = blockIdx.x;
+  const int nn = g.nn;
+  double* u = shd;
+  double* v = u + nn;
+  double* G = v + nn;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    u[i] = U[e * nn + i];
+    v[i] = V[e * nn + i];
+  }
+  __syncthreads();
+  face_traces(g, el.face + e * 4 * g.nq * 3, u, v, G, tr + e * 4 * g.nq * 2);
+}
+
+// ---------------------------------------------------------------------------------
+// PCG on one element system, every vector in LDS, thread t owns index t.
+//   A: operator upper half (LDS) or NULL for the exact Kronecker mass case;
+//   rank-1 term cw * w (w^T x) when cw != 0 (S_hat).
+// Returns the iteration count (maxit + 1 if it did not converge).
+// ---------------------------------------------------------------------------------
+struct PcgWork {
+  double *x, *r, *z, *d, *q, *tmp, *b;
+  const double* Psi;
+  const int* rowoff;
+  double* red;
+};
+
+template <typename TA>
+__device__ int pcg_solve(const PcgGeom& g, const TA* A, double cw, double wt, double dinv,
+                         PcgWork& W, double rtol, int maxit) {
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
+  const int ix = t % n1, iy = t / n1;
+  const bool own = t < nn;
+  // r = b - A x,  ||b||^2, ||r||^2
+  double wx = own ? wt * W.x[t] : 0.0, bb = own ? W.b[t] * W.b[t] : 0.0;
+  block_sum2(wx, bb, W.red);
+  if (bb == 0.0) {
+    if (own) W.x[t] = 0.0;
+    __syncthreads();
+    return 0;
+  }
+  if (own) {
+    const double ax = sym_row<TA, double, double>(A, W.rowoff, W.x, ix, iy, g.p, g.N, n1) + cw * wt * wx;
+    W.r[t] = W.b[t] - ax;
+  }
+  double rr = own ? W.r[t] * W.r[t] : 0.0, dummy = 0.0;
+  block_sum2(rr, dummy, W.red);
+  const double tol2 = rtol * rtol * bb;
+  if (rr <= tol2) return 0;
+  pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
+  if (own) W.d[t] = W.z[t];
+  double rz = own ? W.r[t] * W.z[t] : 0.0, wd = own ? wt * W.z[t] : 0.0;
+  block_sum2(rz, wd, W.red);
+  for (int it = 1; it <= maxit; ++it) {
+    double dq = 0.0;
+    if (own) {
+      const double qv = sym_row<TA, double, double>(A, W.rowoff, W.d, ix, iy, g.p, g.N, n1) + cw * wt * wd;
+      W.q[t] = qv;
+      dq = W.d[t] * qv;
+    }
+    double unused = 0.0;
+    block_sum2(dq, unused, W.red);
+    const double alpha = rz / dq;
+    double r2 = 0.0;
+    if (own) {
+      W.x[t] += alpha * W.d[t];
+      const double rv = W.r[t] - alpha * W.q[t];
+      W.r[t] = rv;
+      r2 = rv * rv;
+    }
+    block_sum2(r2, unused, W.red);
+    if (r2 <= tol2) return it;
+    pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
+    double rzn = own ? W.r[t] * W.z[t] : 0.0, wz = own ? wt * W.z[t] : 0.0;
+    block_sum2(rzn, wz, W.red);
+    const double bet = rzn / rz;
+    rz = rzn;
+    wd = wz + bet * wd;
+    if (own) W.d[t] = W.z[t] + bet * W.d[t];
+    __syncthreads();
+  }
+  return maxit + 1;
+}
+
+// ---------------------------------------------------------------------------------
+// The fused RK stage of the variable-coefficient path (FP64).
+// ---------------------------------------------------------------------------------
+size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed) {
+  (void)mixed;
+  return (size_t)g.nst * sizeof(double)             // operator
+         + (size_t)(11 * g.nn) * sizeof(double)     // U V x r z d q tmp b Fu rv
+         + (size_t)(g.nn + 1) * sizeof(int)         // rowoff
+         + (size_t)(g.nn + g.n1) * sizeof(double)   // Psi, lamr
+         + (size_t)(4 * g.nq * 4) * sizeof(double)  // traces self (2) + sigma (2)
+         + (size_t)(16 * g.n1) * sizeof(double)     // face lines
+         + 32 * sizeof(double);                     // reductions
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
+  extern __shared__ double shd[];
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
+  const long e = blockIdx.x;
+  const bool own = t < nn;
+  double* A = shd;
+  double* U = A + g.nst;
+  double* V = U + nn;
+  PcgWork W;
+  W.x = V + nn;
+  W.r = W.x + nn;
+  W.z = W.r + nn;
+  W.d = W.z + nn;
+  W.q = W.d + nn;
+  W.tmp = W.q + nn;
+  W.b = W.tmp + nn;
+  double* Fu = W.b + nn;
+  double* rv = Fu + nn;
+  double* Psi = rv + nn;
+  double* lamr = Psi + nn;
+  double* trs = lamr + n1;          // [4][nq][2] own traces, then sigma
+  double* lines = trs + 4 * nq * 2; // [4][4][n1]: cB, cD, cV, G per face
+  double* red = lines + 16 * n1;
+  int* rowoff = reinterpret_cast<int*>(red + 32);
+  W.Psi = Psi;
+  W.rowoff = rowoff;
+  W.red = red;
+
+  // ---- loads --------------------------------------------------------------------
+  const double* S = a.el.S + e * g.nst;
+  for (int i = t; i < g.nst; i += blockDim.x) A[i] = S[i];
+  for (int i = t; i <= nn; i += blockDim.x) rowoff[i] = g.rowoff[i];
+  for (int i = t; i < nn; i += blockDim.x) Psi[i] = g.Psi[i];
+  for (int i = t; i < n1; i += blockDim.x) lamr[i] = g.lamr[i];
+  double ub = 0, vb = 0, yu = 0, yv = 0, xs0 = 0, xm0 = 0, wt = 0;
+  if (own) {
+    ub = a.in_u[e * nn + t];
+    vb = a.in_v[e * nn + t];
+    if (STAGE > 1) {
+      yu = a.aux_u[e * nn + t];
+      yv = a.aux_v[e * nn + t];
+    }
+    U[t] = ub;
+    V[t] = vb;
+    xs0 = a.xS[e * nn + t];
+    xm0 = a.xM[e * nn + t];
+    wt = a.el.w[e * nn + t];
+  }
+  const double* sc = a.el.sc + e * 8;
+  const double cw = sc[0], kbr = sc[1], kbs = sc[2], d00 = sc[3], area = sc[4];
+  const double* fc = a.el.face + e * 4 * nq * 3;
+  const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
+
+  // ---- face fluxes sigma_u, sigma_v at the face points (Sec. 2.2.1) ----------------
+  for (int id = t; id < 4 * nq; id += blockDim.x) {
+    const int f = id / nq, q = id - (id / nq) * nq;
+    int nbx = ex, nby = ey, fnb;
+    if (f == 0) { nbx = ex + 1 == a.nx ? 0 : ex + 1; fnb = 1; }
+    else if (f == 1) { nbx = ex == 0 ? a.nx - 1 : ex - 1; fnb = 0; }
+    else if (f == 2) { nby = ey + 1 == a.ny ? 0 : ey + 1; fnb = 3; }
+    else { nby = ey == 0 ? a.ny - 1 : ey - 1; fnb = 2; }
+    const long enb = (long)nby * a.nx + nbx;
+    const double* ts = a.tr_in + (e * 4 * nq + id) * 2;
+    const double* tn = a.tr_in + (enb * 4 * nq + fnb * nq + q) * 2;
+    const double as = ts[0], vs = ts[1], an = tn[0], vn = tn[1];
+    const double jv = vn - vs;
+    trs[id * 2] = (1.0 - a.alpha) * jv - a.beta * (as + an);
+    trs[id * 2 + 1] = (1.0 - a.alpha) * as - a.alpha * an + a.tau * jv;
+  }
+  __syncthreads();
+  // lifts: per face and node l along the face,
+  //   cB[l] = sum_q wq sigma_u (K Nh)_normal B[q][l],  cD[l] = sum_q wq sigma_u (K Nh)_tangent D[q][l],
+  //   cV[l] = sum_q wq c^2 s_J sigma_v B[q][l]
+  if (t < 4 * n1) {
+    const int f = t / n1, l = t - (t / n1) * n1;
+    double cB = 0, cD = 0, cV = 0;
+    for (int k = g.ck0[l]; k <= g.ck1[l]; ++k) {
+      const int j = l - g.cs[k];
+      for (int qa = 0; qa < m; ++qa) {
+        const int q = k * m + qa, id = f * nq + q;
+        const double wq = g.gw[qa] / N;
+        const double* F = fc + id * 3;
+        const double kn = f < 2 ? F[0] : F[1], kt = f < 2 ? F[1] : F[0];
+        const double bj = g.cb[(k * m + qa) * m + j], dj = g.cd[(k * m + qa) * m + j];
+        cB += wq * trs[id * 2] * kn * bj;
+        cD += wq * trs[id * 2] * kt * dj;
+        cV += wq * F[2] * trs[id * 2 + 1] * bj;
+      }
+    }
+    lines[(f * 4 + 0) * n1 + l] = cB;
+    lines[(f * 4 + 1) * n1 + l] = cD;
+    lines[(f * 4 + 2) * n1 + l] = cV;
+  }
+  __syncthreads();
+  if (own) {
+    const int ix = t % n1, iy = t / n1;
+    const double* LE = lines + 0 * 4 * n1;
+    const double* LW = lines + 1 * 4 * n1;
+    const double* LN = lines + 2 * 4 * n1;
+    const double* LS = lines + 3 * 4 * n1;
+    double fu = g.dR[ix] * LE[iy] + g.dL[ix] * LW[iy] + g.dR[iy] * LN[ix] + g.dL[iy] * LS[ix];
+    double fv = 0;
+    if (ix == N) { fu += LE[n1 + iy]; fv += LE[2 * n1 + iy]; }
+    if (ix == 0) { fu += LW[n1 + iy]; fv += LW[2 * n1 + iy]; }
+    if (iy == N) { fu += LN[n1 + ix]; fv += LN[2 * n1 + ix]; }
+    if (iy == 0) { fu += LS[n1 + ix]; fv += LS[2 * n1 + ix]; }
+    Fu[t] = fu;
+    rv[t] = fv;
+  }
+  __syncthreads();
+  // r = -S_K U + F_v
+  if (own) rv[t] -= sym_row<double, double, double>(A, rowoff, U, t % n1, t / n1, g.p, N, n1);
+  // ---- S_hat y = F_u ------------------------------------------------------------------
+  double dS = 0;
+  if (own) {
+    const int kx = t % n1, ky = t / n1;
+    dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
+    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
+    W.x[t] = xs0;
+    W.b[t] = Fu[t];
+  }
+  __syncthreads();
+  const int itS = pcg_solve<double>(g, A, cw, wt, own ? 1.0 / dS : 0.0, W, a.rtol, a.maxit);
+  double y = own ? W.x[t] : 0.0;
+  __syncthreads();
+  // ---- M_J z = r --------------------------------------------------------------------
+  int itM;
+  if (a.mapped) {
+    const double* Mg = a.el.M + e * g.nst;
+    for (int i = t; i < g.nst; i += blockDim.x) A[i] = Mg[i];
+    if (own) {
+      W.x[t] = xm0;
+      W.b[t] = rv[t];
+    }
+    __syncthreads();
+    itM = pcg_solve<double>(g, A, 0.0, 0.0, own ? 1.0 / area : 0.0, W, a.rtol, a.maxit);
+  } else {
+    // Cartesian: M_J = |Omega| M_ref (x) M_ref = Psi_2^{-T} diag(|Omega|) Psi_2^{-1}, so the
+    // preconditioner is the exact inverse (one PCG iteration).
+    double bb = own ? rv[t] * rv[t] : 0.0, unused = 0.0;
+    block_sum2(bb, unused, red);
+    pinv_apply<double>(rv, W.tmp, W.x, Psi, 1.0 / area, n1, nn);
+    itM = bb > 0.0 ? 1 : 0;
+  }
+  const double z = own ? W.x[t] : 0.0;
+  __syncthreads();
+  // ---- RK stage update (as in the constant-coefficient path) ---------------------------
+  const double ku = vb + y, kv = z, dt = a.dt;
+  double nu = 0, nv = 0;
+  if (own) {
+    const long gi = e * nn + t;
+    if (STAGE == 1) {
+      nu = ub + 0.5 * dt * ku;
+      nv = vb + 0.5 * dt * kv;
+    } else if (STAGE == 2) {
+      nu = yu + 0.5 * dt * ku;
+      nv = yv + 0.5 * dt * kv;
+      a.acc_u[gi] = ub + 2.0 * nu - yu;
+      a.acc_v[gi] = vb + 2.0 * nv - yv;
+    } else if (STAGE == 3) {
+      nu = yu + dt * ku;
+      nv = yv + dt * kv;
+    } else {
+      nu = (yu + ub) * (1.0 / 3.0) + dt * (1.0 / 6.0) * ku;
+      nv = (yv + vb) * (1.0 / 3.0) + dt * (1.0 / 6.0) * kv;
+    }
+    a.out_u[gi] = nu;
+    a.out_v[gi] = nv;
+    a.xS[gi] = y;
+    a.xM[gi] = z;
+    U[t] = nu;
+    V[t] = nv;
+  }
+  __syncthreads();
+  face_traces(g, fc, U, V, lines, a.tr_out + e * 4 * nq * 2);
+  if (t == 0) {
+    int* its = a.its + e * 4;
+    its[0] += itS > a.maxit ? a.maxit : itS;
+    its[1] += itM > a.maxit ? a.maxit : itM;
+    if (itS > its[2]) its[2] = itS;
+    if (itM > its[3]) its[3] = itM;
+    if (itS > a.maxit || itM > a.maxit) atomicMin(a.fail, (int)e);
+  }
+}
+
+// Energy sum_k 1/2 V^T M_J V + 1/2 U^T S_K U, one workgroup per element (partials), then a
+// fixed-order sum.
+__global__ __launch_bounds__(1024) void k_pcg_energy(PcgGeom g, PcgElem el,
+                                                     const double* __restrict__ U,
+                                                     const double* __restrict__ V, long nel,
+                                                     double* __restrict__ part) {
+  extern __shared__ double shd[];
+  __shared__ double red[32];
+  const long e = blockIdx.x;
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
+  double* u = shd;
+  double* v = u + nn;
+  for (int i = t; i < nn; i += blockDim.x) {
+    u[i] = U[e * nn + i];
+    v[i] = V[e * nn + i];
+  }
+  __syncthreads();
+  double s = 0.0, unused = 0.0;
+  if (t < nn) {
+    const int ix = t % n1, iy = t / n1;
+    const double su = sym_row<double, double, double>(el.S + e * g.nst, g.rowoff, u, ix, iy, g.p, g.N, n1);
+    double mv;
+    if (el.M) {
+      mv = sym_row<double, double, double>(el.M + e * g.nst, g.rowoff, v, ix, iy, g.p, g.N, n1);
+    } else {
+      mv = 0.0;
+      for (int jy = 0; jy < n1; ++jy)
+        for (int jx = 0; jx < n1; ++jx) mv += g.Mref[iy * n1 + jy] * g.Mref[ix * n1 + jx] * v[jy * n1 + jx];
+      mv *= el.sc[e * 8 + 4];
+    }
+    s = u[t] * su + v[t] * mv;
+  }
+  block_sum2(s, unused, red);
+  if (t == 0) part[e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_part(const double* __restrict__ part, long n,
+                                                  double* __restrict__ out) {
+  __shared__ double red[32];
+  double s = 0.0, unused = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  block_sum2(s, unused, red);
+  if (threadIdx.x == 0) out[0] = 0.5 * s;
+}
+
+// ---------------------------------------------------------------------------------
+static int threads_for(int nn) {
+  int b = ((nn + 63) / 64) * 64;
+  return b < 256 ? 256 : b;
+}
+
+hipError_t launch_assemble(const PcgGeom& g, const double* X, const double* Y, const double* C2,
+                           const PcgElem& el, long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)nel), dim3(256), 0, st, g, X, Y, C2, el, nel);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, const double* C2,
+                            const PcgElem& el, long nel, hipStream_t st) {
+  const long n = nel * 4 * g.nq;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_geom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, X, Y, C2,
+                     el, nel);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* a, float* b, long n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
+                             double* tr, long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  const size_t sh = (2 * g.nn + 4 * g.n1) * sizeof(double);
+  hipLaunchKernelGGL(k_pcg_traces, dim3((unsigned)nel), dim3(threads_for(g.nn)), sh, st, g, el, U,
+                     V, tr, nel);
+  return hipGetLastError();
+}
+
+template <int STAGE>
+static hipError_t launch_stage_k(const PcgStageArgs& a, hipStream_t st) {
+  const size_t sh = pcg_stage_lds_bytes(a.g, a.mixed);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pcg_stage<STAGE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_pcg_stage<STAGE>, dim3((unsigned)a.nel), dim3(threads_for(a.g.nn)), sh, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st) {
+  if (a.nel == 0) return hipSuccess;
+  if (pcg_stage_lds_bytes(a.g, a.mixed) > 160 * 1024) return hipErrorInvalidValue;
+  switch (stage) {
+    case 1: return launch_stage_k<1>(a, st);
+    case 2: return launch_stage_k<2>(a, st);
+    case 3: return launch_stage_k<3>(a, st);
+    default: return launch_stage_k<4>(a, st);
+  }
+}
+
+hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
+                             long nel, double* part, int npart, double* out, hipStream_t st) {
+  (void)npart;
+  if (nel == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pcg_energy, dim3((unsigned)nel), dim3(threads_for(g.nn)),
+                     2 * g.nn * sizeof(double), st, g, el, U, V, nel, part);
+  hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(256), 0, st, part, nel, out);
+  return hipGetLastError();
+}
+
+}  // namespace gdw

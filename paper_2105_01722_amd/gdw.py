@@ -26,13 +26,16 @@ class gdw_desc(ctypes.Structure):
                 ("p", ctypes.c_int), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
                 ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("c2", ctypes.c_double),
                 ("flux", ctypes.c_int), ("xi", ctypes.c_double), ("precision", ctypes.c_int),
-                ("solver", ctypes.c_int)]
+                ("solver", ctypes.c_int), ("coeff_variable", ctypes.c_int), ("mapped", ctypes.c_int),
+                ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int)]
 
 
 class gdw_stats(ctypes.Structure):
     _fields_ = [("steps_taken", ctypes.c_longlong), ("dof_updates", ctypes.c_longlong),
                 ("n1", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
-                ("fail_elem", ctypes.c_int)]
+                ("fail_elem", ctypes.c_int), ("mean_it_S", ctypes.c_double),
+                ("mean_it_M", ctypes.c_double), ("max_it_S", ctypes.c_int), ("max_it_M", ctypes.c_int),
+                ("solves", ctypes.c_longlong)]
 
 
 class GdwError(RuntimeError):
@@ -51,6 +54,7 @@ def _load():
         "gdw_version": (ctypes.c_char_p, []),
         "gdw_last_error": (ctypes.c_char_p, []),
         "gdw_create": (I, [ctypes.POINTER(gdw_desc), ctypes.POINTER(P)]),
+        "gdw_set_coeff": (I, [P, P, P, P, P]),
         "gdw_set_state": (I, [P, P, P, P]),
         "gdw_run": (I, [P, D, I, P]),
         "gdw_get_state": (I, [P, P, P, P]),
@@ -100,6 +104,10 @@ def gdw_create(desc):
     return ctx
 
 
+def gdw_set_coeff(ctx, c2_ptr, X_ptr, Y_ptr, stream=None):
+    _check(lib.gdw_set_coeff(ctx, c2_ptr, X_ptr, Y_ptr, _stream(stream)), "gdw_set_coeff")
+
+
 def gdw_set_state(ctx, U_ptr, V_ptr, stream=None):
     _check(lib.gdw_set_state(ctx, U_ptr, V_ptr, _stream(stream)), "gdw_set_state")
 
@@ -118,10 +126,14 @@ def gdw_energy(ctx, stream=None):
     return e.value
 
 
-def gdw_get_stats(ctx, stream=None):
+def gdw_get_stats(ctx, stream=None, check=True):
     s = gdw_stats()
-    _check(lib.gdw_get_stats(ctx, ctypes.byref(s), _stream(stream)), "gdw_get_stats")
-    return {f: getattr(s, f) for f, _ in gdw_stats._fields_}
+    st = lib.gdw_get_stats(ctx, ctypes.byref(s), _stream(stream))
+    out = {f: getattr(s, f) for f, _ in gdw_stats._fields_}
+    out["status"] = st
+    if check:
+        _check(st, "gdw_get_stats")
+    return out
 
 
 def gdw_destroy(ctx):
@@ -133,7 +145,8 @@ class Solver:
     """One problem: nx x ny periodic elements, N cells, odd degree p (see include/gdw.h)."""
 
     def __init__(self, nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64",
-                 solver="auto", Lx=1.0, Ly=1.0, x0=0.0, y0=0.0):
+                 solver="auto", Lx=1.0, Ly=1.0, x0=0.0, y0=0.0, coeff_variable=False,
+                 mapped=False, pcg_rtol=1e-12, pcg_maxit=200):
         d = gdw_desc()
         d.nx, d.ny, d.N, d.p = nx, ny, N, p
         d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
@@ -142,6 +155,10 @@ class Solver:
         d.xi = xi
         d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32}[precision]
         d.solver = {"auto": GDW_SOLVE_AUTO, "fdm": GDW_SOLVE_FDM, "pcg": GDW_SOLVE_PCG}[solver]
+        d.coeff_variable = int(bool(coeff_variable))
+        d.mapped = int(bool(mapped))
+        d.pcg_rtol = pcg_rtol
+        d.pcg_maxit = pcg_maxit
         self.desc = d
         self.shape = (ny, nx, N + 1, N + 1)
         self.n = nx * ny * (N + 1) ** 2
@@ -153,6 +170,21 @@ class Solver:
         V = torch.as_tensor(V, dtype=torch.float64, device="cuda").contiguous()
         gdw_set_state(self.ctx, _dptr(U, self.n, "U"), _dptr(V, self.n, "V"), stream)
         self._keep = (U, V)  # alive until the queued copy has run
+
+    def set_coeff(self, c2=None, X=None, Y=None, stream=None):
+        """Nodal c^2 and node coordinates (None = constant c^2 / Cartesian nodes)."""
+        import torch
+        keep, ptrs = [], []
+        for name, a in (("c2", c2), ("X", X), ("Y", Y)):
+            if a is None:
+                ptrs.append(None)
+                continue
+            t = torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+            keep.append(t)
+            ptrs.append(_dptr(t, self.n, name))
+        gdw_set_coeff(self.ctx, *ptrs, stream=stream)
+        torch.cuda.current_stream().synchronize() if stream is None else None
+        self._keep_coeff = keep
 
     def run(self, dt, steps, stream=None):
         gdw_run(self.ctx, dt, steps, stream)
@@ -167,8 +199,8 @@ class Solver:
     def energy(self, stream=None):
         return gdw_energy(self.ctx, stream)
 
-    def stats(self, stream=None):
-        return gdw_get_stats(self.ctx, stream)
+    def stats(self, stream=None, check=True):
+        return gdw_get_stats(self.ctx, stream, check)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

@@ -55,6 +55,10 @@ def _desc(**kw):
     (dict(flux=gdw.GDW_FLUX_UPWIND, xi=0.0), gdw.GDW_EINVAL),
     (dict(precision=9), gdw.GDW_EINVAL),
     (dict(N=32), gdw.GDW_EINVAL),
+    (dict(solver=gdw.GDW_SOLVE_FDM, coeff_variable=1), gdw.GDW_EINVAL),
+    (dict(solver=gdw.GDW_SOLVE_FDM, mapped=1), gdw.GDW_EINVAL),
+    (dict(coeff_variable=1, N=12, p=9), gdw.GDW_EUNSUPPORTED),
+    (dict(mapped=1, pcg_rtol=float("nan")), gdw.GDW_EINVAL),
 ])
 def test_invalid_descriptors_rejected_on_host(kw, status):
     """Validation happens before any device call, so it runs without a GPU."""
