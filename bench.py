@@ -65,6 +65,62 @@ def _time_gpu(w, precision, steps, warmup):
     return ms, err, st
 
 
+def _pcg_workload(n=128, N=12, p=5, grf_seed=3, mode_seed=2):
+    """Variable c^2 = 1 + 0.5 g (g: clipped smooth periodic random field, length 0.1) on
+    the mapped mesh X = x + 0.05 s, Y = y + 0.05 s, s = sin(2 pi x) sin(2 pi y)."""
+    from paper_2105_01722_amd import inputs
+    X, Y = inputs.node_coords(n, n, N)
+    c2 = inputs.c2_field(grf_seed, X, Y)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    U0 = inputs.fourier_field(inputs.fourier_modes(mode_seed), Xm, Ym)
+    return dict(n=n, N=N, p=p, X=Xm, Y=Ym, c2=c2, U0=U0, dt=0.1 / (n * N))
+
+
+def _pcg_flops_per_step(st, nel, N, p):
+    """Algorithmic FP64 flops of one RK4 step of the PCG path: per element solve,
+    (iterations + 1) x (one full-stencil matvec + one preconditioner application),
+    plus the -S_K U product; lifts and traces are not counted."""
+    n1 = N + 1
+    w = sum(min(k + p, N) - max(k - p, 0) + 1 for k in range(n1))
+    nnz = w * w
+    pre = 4 * 2 * n1 ** 3
+    per_stage = nel * ((st["mean_it_S"] + 1) * (2 * nnz + pre) + 2 * nnz
+                       + (st["mean_it_M"] + 1) * (2 * nnz + pre))
+    return 4 * per_stage
+
+
+def _time_pcg(w, steps, warmup, rtol=1e-12):
+    import torch
+    from paper_2105_01722_amd import gdw
+    n, N, p = w["n"], w["N"], w["p"]
+    s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
+                   mapped=True, pcg_rtol=rtol)
+    s.set_coeff(w["c2"], w["X"], w["Y"])
+    U0 = torch.from_numpy(w["U0"]).cuda()
+    s.set_state(U0, torch.zeros_like(U0))
+    if warmup:
+        s.run(w["dt"], warmup)
+    torch.cuda.synchronize()
+    st0 = s.stats()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(w["dt"], steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = s.stats()
+    s.close()
+    # iteration means of the timed steps only
+    tot = st["solves"]
+    prev = st0["solves"]
+    mS = (st["mean_it_S"] * tot - st0["mean_it_S"] * prev) / (tot - prev)
+    mM = (st["mean_it_M"] * tot - st0["mean_it_M"] * prev) / (tot - prev)
+    return ms, {"mean_it_S": mS, "mean_it_M": mM, "max_it_S": st["max_it_S"],
+                "max_it_M": st["max_it_M"]}
+
+
 def _cpu_baseline(w, n_patch=32, steps=10):
     """The FP64 oracle, as it is, on a bounded sample: a 32 x 32-element periodic patch
     of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps."""
@@ -98,6 +154,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the variable-coefficient PCG workload")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="profiling aid: run only the PCG workload (prints its section only)")
+    ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (HBM counter "
                          "calibration under rocprofv3 --pmc)")
@@ -121,6 +181,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.pcg_only:
+        pw = _pcg_workload()
+        ms, its = _time_pcg(pw, max(1, args.pcg_steps), 1)
+        print(json.dumps({"pcg_ms_per_step": ms / max(1, args.pcg_steps), **its}))
+        return
     w = _workload()
     n, N = w["n"], w["N"]
     ndof = n * n * (N + 1) ** 2
@@ -156,6 +221,26 @@ def main():
         out["fp32"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                        "rel_err_vs_exact": err32,
                        "roofline_frac": 24 * 4 * ndof * args.steps / (ms32 * 1e-3) / HBM_PEAK}
+    if not args.no_pcg:
+        pw = _pcg_workload()
+        pn, pN = pw["n"], pw["N"]
+        pdof = pn * pn * (pN + 1) ** 2
+        ksteps = max(1, min(args.steps, args.pcg_steps))
+        ms, its = _time_pcg(pw, ksteps, 1)
+        print("bench: pcg fp64 %.3f ms/step" % (ms / ksteps), file=sys.stderr, flush=True)
+        flops = _pcg_flops_per_step(its, pn * pn, pN, pw["p"]) * ksteps / (ms * 1e-3)
+        out["pcg"] = {
+            "workload": "128x128 mapped elements (X = x + 0.05 sin(2 pi x) sin(2 pi y), same for Y), "
+                        "N=12, p=5, c^2 = 1 + 0.5 g (clipped smooth random field, length 0.1), upwind, "
+                        "PCG rtol 1e-12, RK4 dt = 0.1 h",
+            "dof_per_field": pdof, "steps": ksteps, "ms_per_step": ms / ksteps,
+            "value": pdof * ksteps / (ms * 1e-3), "unit": "DOF-updates/s", "dtype": "f64",
+            "mean_it_S": its["mean_it_S"], "mean_it_M": its["mean_it_M"],
+            "max_it_S": its["max_it_S"], "max_it_M": its["max_it_M"],
+            "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": 78.6,
+                         "unit": "TFLOP/s", "frac": flops / 78.6e12, "traffic": None,
+                         "kernel": "k_pcg_stage<*> (4 stage variants)"},
+        }
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(w)
         print("bench: cpu baseline done", file=sys.stderr, flush=True)

@@ -73,6 +73,8 @@ struct gdw_ctx {
   long long stages_since_state = 0;
   double rtol = 1e-12;
   int maxit = 200;
+  const int* fo = nullptr;     // full stencil row starts (device)
+  const int* dst = nullptr;    // full-rectangle destinations of the upper entries (device)
 };
 
 static void free_all(gdw_ctx* c) {
@@ -272,8 +274,14 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   const int N = d->N, p = d->p, n1 = N + 1, nn = n1 * n1, m = p + 1;
   PcgGeom& g = c->g;
   g.N = N; g.p = p; g.n1 = n1; g.nn = nn; g.m = m; g.nq = N * m;
-  std::vector<int> rowoff(nn + 1, 0), cs(N), ck0(n1, N), ck1(n1, -1);
-  for (int i = 0; i < nn; ++i) rowoff[i + 1] = rowoff[i] + st_count(i % n1, i / n1, p, N);
+  std::vector<int> rowoff(nn + 1, 0), fo(nn + 1, 0), cs(N), ck0(n1, N), ck1(n1, -1);
+  for (int i = 0; i < nn; ++i) {
+    rowoff[i + 1] = rowoff[i] + st_count(i % n1, i / n1, p, N);
+    // rows padded to an odd number of doubles: consecutive rows, read by consecutive
+    // lanes, then start in different LDS bank pairs
+    const int len = st_w(i % n1, p, N) * st_w(i / n1, p, N);
+    fo[i + 1] = fo[i] + len + (len % 2 == 0 ? 1 : 0);
+  }
   g.nst = rowoff[nn];
   for (int k = 0; k < N; ++k) {
     cs[k] = gd_window_start(k, N, p);
@@ -308,6 +316,22 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   if ((s = own_upload<double>(c, 9, Psi, &g.Psi)) != GDW_OK) return s;
   if ((s = own_upload<double>(c, 10, lam, &g.lamr)) != GDW_OK) return s;
   if ((s = own_upload<double>(c, 11, Mref, &g.Mref)) != GDW_OK) return s;
+  if ((s = own_upload<int>(c, 12, fo, &c->fo)) != GDW_OK) return s;
+  {
+    // destinations of each stored upper entry (i, j) in the full rectangles: (i, j), (j, i)
+    std::vector<int> dst((size_t)2 * g.nst);
+    for (int i = 0; i < nn; ++i) {
+      const int ix = i % n1, iy = i / n1;
+      for (int j = i; j < nn; ++j) {
+        const int jx = j % n1, jy = j / n1;
+        if (!st_in_upper(ix, iy, jx, jy, p, N)) continue;
+        const int h = rowoff[i] + st_pos(ix, iy, jx, jy, p, N);
+        dst[2 * h] = fo[i] + (jy - st_lo(iy, p)) * st_w(ix, p, N) + (jx - st_lo(ix, p));
+        dst[2 * h + 1] = fo[j] + (iy - st_lo(jy, p)) * st_w(jx, p, N) + (ix - st_lo(jx, p));
+      }
+    }
+    if ((s = own_upload<int>(c, 13, dst, &c->dst)) != GDW_OK) return s;
+  }
   if (pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
     set_error("element operator does not fit the LDS of a workgroup (reduce N or p)");
     return GDW_EUNSUPPORTED;
@@ -502,6 +526,8 @@ static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   a.rtol_inner = 1e-6;
   a.maxit = c->maxit;
   a.mixed = 0;
+  a.fo = c->fo;
+  a.dst = c->dst;
   double* y_u = (double*)c->Y[0][0];
   double* y_v = (double*)c->Y[0][1];
   double* Y_u = (double*)c->Y[1][0];

@@ -58,6 +58,9 @@ struct PcgStageArgs {
   double dt, alpha, beta, tau, rtol, rtol_inner;
   int maxit;
   int mixed;            // 1: FP32 inner PCG with FP64 residual refinement
+  const int* fo;        // [nn+1] row starts of the full stencil rectangles
+  const int* dst;       // [nst][2] full-rectangle positions (i,j), (j,i) of upper entry h
+  int full, Q, nnz_full;  // set by the launcher: LDS layout of the operator
 };
 
 hipError_t launch_assemble(const PcgGeom& g, const double* X, const double* Y, const double* C2,

@@ -29,29 +29,58 @@ namespace gdw {
 // ---------------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Wave-wide sum through DPP lane moves (no LDS traffic); every lane returns the sum.
+template <int CTRL, int ROW_MASK, bool BC>
+__device__ inline double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, BC);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, BC);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Deterministic workgroup sum of two values (fixed wave order); red: 2*16 doubles.
+__device__ inline double wave_sum(double v) {
+  v += dpp_mov<0xb1, 0xf, false>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4e, 0xf, false>(v);    // quad_perm [2,3,0,1]: quad sums
+  v += dpp_mov<0x141, 0xf, false>(v);   // row_half_mirror: 8-lane sums
+  v += dpp_mov<0x140, 0xf, false>(v);   // row_mirror: 16-lane row sums
+  v += dpp_mov<0x142, 0xa, false>(v);   // row_bcast:15 into rows 1, 3
+  v += dpp_mov<0x143, 0xc, false>(v);   // row_bcast:31 into rows 2, 3: lane 63 = total
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Deterministic workgroup sum of K values held by the threads t < nact (the other
+// threads pass zeros and may be anywhere in the workgroup); fixed wave order.
+// red: 16*K doubles.  Every thread returns the sums.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* red, int nact) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = (nact + 63) >> 6;
+  if (w < nw) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double s = wave_sum(v[k]);
+      if (lane == 0) red[k * 16 + w] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[k * 16 + i];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Deterministic workgroup sum of two values over all threads (fixed wave order).
 __device__ inline void block_sum2(double& a, double& b, double* red) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    red[w] = a;
-    red[16 + w] = b;
-  }
-  __syncthreads();
-  double sa = 0.0, sb = 0.0;
-  for (int k = 0; k < nw; ++k) {
-    sa += red[k];
-    sb += red[16 + k];
-  }
-  a = sa;
-  b = sb;
-  __syncthreads();
+  double v[2] = {a, b};
+  block_sum<2>(v, red, blockDim.x);
+  a = v[0];
+  b = v[1];
 }
 
 // Row i = (ix, iy) of a symmetric element operator stored as its upper half.
@@ -338,69 +367,116 @@ __global__ __launch_bounds__(1024) void k_pcg_traces(PcgGeom g, PcgElem el,
 }
 
 // ---------------------------------------------------------------------------------
-// PCG on one element system, every vector in LDS, thread t owns index t.
-//   A: operator upper half (LDS) or NULL for the exact Kronecker mass case;
-//   rank-1 term cw * w (w^T x) when cw != 0 (S_hat).
-// Returns the iteration count (maxit + 1 if it did not converge).
+// Element operator in LDS.  FULL: every coupled entry of a row stored as the
+// rectangle jy in [lo(iy), hi(iy)] x jx in [lo(ix), hi(ix)] (row start fo[r]); a row
+// is split over Q threads (thread part q takes jy = lo(iy) + q, + Q, ...) and the Q
+// partial sums are added in a fixed order.  HALF: the upper half as stored in HBM
+// (stencil.h), one thread per row; used when the full rectangle does not fit.
 // ---------------------------------------------------------------------------------
-struct PcgWork {
+struct PcgShared {
+  double* A;        // operator (FULL or HALF layout)
+  double* part;     // [Q][nn] partial row sums (FULL)
   double *x, *r, *z, *d, *q, *tmp, *b;
-  const double* Psi;
-  const int* rowoff;
+  double* Psi;
   double* red;
+  const int* fo;    // FULL row starts [nn+1]
+  const int* ho;    // HALF row starts [nn+1]
+  int Q;
+  int full;
 };
 
-template <typename TA>
-__device__ int pcg_solve(const PcgGeom& g, const TA* A, double cw, double wt, double dinv,
-                         PcgWork& W, double rtol, int maxit) {
+// (A x)_t for t < nn (other threads return 0).  Contains barriers; x must be complete.
+__device__ inline double op_apply(const PcgGeom& g, const PcgShared& W, const double* x) {
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1, p = g.p, N = g.N;
+  if (W.full) {
+    if (t < W.Q * nn) {
+      const int r = t % nn, qp = t / nn;
+      const int ix = r % n1, iy = r / n1;
+      const int xl = st_lo(ix, p), w = st_w(ix, p, N), yl = st_lo(iy, p), yh = st_hi(iy, p, N);
+      double acc = 0.0;
+      for (int jy = yl + qp; jy <= yh; jy += W.Q) {
+        const double* a = W.A + W.fo[r] + (jy - yl) * w;
+        const double* xx = x + jy * n1 + xl;
+        for (int k = 0; k < w; ++k) acc += a[k] * xx[k];
+      }
+      W.part[qp * nn + r] = acc;
+    }
+    __syncthreads();
+    double y = 0.0;
+    if (t < nn)
+      for (int qp = 0; qp < W.Q; ++qp) y += W.part[qp * nn + t];
+    return y;
+  }
+  return t < nn ? sym_row<double, double, double>(W.A, W.ho, x, t % n1, t / n1, p, N, n1) : 0.0;
+}
+
+// Copy one element operator from its HBM upper half into LDS.  In FULL mode entry h of
+// the upper half, (i, j), goes to both (i, j) and (j, i) of the full rectangles; the
+// two destinations come from the precomputed table dst[2h], dst[2h+1], so that the HBM
+// reads are a plain coalesced sweep.
+__device__ inline void op_load(const PcgGeom& g, const PcgShared& W, const double* __restrict__ half,
+                               const int* __restrict__ dst) {
+  const int t = threadIdx.x;
+  if (!W.full) {
+    for (int i = t; i < g.nst; i += blockDim.x) W.A[i] = half[i];
+    return;
+  }
+  for (int h = t; h < g.nst; h += blockDim.x) {
+    const double v = half[h];
+    const int2 d2 = reinterpret_cast<const int2*>(dst)[h];
+    W.A[d2.x] = v;
+    W.A[d2.y] = v;
+  }
+}
+
+// PCG on one element system; thread t owns index t.  Rank-1 term cw * w (w^T x) when
+// cw != 0 (S_hat).  Two workgroup reductions per iteration: d.q, then
+// (r.r, r.z, w.z) after the preconditioner (z is formed before the convergence test).
+// Returns the iteration count (maxit + 1 if it did not converge).
+__device__ int pcg_solve(const PcgGeom& g, const PcgShared& W, double cw, double wt, double dinv,
+                         double rtol, int maxit) {
   const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
-  const int ix = t % n1, iy = t / n1;
   const bool own = t < nn;
-  // r = b - A x,  ||b||^2, ||r||^2
-  double wx = own ? wt * W.x[t] : 0.0, bb = own ? W.b[t] * W.b[t] : 0.0;
-  block_sum2(wx, bb, W.red);
+  double s2[2] = {own ? wt * W.x[t] : 0.0, own ? W.b[t] * W.b[t] : 0.0};
+  block_sum<2>(s2, W.red, nn);
+  const double wx = s2[0], bb = s2[1];
   if (bb == 0.0) {
     if (own) W.x[t] = 0.0;
     __syncthreads();
     return 0;
   }
-  if (own) {
-    const double ax = sym_row<TA, double, double>(A, W.rowoff, W.x, ix, iy, g.p, g.N, n1) + cw * wt * wx;
-    W.r[t] = W.b[t] - ax;
+  {
+    const double ax = op_apply(g, W, W.x) + cw * wt * wx;
+    if (own) W.r[t] = W.b[t] - ax;
   }
-  double rr = own ? W.r[t] * W.r[t] : 0.0, dummy = 0.0;
-  block_sum2(rr, dummy, W.red);
-  const double tol2 = rtol * rtol * bb;
-  if (rr <= tol2) return 0;
+  __syncthreads();
   pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
+  double s3[3] = {own ? W.r[t] * W.r[t] : 0.0, own ? W.r[t] * W.z[t] : 0.0,
+                  own ? wt * W.z[t] : 0.0};
+  block_sum<3>(s3, W.red, nn);
+  const double tol2 = rtol * rtol * bb;
+  if (s3[0] <= tol2) return 0;
+  double rz = s3[1], wd = s3[2];
   if (own) W.d[t] = W.z[t];
-  double rz = own ? W.r[t] * W.z[t] : 0.0, wd = own ? wt * W.z[t] : 0.0;
-  block_sum2(rz, wd, W.red);
+  __syncthreads();
   for (int it = 1; it <= maxit; ++it) {
-    double dq = 0.0;
-    if (own) {
-      const double qv = sym_row<TA, double, double>(A, W.rowoff, W.d, ix, iy, g.p, g.N, n1) + cw * wt * wd;
-      W.q[t] = qv;
-      dq = W.d[t] * qv;
-    }
-    double unused = 0.0;
-    block_sum2(dq, unused, W.red);
-    const double alpha = rz / dq;
-    double r2 = 0.0;
+    const double qv = op_apply(g, W, W.d) + cw * wt * wd;
+    double s1[1] = {own ? W.d[t] * qv : 0.0};
+    block_sum<1>(s1, W.red, nn);
+    const double alpha = rz / s1[0];
     if (own) {
       W.x[t] += alpha * W.d[t];
-      const double rv = W.r[t] - alpha * W.q[t];
-      W.r[t] = rv;
-      r2 = rv * rv;
+      W.r[t] -= alpha * qv;
     }
-    block_sum2(r2, unused, W.red);
-    if (r2 <= tol2) return it;
+    __syncthreads();
     pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
-    double rzn = own ? W.r[t] * W.z[t] : 0.0, wz = own ? wt * W.z[t] : 0.0;
-    block_sum2(rzn, wz, W.red);
-    const double bet = rzn / rz;
-    rz = rzn;
-    wd = wz + bet * wd;
+    double s3b[3] = {own ? W.r[t] * W.r[t] : 0.0, own ? W.r[t] * W.z[t] : 0.0,
+                     own ? wt * W.z[t] : 0.0};
+    block_sum<3>(s3b, W.red, nn);
+    if (s3b[0] <= tol2) return it;
+    const double bet = s3b[1] / rz;
+    rz = s3b[1];
+    wd = s3b[2] + bet * wd;
     if (own) W.d[t] = W.z[t] + bet * W.d[t];
     __syncthreads();
   }
@@ -410,15 +486,78 @@ __device__ int pcg_solve(const PcgGeom& g, const TA* A, double cw, double wt, do
 // ---------------------------------------------------------------------------------
 // The fused RK stage of the variable-coefficient path (FP64).
 // ---------------------------------------------------------------------------------
+// size of the full-rectangle operator, rows padded to odd lengths (as the host's fo)
+static int full_nnz(const PcgGeom& g) {
+  int tot = 0;
+  for (int r = 0; r < g.nn; ++r) {
+    const int len = st_w(r % g.n1, g.p, g.N) * st_w(r / g.n1, g.p, g.N);
+    tot += len + (len % 2 == 0 ? 1 : 0);
+  }
+  return tot;
+}
+
+static int full_parts(const PcgGeom& g) {
+  int q = 1024 / g.nn;
+  if (q > 2 * g.p + 1) q = 2 * g.p + 1;
+  return q < 1 ? 1 : q;
+}
+
+static size_t stage_lds(const PcgGeom& g, int full) {
+  const size_t nd = (size_t)(full ? full_nnz(g) + full_parts(g) * g.nn : g.nst)  // A, part
+                    + 11 * g.nn + g.nn + g.n1                                    // vectors, Psi, lamr
+                    + 2 * g.N * g.m * g.m + g.m + 2 * g.n1                       // cb cd gw dL dR
+                    + 4 * g.nq * 3 + 4 * g.nq * 2 + 16 * g.n1 + 64;              // face, sigma, lines, red
+  const size_t ni = 2 * (g.nn + 1) + g.N + 2 * g.n1;                             // fo ho cs ck0 ck1
+  return nd * sizeof(double) + ni * sizeof(int);
+}
+
 size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed) {
   (void)mixed;
-  return (size_t)g.nst * sizeof(double)             // operator
-         + (size_t)(11 * g.nn) * sizeof(double)     // U V x r z d q tmp b Fu rv
-         + (size_t)(g.nn + 1) * sizeof(int)         // rowoff
-         + (size_t)(g.nn + g.n1) * sizeof(double)   // Psi, lamr
-         + (size_t)(4 * g.nq * 4) * sizeof(double)  // traces self (2) + sigma (2)
-         + (size_t)(16 * g.n1) * sizeof(double)     // face lines
-         + 32 * sizeof(double);                     // reductions
+  const size_t f = stage_lds(g, 1);
+  return f <= 160 * 1024 ? f : stage_lds(g, 0);
+}
+
+static int stage_full(const PcgGeom& g) { return stage_lds(g, 1) <= 160 * 1024 ? 1 : 0; }
+
+// (a, v) traces at the face points of a nodal state in LDS (tables in LDS).
+struct FaceTabs {
+  const double *cb, *cd, *gw, *dL, *dR, *fc;
+  const int *cs, *ck0, *ck1;
+};
+
+__device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const double* U,
+                                const double* V, double* G, double* __restrict__ tr) {
+  const int t = threadIdx.x, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
+  if (t < 4 * n1) {
+    const int f = t / n1, l = t - (t / n1) * n1;
+    const double* dn = (f == 0 || f == 2) ? T.dR : T.dL;
+    double s = 0;
+    if (f < 2)
+      for (int i = 0; i < n1; ++i) s += dn[i] * U[l * n1 + i];
+    else
+      for (int i = 0; i < n1; ++i) s += dn[i] * U[i * n1 + l];
+    G[t] = s;
+  }
+  __syncthreads();
+  for (int id = t; id < 4 * nq; id += blockDim.x) {
+    const int f = id / nq, q = id - (id / nq) * nq;
+    const int k = q / m, a = q - (q / m) * m, s0 = T.cs[k];
+    const double* cb = T.cb + (k * m + a) * m;
+    const double* cd = T.cd + (k * m + a) * m;
+    const int node = (f == 0 || f == 2) ? N : 0;
+    double un = 0, ut = 0, vv = 0;
+    for (int j = 0; j < m; ++j) {
+      const int l = s0 + j;
+      const int fnd = (f < 2) ? l * n1 + node : node * n1 + l;
+      un += cb[j] * G[f * n1 + l];
+      ut += cd[j] * U[fnd];
+      vv += cb[j] * V[fnd];
+    }
+    const double* F = T.fc + id * 3;
+    const double ur = f < 2 ? un : ut, us = f < 2 ? ut : un;
+    tr[id * 2] = (F[0] * ur + F[1] * us) / F[2];
+    tr[id * 2 + 1] = vv;
+  }
 }
 
 template <int STAGE>
@@ -428,35 +567,65 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
   const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
   const long e = blockIdx.x;
   const bool own = t < nn;
-  double* A = shd;
-  double* U = A + g.nst;
-  double* V = U + nn;
-  PcgWork W;
-  W.x = V + nn;
-  W.r = W.x + nn;
-  W.z = W.r + nn;
-  W.d = W.z + nn;
-  W.q = W.d + nn;
-  W.tmp = W.q + nn;
-  W.b = W.tmp + nn;
-  double* Fu = W.b + nn;
-  double* rv = Fu + nn;
-  double* Psi = rv + nn;
-  double* lamr = Psi + nn;
-  double* trs = lamr + n1;          // [4][nq][2] own traces, then sigma
-  double* lines = trs + 4 * nq * 2; // [4][4][n1]: cB, cD, cV, G per face
-  double* red = lines + 16 * n1;
-  int* rowoff = reinterpret_cast<int*>(red + 32);
-  W.Psi = Psi;
-  W.rowoff = rowoff;
-  W.red = red;
+  PcgShared W;
+  W.full = a.full;
+  W.Q = a.full ? a.Q : 0;
+  double* sp = shd;
+  W.A = sp;            sp += a.full ? a.nnz_full : g.nst;
+  W.part = sp;         sp += W.Q * nn;
+  double* U = sp;      sp += nn;
+  double* V = sp;      sp += nn;
+  W.x = sp;            sp += nn;
+  W.r = sp;            sp += nn;
+  W.z = sp;            sp += nn;
+  W.d = sp;            sp += nn;
+  W.q = sp;            sp += nn;
+  W.tmp = sp;          sp += nn;
+  W.b = sp;            sp += nn;
+  double* Fu = sp;     sp += nn;
+  double* rv = sp;     sp += nn;
+  W.Psi = sp;          sp += nn;
+  double* lamr = sp;   sp += n1;
+  double* cb = sp;     sp += N * m * m;
+  double* cd = sp;     sp += N * m * m;
+  double* gw = sp;     sp += m;
+  double* dL = sp;     sp += n1;
+  double* dR = sp;     sp += n1;
+  double* fc = sp;     sp += 4 * nq * 3;
+  double* sig = sp;    sp += 4 * nq * 2;
+  double* lines = sp;  sp += 16 * n1;
+  W.red = sp;          sp += 64;
+  int* ip = reinterpret_cast<int*>(sp);
+  int* fo = ip;        ip += nn + 1;
+  int* ho = ip;        ip += nn + 1;
+  int* cs = ip;        ip += N;
+  int* ck0 = ip;       ip += n1;
+  int* ck1 = ip;
+  W.fo = fo;
+  W.ho = ho;
+  FaceTabs T{cb, cd, gw, dL, dR, fc, cs, ck0, ck1};
 
-  // ---- loads --------------------------------------------------------------------
-  const double* S = a.el.S + e * g.nst;
-  for (int i = t; i < g.nst; i += blockDim.x) A[i] = S[i];
-  for (int i = t; i <= nn; i += blockDim.x) rowoff[i] = g.rowoff[i];
-  for (int i = t; i < nn; i += blockDim.x) Psi[i] = g.Psi[i];
-  for (int i = t; i < n1; i += blockDim.x) lamr[i] = g.lamr[i];
+  // ---- tables and element data into LDS ------------------------------------------
+  for (int i = t; i <= nn; i += blockDim.x) {
+    fo[i] = a.fo[i];
+    ho[i] = g.rowoff[i];
+  }
+  for (int i = t; i < nn; i += blockDim.x) W.Psi[i] = g.Psi[i];
+  for (int i = t; i < N * m * m; i += blockDim.x) {
+    cb[i] = g.cb[i];
+    cd[i] = g.cd[i];
+  }
+  for (int i = t; i < n1; i += blockDim.x) {
+    lamr[i] = g.lamr[i];
+    dL[i] = g.dL[i];
+    dR[i] = g.dR[i];
+    ck0[i] = g.ck0[i];
+    ck1[i] = g.ck1[i];
+  }
+  for (int i = t; i < m; i += blockDim.x) gw[i] = g.gw[i];
+  for (int i = t; i < N; i += blockDim.x) cs[i] = g.cs[i];
+  const double* fcg = a.el.face + e * 4 * nq * 3;
+  for (int i = t; i < 4 * nq * 3; i += blockDim.x) fc[i] = fcg[i];
   double ub = 0, vb = 0, yu = 0, yv = 0, xs0 = 0, xm0 = 0, wt = 0;
   if (own) {
     ub = a.in_u[e * nn + t];
@@ -473,8 +642,9 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
   }
   const double* sc = a.el.sc + e * 8;
   const double cw = sc[0], kbr = sc[1], kbs = sc[2], d00 = sc[3], area = sc[4];
-  const double* fc = a.el.face + e * 4 * nq * 3;
   const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
+  __syncthreads();
+  op_load(g, W, a.el.S + e * g.nst, a.dst);
 
   // ---- face fluxes sigma_u, sigma_v at the face points (Sec. 2.2.1) ----------------
   for (int id = t; id < 4 * nq; id += blockDim.x) {
@@ -489,8 +659,8 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     const double* tn = a.tr_in + (enb * 4 * nq + fnb * nq + q) * 2;
     const double as = ts[0], vs = ts[1], an = tn[0], vn = tn[1];
     const double jv = vn - vs;
-    trs[id * 2] = (1.0 - a.alpha) * jv - a.beta * (as + an);
-    trs[id * 2 + 1] = (1.0 - a.alpha) * as - a.alpha * an + a.tau * jv;
+    sig[id * 2] = (1.0 - a.alpha) * jv - a.beta * (as + an);
+    sig[id * 2 + 1] = (1.0 - a.alpha) * as - a.alpha * an + a.tau * jv;
   }
   __syncthreads();
   // lifts: per face and node l along the face,
@@ -499,17 +669,17 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
   if (t < 4 * n1) {
     const int f = t / n1, l = t - (t / n1) * n1;
     double cB = 0, cD = 0, cV = 0;
-    for (int k = g.ck0[l]; k <= g.ck1[l]; ++k) {
-      const int j = l - g.cs[k];
+    for (int k = ck0[l]; k <= ck1[l]; ++k) {
+      const int j = l - cs[k];
       for (int qa = 0; qa < m; ++qa) {
-        const int q = k * m + qa, id = f * nq + q;
-        const double wq = g.gw[qa] / N;
+        const int id = f * nq + k * m + qa;
+        const double wq = gw[qa] / N;
         const double* F = fc + id * 3;
         const double kn = f < 2 ? F[0] : F[1], kt = f < 2 ? F[1] : F[0];
-        const double bj = g.cb[(k * m + qa) * m + j], dj = g.cd[(k * m + qa) * m + j];
-        cB += wq * trs[id * 2] * kn * bj;
-        cD += wq * trs[id * 2] * kt * dj;
-        cV += wq * F[2] * trs[id * 2 + 1] * bj;
+        const double bj = cb[(k * m + qa) * m + j], dj = cd[(k * m + qa) * m + j];
+        cB += wq * sig[id * 2] * kn * bj;
+        cD += wq * sig[id * 2] * kt * dj;
+        cV += wq * F[2] * sig[id * 2 + 1] * bj;
       }
     }
     lines[(f * 4 + 0) * n1 + l] = cB;
@@ -523,7 +693,7 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     const double* LW = lines + 1 * 4 * n1;
     const double* LN = lines + 2 * 4 * n1;
     const double* LS = lines + 3 * 4 * n1;
-    double fu = g.dR[ix] * LE[iy] + g.dL[ix] * LW[iy] + g.dR[iy] * LN[ix] + g.dL[iy] * LS[ix];
+    double fu = dR[ix] * LE[iy] + dL[ix] * LW[iy] + dR[iy] * LN[ix] + dL[iy] * LS[ix];
     double fv = 0;
     if (ix == N) { fu += LE[n1 + iy]; fv += LE[2 * n1 + iy]; }
     if (ix == 0) { fu += LW[n1 + iy]; fv += LW[2 * n1 + iy]; }
@@ -532,11 +702,14 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     Fu[t] = fu;
     rv[t] = fv;
   }
-  __syncthreads();
-  // r = -S_K U + F_v
-  if (own) rv[t] -= sym_row<double, double, double>(A, rowoff, U, t % n1, t / n1, g.p, N, n1);
+  // r = -S_K U + F_v   (op_apply starts with the operator / U complete: barrier above
+  // covers U and the operator load)
+  {
+    const double su = op_apply(g, W, U);
+    if (own) rv[t] -= su;
+  }
   // ---- S_hat y = F_u ------------------------------------------------------------------
-  double dS = 0;
+  double dS = 1.0;
   if (own) {
     const int kx = t % n1, ky = t / n1;
     dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
@@ -545,35 +718,35 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     W.b[t] = Fu[t];
   }
   __syncthreads();
-  const int itS = pcg_solve<double>(g, A, cw, wt, own ? 1.0 / dS : 0.0, W, a.rtol, a.maxit);
-  double y = own ? W.x[t] : 0.0;
+  const int itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  const double y = own ? W.x[t] : 0.0;
   __syncthreads();
   // ---- M_J z = r --------------------------------------------------------------------
   int itM;
   if (a.mapped) {
-    const double* Mg = a.el.M + e * g.nst;
-    for (int i = t; i < g.nst; i += blockDim.x) A[i] = Mg[i];
+    op_load(g, W, a.el.M + e * g.nst, a.dst);
     if (own) {
       W.x[t] = xm0;
       W.b[t] = rv[t];
     }
     __syncthreads();
-    itM = pcg_solve<double>(g, A, 0.0, 0.0, own ? 1.0 / area : 0.0, W, a.rtol, a.maxit);
+    itM = pcg_solve(g, W, 0.0, 0.0, own ? 1.0 / area : 0.0, a.rtol, a.maxit);
   } else {
     // Cartesian: M_J = |Omega| M_ref (x) M_ref = Psi_2^{-T} diag(|Omega|) Psi_2^{-1}, so the
     // preconditioner is the exact inverse (one PCG iteration).
-    double bb = own ? rv[t] * rv[t] : 0.0, unused = 0.0;
-    block_sum2(bb, unused, red);
-    pinv_apply<double>(rv, W.tmp, W.x, Psi, 1.0 / area, n1, nn);
+    double bb1[1] = {own ? rv[t] * rv[t] : 0.0};
+    block_sum<1>(bb1, W.red, nn);
+    const double bb = bb1[0];
+    pinv_apply<double>(rv, W.tmp, W.x, W.Psi, 1.0 / area, n1, nn);
     itM = bb > 0.0 ? 1 : 0;
   }
   const double z = own ? W.x[t] : 0.0;
   __syncthreads();
   // ---- RK stage update (as in the constant-coefficient path) ---------------------------
   const double ku = vb + y, kv = z, dt = a.dt;
-  double nu = 0, nv = 0;
   if (own) {
     const long gi = e * nn + t;
+    double nu, nv;
     if (STAGE == 1) {
       nu = ub + 0.5 * dt * ku;
       nv = vb + 0.5 * dt * kv;
@@ -597,7 +770,7 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     V[t] = nv;
   }
   __syncthreads();
-  face_traces(g, fc, U, V, lines, a.tr_out + e * 4 * nq * 2);
+  face_traces_lds(g, T, U, V, lines, a.tr_out + e * 4 * nq * 2);
   if (t == 0) {
     int* its = a.its + e * 4;
     its[0] += itS > a.maxit ? a.maxit : itS;
@@ -691,8 +864,12 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
 }
 
 template <int STAGE>
-static hipError_t launch_stage_k(const PcgStageArgs& a, hipStream_t st) {
-  const size_t sh = pcg_stage_lds_bytes(a.g, a.mixed);
+static hipError_t launch_stage_k(const PcgStageArgs& a0, hipStream_t st) {
+  PcgStageArgs a = a0;
+  a.full = stage_full(a.g);
+  a.Q = full_parts(a.g);
+  a.nnz_full = full_nnz(a.g);
+  const size_t sh = stage_lds(a.g, a.full);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pcg_stage<STAGE>,
@@ -700,13 +877,15 @@ static hipError_t launch_stage_k(const PcgStageArgs& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_pcg_stage<STAGE>, dim3((unsigned)a.nel), dim3(threads_for(a.g.nn)), sh, st, a);
+  const int threads = a.full ? 1024 : threads_for(a.g.nn);
+  hipLaunchKernelGGL(k_pcg_stage<STAGE>, dim3((unsigned)a.nel), dim3(threads), sh, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st) {
   if (a.nel == 0) return hipSuccess;
   if (pcg_stage_lds_bytes(a.g, a.mixed) > 160 * 1024) return hipErrorInvalidValue;
+  if (a.fo == nullptr || a.dst == nullptr) return hipErrorInvalidValue;
   switch (stage) {
     case 1: return launch_stage_k<1>(a, st);
     case 2: return launch_stage_k<2>(a, st);
