@@ -154,6 +154,69 @@ gdw_status gdw_get_stats(gdw_ctx* ctx, gdw_stats* out, void* stream);
  * device first so that no queued kernel still uses the context. */
 void gdw_destroy(gdw_ctx* ctx);
 
+/* ---------------------------------------------------------------------------------
+ * Learned correction of the PCG preconditioner (an addition to the paper's method).
+ *
+ * The tensor-product preconditioner of the S_hat solve has the modal diagonal
+ * D_(ky,kx) = kbar_rr lam_kx + kbar_ss lam_ky (Sec. 3.2 eigenbasis, element averages).  A
+ * correction multiplies every entry but (0,0) by exp(o_k).  o comes either from a
+ * caller-given array or from a small network (64 -> H -> H -> (N+1)^2 - 1, ReLU) applied
+ * to the element's standardised coefficient samples ((c^2 - 1)/0.5 at the centres of an
+ * 8 x 8 subdivision of the reference square).  The network runs on the matrix cores:
+ * FP16 weights with FP32 accumulation forward, FP32 backward, Adam with FP32 master
+ * weights.  Non-finite o is replaced by 0 and |o| is clipped at 8, so the corrected
+ * preconditioner stays symmetric positive definite; a learned S_hat solve that reaches
+ * pcg_maxit is repeated with the plain preconditioner.
+ * ------------------------------------------------------------------------------- */
+typedef struct gdw_mlp gdw_mlp;
+
+/* Network with n_in inputs, two hidden layers of `hidden` units and n_out outputs; He
+ * initialisation from `seed` (std::mt19937_64, Box-Muller), zero biases.  Workspaces
+ * are sized for minibatches of up to max_batch rows.  Errors: EINVAL for non-positive
+ * sizes or NULL out. */
+gdw_status gdw_mlp_create(int n_in, int hidden, int n_out, unsigned long long seed, int max_batch,
+                          gdw_mlp** out);
+
+/* Number of parameters; flat layout W1[hidden][n_in], b1[hidden], W2[hidden][hidden],
+ * b2[hidden], W3[n_out][hidden], b3[n_out]. */
+gdw_status gdw_mlp_num_params(const gdw_mlp* mlp, long long* n);
+
+/* Copy the FP32 master parameters to / from host memory (synchronous); set also resets
+ * the Adam state. */
+gdw_status gdw_mlp_get_params(gdw_mlp* mlp, float* host);
+gdw_status gdw_mlp_set_params(gdw_mlp* mlp, const float* host);
+
+/* out[n][n_out] = network(x[n][n_in]); device FP32 arrays; any n >= 0 (chunked). */
+gdw_status gdw_mlp_forward(gdw_mlp* mlp, const float* x, int n, float* out, void* stream);
+
+/* Gradient (device FP32, flat layout) of mean((network(x) - y)^2) over one minibatch of
+ * n <= max_batch rows, and that loss in *loss_host (synchronises `stream`). */
+gdw_status gdw_mlp_grad(gdw_mlp* mlp, const float* x, const float* y, int n, float* grad,
+                        double* loss_host, void* stream);
+
+/* Adam training (lr, b1 = 0.9, b2 = 0.999, eps = 1e-8) over `epochs` passes of contiguous
+ * minibatches of `batch` rows (the last one shorter) of (x, y), device FP32 arrays.
+ * loss_host[epoch] receives the mean minibatch loss of each epoch (synchronises). */
+gdw_status gdw_mlp_train(gdw_mlp* mlp, const float* x, const float* y, int n, int epochs, int batch,
+                         float lr, double* loss_host, void* stream);
+
+void gdw_mlp_destroy(gdw_mlp* mlp);
+
+/* PCG path: training data from the assembled operators of the context (after
+ * gdw_set_coeff): samples[n_el][64] (standardised coefficient samples) and
+ * targets[n_el][(N+1)^2 - 1] = log(d_k / D_k), d = diag(Psi_2^T S_hat Psi_2) (the exact
+ * modal diagonal).  Device FP32 arrays; either may be NULL.  Errors: EINVAL on the FDM
+ * path or before gdw_set_coeff. */
+gdw_status gdw_precond_data(gdw_ctx* ctx, float* samples, float* targets, void* stream);
+
+/* PCG path: o = network(samples of every element) becomes the preconditioner correction.
+ * Errors: EINVAL if the network is not 64 -> ... -> (N+1)^2 - 1 or before gdw_set_coeff. */
+gdw_status gdw_set_precond_mlp(gdw_ctx* ctx, gdw_mlp* mlp, void* stream);
+
+/* PCG path: o given directly (device FP32 [n_el][(N+1)^2 - 1]); NULL restores the plain
+ * preconditioner. */
+gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,11 +7,13 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "fdm.h"
 #include "gdw_internal.h"
+#include "mlp.h"
 #include "pcg.h"
 #include "stencil.h"
 
@@ -75,6 +77,8 @@ struct gdw_ctx {
   int maxit = 200;
   const int* fo = nullptr;     // full stencil row starts (device)
   const int* dst = nullptr;    // full-rectangle destinations of the upper entries (device)
+  double* c2n = nullptr;       // nodal c^2 as given to set_coeff (network inputs)
+  const double* Bs = nullptr;  // [8][n1] basis values at the 8 sample centres
 };
 
 static void free_all(gdw_ctx* c) {
@@ -84,7 +88,7 @@ static void free_all(gdw_ctx* c) {
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.S32); F(c->el.M32); F(c->el.w); F(c->el.sc); F(c->el.face);
-  F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords);
+  F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
 }
 
 extern "C" const char* gdw_version(void) { return "gdw 0.1 (gfx950)"; }
@@ -318,6 +322,16 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   if ((s = own_upload<double>(c, 11, Mref, &g.Mref)) != GDW_OK) return s;
   if ((s = own_upload<int>(c, 12, fo, &c->fo)) != GDW_OK) return s;
   {
+    // basis values at the centres of an 8 x 8 subdivision (network inputs)
+    std::vector<double> Bs((size_t)8 * n1), vv(n1), dd(n1);
+    for (int sidx = 0; sidx < 8; ++sidx) {
+      const double tt = (sidx + 0.5) / 8.0 * N;
+      gd1d_eval_cell(N, p, std::min((int)tt, N - 1), tt, vv.data(), dd.data());
+      for (int i = 0; i < n1; ++i) Bs[(size_t)sidx * n1 + i] = vv[i];
+    }
+    if ((s = own_upload<double>(c, 14, Bs, &c->Bs)) != GDW_OK) return s;
+  }
+  {
     // destinations of each stored upper entry (i, j) in the full rectangles: (i, j), (j, i)
     std::vector<int> dst((size_t)2 * g.nst);
     for (int i = 0; i < nn; ++i) {
@@ -371,6 +385,7 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
           xyz[(size_t)nel * nn + k] = d->y0 + (double)(ey * N + iy) * (d->Ly / ((double)d->ny * N));
           xyz[(size_t)2 * nel * nn + k] = d->c2;
         }
+  GDW_HIP(hipMalloc(&c->c2n, (size_t)nel * nn * sizeof(double)));
   GDW_HIP(hipMalloc(&c->coords, xyz.size() * sizeof(double)));
   GDW_HIP(hipMemcpy(c->coords, xyz.data(), xyz.size() * sizeof(double), hipMemcpyHostToDevice));
   c->rtol = d->pcg_rtol > 0 ? d->pcg_rtol : 1e-12;
@@ -419,6 +434,7 @@ extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* 
   const double* Xd = X ? X : c->coords;
   const double* Yd = Y ? Y : c->coords + (size_t)c->nel * nn;
   const double* Cd = c2 ? c2 : c->coords + (size_t)2 * c->nel * nn;
+  GDW_HIP(hipMemcpyAsync(c->c2n, Cd, (size_t)c->nel * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
   GDW_HIP(launch_assemble(c->g, Xd, Yd, Cd, c->el, c->nel, st));
   GDW_HIP(launch_face_geom(c->g, Xd, Yd, Cd, c->el, c->nel, st));
   c->have_coeff = 1;
@@ -672,4 +688,240 @@ extern "C" void gdw_destroy(gdw_ctx* c) {
   (void)hipDeviceSynchronize();
   free_all(c);
   delete c;
+}
+
+// ---------------------------------------------------------------------------------
+// Learned preconditioner correction
+// ---------------------------------------------------------------------------------
+struct gdw_mlp {
+  MlpNet net{};
+  MlpWork w{};
+};
+
+static void mlp_free(gdw_mlp* m) {
+  auto F = [](void* p) { if (p) (void)hipFree(p); };
+  F(m->net.th); F(m->net.g); F(m->net.m); F(m->net.v); F(m->net.w16);
+  F(m->w.z1); F(m->w.h1); F(m->w.z2); F(m->w.h2); F(m->w.dh); F(m->w.dz); F(m->w.out);
+  F(m->w.dout); F(m->w.part); F(m->w.loss);
+}
+
+static gdw_status mlp_alloc(gdw_mlp* m, int n_in, int hidden, int n_out, int bmax) {
+  MlpNet& n = m->net;
+  n.n_in = n_in; n.hidden = hidden; n.n_out = n_out;
+  n.oW1 = 0;
+  n.ob1 = n.oW1 + (long)hidden * n_in;
+  n.oW2 = n.ob1 + hidden;
+  n.ob2 = n.oW2 + (long)hidden * hidden;
+  n.oW3 = n.ob2 + hidden;
+  n.ob3 = n.oW3 + (long)n_out * hidden;
+  n.np = n.ob3 + n_out;
+  GDW_HIP(hipMalloc(&n.th, n.np * sizeof(float)));
+  GDW_HIP(hipMalloc(&n.g, n.np * sizeof(float)));
+  GDW_HIP(hipMalloc(&n.m, n.np * sizeof(float)));
+  GDW_HIP(hipMalloc(&n.v, n.np * sizeof(float)));
+  GDW_HIP(hipMalloc(&n.w16, n.np * sizeof(_Float16)));
+  MlpWork& w = m->w;
+  w.bmax = bmax;
+  const size_t bh = (size_t)bmax * hidden * sizeof(float), bk = (size_t)bmax * n_out * sizeof(float);
+  GDW_HIP(hipMalloc(&w.z1, bh)); GDW_HIP(hipMalloc(&w.h1, bh)); GDW_HIP(hipMalloc(&w.z2, bh));
+  GDW_HIP(hipMalloc(&w.h2, bh)); GDW_HIP(hipMalloc(&w.dh, bh)); GDW_HIP(hipMalloc(&w.dz, bh));
+  GDW_HIP(hipMalloc(&w.out, bk)); GDW_HIP(hipMalloc(&w.dout, bk));
+  GDW_HIP(hipMalloc(&w.part, 64 * sizeof(double)));
+  return GDW_OK;
+}
+
+static gdw_status mlp_upload(gdw_mlp* m, const std::vector<float>& th) {
+  MlpNet& n = m->net;
+  GDW_HIP(hipMemcpy(n.th, th.data(), n.np * sizeof(float), hipMemcpyHostToDevice));
+  GDW_HIP(hipMemset(n.m, 0, n.np * sizeof(float)));
+  GDW_HIP(hipMemset(n.v, 0, n.np * sizeof(float)));
+  GDW_HIP(hipMemset(n.g, 0, n.np * sizeof(float)));
+  n.step = 0;
+  GDW_HIP(mlp_refresh_half(n, nullptr));
+  GDW_HIP(hipDeviceSynchronize());
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_create(int n_in, int hidden, int n_out, unsigned long long seed,
+                                     int max_batch, gdw_mlp** out) {
+  if (!out) { set_error("out is NULL"); return GDW_EINVAL; }
+  *out = nullptr;
+  if (n_in < 1 || hidden < 1 || n_out < 1 || max_batch < 1 || hidden > 4096 || n_in > 4096 ||
+      n_out > 4096 || max_batch > (1 << 20)) {
+    set_error("invalid network sizes"); return GDW_EINVAL;
+  }
+  gdw_mlp* m = new (std::nothrow) gdw_mlp();
+  if (!m) { set_error("host allocation failed"); return GDW_ENOMEM; }
+  gdw_status s = mlp_alloc(m, n_in, hidden, n_out, max_batch);
+  if (s == GDW_OK) {
+    std::vector<float> th(m->net.np, 0.f);
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    auto normal = [&]() {
+      const double u1 = std::max(U(rng), 1e-300), u2 = U(rng);
+      return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    auto fill = [&](long off, long cnt, int fan_in) {
+      const double sd = std::sqrt(2.0 / fan_in);
+      for (long i = 0; i < cnt; ++i) th[off + i] = (float)(sd * normal());
+    };
+    fill(m->net.oW1, (long)hidden * n_in, n_in);
+    fill(m->net.oW2, (long)hidden * hidden, hidden);
+    fill(m->net.oW3, (long)n_out * hidden, hidden);
+    s = mlp_upload(m, th);
+  }
+  if (s != GDW_OK) {
+    mlp_free(m);
+    delete m;
+    return s;
+  }
+  *out = m;
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_num_params(const gdw_mlp* m, long long* n) {
+  if (!m || !n) { set_error("NULL argument"); return GDW_EINVAL; }
+  *n = m->net.np;
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_get_params(gdw_mlp* m, float* host) {
+  if (!m || !host) { set_error("NULL argument"); return GDW_EINVAL; }
+  GDW_HIP(hipDeviceSynchronize());
+  GDW_HIP(hipMemcpy(host, m->net.th, m->net.np * sizeof(float), hipMemcpyDeviceToHost));
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_set_params(gdw_mlp* m, const float* host) {
+  if (!m || !host) { set_error("NULL argument"); return GDW_EINVAL; }
+  GDW_HIP(hipDeviceSynchronize());
+  std::vector<float> th(host, host + m->net.np);
+  return mlp_upload(m, th);
+}
+
+static gdw_status mlp_forward_all(gdw_mlp* m, const float* x, long n, float* out, hipStream_t st) {
+  const int B = m->w.bmax, I = m->net.n_in, K = m->net.n_out;
+  for (long i0 = 0; i0 < n; i0 += B) {
+    const int b = (int)std::min<long>(B, n - i0);
+    GDW_HIP(mlp_forward(m->net, x + i0 * I, b, m->w, st));
+    GDW_HIP(hipMemcpyAsync(out + i0 * K, m->w.out, (size_t)b * K * sizeof(float),
+                           hipMemcpyDeviceToDevice, st));
+  }
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_forward(gdw_mlp* m, const float* x, int n, float* out, void* stream) {
+  if (!m || n < 0 || (n > 0 && (!x || !out))) { set_error("invalid argument"); return GDW_EINVAL; }
+  return mlp_forward_all(m, x, n, out, (hipStream_t)stream);
+}
+
+extern "C" gdw_status gdw_mlp_grad(gdw_mlp* m, const float* x, const float* y, int n, float* grad,
+                                   double* loss_host, void* stream) {
+  if (!m || !x || !y || !grad || n < 1 || n > m->w.bmax) { set_error("invalid argument"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  double* acc = nullptr;
+  GDW_HIP(hipMalloc(&acc, sizeof(double)));
+  gdw_status s = GDW_OK;
+  hipError_t e = hipMemsetAsync(acc, 0, sizeof(double), st);
+  if (e == hipSuccess) e = mlp_forward(m->net, x, n, m->w, st);
+  if (e == hipSuccess) e = mlp_backward(m->net, x, y, n, m->w, acc, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grad, m->net.g, m->net.np * sizeof(float), hipMemcpyDeviceToDevice, st);
+  double loss = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&loss, acc, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(acc);
+  if (e != hipSuccess) { set_error(std::string("gdw_mlp_grad: ") + hipGetErrorString(e)); s = GDW_EHIP; }
+  if (loss_host) *loss_host = loss;
+  return s;
+}
+
+extern "C" gdw_status gdw_mlp_train(gdw_mlp* m, const float* x, const float* y, int n, int epochs,
+                                    int batch, float lr, double* loss_host, void* stream) {
+  if (!m || !x || !y || n < 1 || epochs < 0 || batch < 1 || batch > m->w.bmax || !(lr > 0)) {
+    set_error("invalid argument"); return GDW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  double* acc = nullptr;
+  GDW_HIP(hipMalloc(&acc, std::max(epochs, 1) * sizeof(double)));
+  hipError_t e = hipMemsetAsync(acc, 0, std::max(epochs, 1) * sizeof(double), st);
+  const int I = m->net.n_in, K = m->net.n_out;
+  const long nbatch = (n + batch - 1) / batch;
+  for (int ep = 0; ep < epochs && e == hipSuccess; ++ep)
+    for (long b = 0; b < nbatch && e == hipSuccess; ++b) {
+      const long i0 = b * batch;
+      const int bs = (int)std::min<long>(batch, n - i0);
+      e = mlp_forward(m->net, x + i0 * I, bs, m->w, st);
+      if (e == hipSuccess) e = mlp_backward(m->net, x + i0 * I, y + i0 * K, bs, m->w, acc + ep, st);
+      if (e == hipSuccess) e = mlp_adam(m->net, lr, st);
+    }
+  std::vector<double> h(std::max(epochs, 1));
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), acc, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(acc);
+  if (e != hipSuccess) { set_error(std::string("gdw_mlp_train: ") + hipGetErrorString(e)); return GDW_EHIP; }
+  if (loss_host)
+    for (int ep = 0; ep < epochs; ++ep) loss_host[ep] = h[ep] / (double)nbatch;
+  return GDW_OK;
+}
+
+extern "C" void gdw_mlp_destroy(gdw_mlp* m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  mlp_free(m);
+  delete m;
+}
+
+extern "C" gdw_status gdw_precond_data(gdw_ctx* c, float* samples, float* targets, void* stream) {
+  if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
+  if (c->solver != GDW_SOLVE_PCG || !c->have_coeff) {
+    set_error("gdw_precond_data needs the PCG path after gdw_set_coeff"); return GDW_EINVAL;
+  }
+  GDW_HIP(launch_precond_data(c->g, c->el, c->c2n, c->Bs, samples, targets, c->nel, (hipStream_t)stream));
+  return GDW_OK;
+}
+
+static gdw_status ensure_dlog(gdw_ctx* c) {
+  if (!c->el.dlog) GDW_HIP(hipMalloc(&c->el.dlog, (size_t)c->nel * c->g.nn * sizeof(float)));
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_set_precond_log(gdw_ctx* c, const float* log_scale, void* stream) {
+  if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
+  if (c->solver != GDW_SOLVE_PCG) { set_error("PCG path only"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  if (!log_scale) {
+    GDW_HIP(hipStreamSynchronize(st));
+    if (c->el.dlog) (void)hipFree(c->el.dlog);
+    c->el.dlog = nullptr;
+    return GDW_OK;
+  }
+  gdw_status s = ensure_dlog(c);
+  if (s != GDW_OK) return s;
+  GDW_HIP(launch_set_dlog(log_scale, c->nel, c->g.nn, c->el.dlog, st));
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_set_precond_mlp(gdw_ctx* c, gdw_mlp* m, void* stream) {
+  if (!c || !m) { set_error("NULL argument"); return GDW_EINVAL; }
+  if (c->solver != GDW_SOLVE_PCG || !c->have_coeff) {
+    set_error("gdw_set_precond_mlp needs the PCG path after gdw_set_coeff"); return GDW_EINVAL;
+  }
+  if (m->net.n_in != 64 || m->net.n_out != c->g.nn - 1) {
+    set_error("network must map 64 samples to (N+1)^2 - 1 outputs"); return GDW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  gdw_status s = ensure_dlog(c);
+  if (s != GDW_OK) return s;
+  float *smp = nullptr, *out = nullptr;
+  GDW_HIP(hipMalloc(&smp, (size_t)c->nel * 64 * sizeof(float)));
+  hipError_t e = hipMalloc(&out, (size_t)c->nel * (c->g.nn - 1) * sizeof(float));
+  if (e == hipSuccess) e = launch_precond_data(c->g, c->el, c->c2n, c->Bs, smp, nullptr, c->nel, st);
+  if (e == hipSuccess && mlp_forward_all(m, smp, c->nel, out, st) != GDW_OK) e = hipErrorUnknown;
+  if (e == hipSuccess) e = launch_set_dlog(out, c->nel, c->g.nn, c->el.dlog, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(smp);
+  if (out) (void)hipFree(out);
+  if (e != hipSuccess) { set_error(std::string("gdw_set_precond_mlp: ") + hipGetErrorString(e)); return GDW_EHIP; }
+  return GDW_OK;
 }

@@ -718,7 +718,17 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
     W.b[t] = Fu[t];
   }
   __syncthreads();
-  const int itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  int itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  if (itS > a.maxit && a.el.dlog) {
+    // the corrected preconditioner failed: repeat with the plain one from the same start
+    if (own) {
+      const int kx = t % n1, ky = t / n1;
+      dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
+      W.x[t] = xs0;
+    }
+    __syncthreads();
+    itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  }
   const double y = own ? W.x[t] : 0.0;
   __syncthreads();
   // ---- M_J z = r --------------------------------------------------------------------

@@ -61,6 +61,17 @@ def _load():
         "gdw_energy": (I, [P, ctypes.POINTER(D), P]),
         "gdw_get_stats": (I, [P, ctypes.POINTER(gdw_stats), P]),
         "gdw_destroy": (V, [P]),
+        "gdw_mlp_create": (I, [I, I, I, ctypes.c_ulonglong, I, ctypes.POINTER(P)]),
+        "gdw_mlp_num_params": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        "gdw_mlp_get_params": (I, [P, P]),
+        "gdw_mlp_set_params": (I, [P, P]),
+        "gdw_mlp_forward": (I, [P, P, I, P, P]),
+        "gdw_mlp_grad": (I, [P, P, P, I, P, ctypes.POINTER(D), P]),
+        "gdw_mlp_train": (I, [P, P, P, I, I, I, ctypes.c_float, P, P]),
+        "gdw_mlp_destroy": (V, [P]),
+        "gdw_precond_data": (I, [P, P, P, P]),
+        "gdw_set_precond_mlp": (I, [P, P, P]),
+        "gdw_set_precond_log": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -186,6 +197,31 @@ class Solver:
         torch.cuda.current_stream().synchronize() if stream is None else None
         self._keep_coeff = keep
 
+    def precond_data(self, stream=None):
+        """(samples [n_el, 64], targets [n_el, (N+1)^2 - 1]) as float32 CUDA tensors."""
+        import torch
+        nel = self.desc.nx * self.desc.ny
+        nn = (self.desc.N + 1) ** 2
+        smp = torch.empty((nel, 64), dtype=torch.float32, device="cuda")
+        tgt = torch.empty((nel, nn - 1), dtype=torch.float32, device="cuda")
+        _check(lib.gdw_precond_data(self.ctx, ctypes.c_void_p(smp.data_ptr()),
+                                    ctypes.c_void_p(tgt.data_ptr()), _stream(stream)),
+               "gdw_precond_data")
+        return smp, tgt
+
+    def set_precond_log(self, o=None, stream=None):
+        import torch
+        if o is None:
+            _check(lib.gdw_set_precond_log(self.ctx, None, _stream(stream)), "gdw_set_precond_log")
+            return
+        o = torch.as_tensor(o, dtype=torch.float32, device="cuda").contiguous()
+        _check(lib.gdw_set_precond_log(self.ctx, ctypes.c_void_p(o.data_ptr()), _stream(stream)),
+               "gdw_set_precond_log")
+        torch.cuda.current_stream().synchronize()
+
+    def set_precond_mlp(self, net, stream=None):
+        _check(lib.gdw_set_precond_mlp(self.ctx, net.h, _stream(stream)), "gdw_set_precond_mlp")
+
     def run(self, dt, steps, stream=None):
         gdw_run(self.ctx, dt, steps, stream)
 
@@ -206,6 +242,71 @@ class Solver:
         if getattr(self, "ctx", None) is not None:
             gdw_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The preconditioner-correction network (include/gdw.h, gdw_mlp_*)."""
+
+    def __init__(self, n_in=64, hidden=128, n_out=168, seed=0, max_batch=4096):
+        self.h = ctypes.c_void_p()
+        _check(lib.gdw_mlp_create(n_in, hidden, n_out, seed, max_batch, ctypes.byref(self.h)),
+               "gdw_mlp_create")
+        n = ctypes.c_longlong()
+        _check(lib.gdw_mlp_num_params(self.h, ctypes.byref(n)), "gdw_mlp_num_params")
+        self.n_in, self.hidden, self.n_out, self.np = n_in, hidden, n_out, n.value
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.np, dtype=np.float32)
+        _check(lib.gdw_mlp_get_params(self.h, a.ctypes.data_as(ctypes.c_void_p)), "gdw_mlp_get_params")
+        return a
+
+    def set_params(self, theta):
+        import numpy as np
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.np
+        _check(lib.gdw_mlp_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p)), "gdw_mlp_set_params")
+
+    def forward(self, x, stream=None):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        out = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        _check(lib.gdw_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)), "gdw_mlp_forward")
+        return out
+
+    def grad(self, x, y, stream=None):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        y = torch.as_tensor(y, dtype=torch.float32, device="cuda").contiguous()
+        g = torch.empty(self.np, dtype=torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        _check(lib.gdw_mlp_grad(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                x.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss),
+                                _stream(stream)), "gdw_mlp_grad")
+        return g, loss.value
+
+    def train(self, x, y, epochs, batch=256, lr=1e-3, stream=None):
+        import numpy as np
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        y = torch.as_tensor(y, dtype=torch.float32, device="cuda").contiguous()
+        losses = np.zeros(max(epochs, 1), dtype=np.float64)
+        _check(lib.gdw_mlp_train(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 x.shape[0], epochs, batch, ctypes.c_float(lr),
+                                 losses.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "gdw_mlp_train")
+        return losses[:epochs]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib.gdw_mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -87,3 +87,21 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+@pytest.mark.parametrize("args", [(0, 16, 8, 1, 64), (64, 0, 8, 1, 64), (64, 16, 0, 1, 64),
+                                  (64, 16, 8, 1, 0), (64, 100000, 8, 1, 64)])
+def test_mlp_create_rejects_bad_sizes(args):
+    h = ctypes.c_void_p()
+    assert gdw.lib.gdw_mlp_create(*args, ctypes.byref(h)) == gdw.GDW_EINVAL
+    assert h.value is None
+
+
+def test_mlp_and_precond_null_arguments():
+    assert gdw.lib.gdw_mlp_get_params(None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_mlp_forward(None, None, 1, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_mlp_train(None, None, None, 1, 1, 1, ctypes.c_float(1e-3), None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_precond_data(None, None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_set_precond_mlp(None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_set_coeff(None, None, None, None, None) == gdw.GDW_EINVAL
+    gdw.lib.gdw_mlp_destroy(None)
