@@ -26,6 +26,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
+# HBM bytes per launch of the FP64 stage kernel k_stage<double,*,17,4> on the workload
+# below, from rocprofv3 FETCH_SIZE / WRITE_SIZE (mean over the 4 stage variants), scaled
+# by a plain device copy's reading of the same counters (x2.0 read, x1.0 write); the
+# summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.  Set to None
+# whenever that kernel changes until the counters are taken again.
+FDM_STAGE_TRAFFIC = (302909.0 * 2.0 + 439582.25) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -121,6 +127,74 @@ def _time_pcg(w, steps, warmup, rtol=1e-12):
                 "max_it_M": st["max_it_M"]}
 
 
+def _learned_section(steps, epochs=60, n_train=20000, seed_train=5000, seed_test=6):
+    """Learned correction of the tensor-product preconditioner on the 256 x 256 Cartesian
+    variable-coefficient workload (N=12, p=5, upwind, rtol 1e-10): train on the solver's
+    own data from another coefficient field (n_train random elements), then compare PCG
+    iterations and time with the plain preconditioner and with the exact modal
+    diagonal itself (the analytic control)."""
+    import time as _t
+    import torch
+    from paper_2105_01722_amd import gdw, inputs
+    n, N, p = 256, 12, 5
+    K = (N + 1) ** 2 - 1
+    X, Y = inputs.node_coords(n, n, N)
+    # training data from the solver's own assembled operators
+    tr = gdw.Solver(n, n, N, p, flux="upwind", solver="pcg", coeff_variable=True)
+    tr.set_coeff(inputs.c2_field(seed_train, X, Y))
+    smp, tgt = tr.precond_data()
+    tr.close()
+    perm = torch.from_numpy(np.random.default_rng(7).permutation(n * n)[:n_train]).cuda()
+    xs, ys = smp[perm].contiguous(), tgt[perm].contiguous()
+    net = gdw.Mlp(64, 128, K, seed=11, max_batch=4096)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    losses = net.train(xs, ys, epochs=epochs, batch=256, lr=1e-3)
+    train_s = _t.perf_counter() - t0
+    c2 = inputs.c2_field(seed_test, X, Y)
+    U0 = torch.from_numpy(inputs.fourier_field(inputs.fourier_modes(2), X, Y)).cuda()
+    V0 = torch.zeros_like(U0)
+    dt = 0.1 / (n * N)
+    res = {}
+    ref = None
+    for mode in ("plain", "learned", "exact_diag"):
+        s = gdw.Solver(n, n, N, p, flux="upwind", solver="pcg", coeff_variable=True, pcg_rtol=1e-10)
+        s.set_coeff(c2)
+        if mode == "learned":
+            s.set_precond_mlp(net)
+        elif mode == "exact_diag":
+            _, t = s.precond_data()
+            s.set_precond_log(t)
+        s.set_state(U0, V0)
+        s.run(dt, 1)
+        torch.cuda.synchronize()
+        st0 = s.stats()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.run(dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = s.stats()
+        U, _ = s.get_state()
+        s.close()
+        Uh = U.cpu().numpy()
+        if ref is None:
+            ref = Uh
+        tot, prev = st["solves"], st0["solves"]
+        res[mode] = {"ms_per_step": ms / steps,
+                     "mean_it_S": (st["mean_it_S"] * tot - st0["mean_it_S"] * prev) / (tot - prev),
+                     "mean_it_M": (st["mean_it_M"] * tot - st0["mean_it_M"] * prev) / (tot - prev),
+                     "rel_diff_vs_plain": float(np.linalg.norm(Uh - ref) / np.linalg.norm(ref))}
+    net.close()
+    return {"workload": "256x256 Cartesian elements, N=12, p=5, c^2 = 1 + 0.5 g (clipped smooth "
+                        "random field), upwind, PCG rtol 1e-10, RK4 dt = 0.1 h",
+            "train": {"elements": n_train, "epochs": epochs, "batch": 256, "seconds": train_s,
+                      "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
+            "steps": steps, **res}
+
+
 def _cpu_baseline(w, n_patch=32, steps=10):
     """The FP64 oracle, as it is, on a bounded sample: a 32 x 32-element periodic patch
     of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps."""
@@ -155,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
     ap.add_argument("--no-pcg", action="store_true", help="skip the variable-coefficient PCG workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--pcg-only", action="store_true",
                     help="profiling aid: run only the PCG workload (prints its section only)")
     ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
@@ -210,7 +285,9 @@ def main():
                    "parallelism": "single GPU"},
         "rel_err_vs_exact": err64,
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": FDM_STAGE_TRAFFIC,
+                     "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
                      "kernel": "k_stage<double,*,17,4> (4 stage variants)",
                      "avg_launch_us": ms64 * 1e3 / launches,
                      "alg_bytes_per_launch": alg_bytes_step / 4},
@@ -241,6 +318,9 @@ def main():
                          "unit": "TFLOP/s", "frac": flops / 78.6e12, "traffic": None,
                          "kernel": "k_pcg_stage<*> (4 stage variants)"},
         }
+    if not args.no_learned:
+        out["learned"] = _learned_section(max(1, min(args.steps, 3)))
+        print("bench: learned section done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(w)
         print("bench: cpu baseline done", file=sys.stderr, flush=True)
