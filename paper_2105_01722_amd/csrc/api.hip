@@ -151,7 +151,7 @@ static gdw_status eigen_dir(int N, int p, double H, std::vector<double>& Psi,
   do {
     if ((e = hipMalloc(&dM, n1 * n1 * sizeof(double))) != hipSuccess) break;
     if ((e = hipMalloc(&dS, n1 * n1 * sizeof(double))) != hipSuccess) break;
-    if ((e = hipMalloc(&work, (3 * n1 * n1 + n1) * sizeof(double))) != hipSuccess) break;
+    if ((e = hipMalloc(&work, (3 * n1 * n1 + 5 * n1) * sizeof(double))) != hipSuccess) break;
     if ((e = hipMalloc(&dPsi, n1 * n1 * sizeof(double))) != hipSuccess) break;
     if ((e = hipMalloc(&dlam, n1 * sizeof(double))) != hipSuccess) break;
     if ((e = hipMalloc(&dinfo, (1 + n1) * sizeof(int))) != hipSuccess) break;

@@ -34,9 +34,94 @@
 namespace gdw {
 
 // ---------------------------------------------------------------------------------
+// Double-double helpers (error-free transformations: Knuth's TwoSum and the fma-based
+// TwoProduct) for the residuals of the eigenpair refinement below.
+// ---------------------------------------------------------------------------------
+struct dd { double hi, lo; };
+
+__device__ inline dd dd_two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+
+// x + a*b with a, b doubles
+__device__ inline dd dd_fma(dd x, double a, double b) {
+  const double p = a * b;
+  const double pe = fma(a, b, -p);
+  dd s = dd_two_sum(x.hi, p);
+  s.lo += x.lo + pe;
+  return dd_two_sum(s.hi, s.lo);
+}
+
+// x + a*y with y double-double
+__device__ inline dd dd_fma_dd(dd x, double a, dd y) {
+  x = dd_fma(x, a, y.hi);
+  x.lo += a * y.lo;
+  return dd_two_sum(x.hi, x.lo);
+}
+
+// One refinement sweep of the eigenpairs of S x = lambda M x (Ogita and Aishima's
+// iteration for symmetric eigenproblems, in its M-orthonormal form): with
+// R = I - X^T M X and T = X^T S X evaluated in double-double,
+// lambda_i = T_ii / (1 - R_ii), E_ii = R_ii / 2 and, for i != j,
+// E_ij = (T_ij + lambda_j R_ij) / (lambda_j - lambda_i); X <- X + X E.
+// X = Psi [n][n] (column k = eigenvector k), lam [n]; R, T [n][n] and col [4n] scratch.
+__device__ void eig_refine_sweep(const double* M, const double* S, int n, double* X, double* lam,
+                                 double* R, double* T, double* col, bool update) {
+  for (int j = 0; j < n; ++j) {
+    dd* mx = reinterpret_cast<dd*>(col);          // (M X)_{:, j}
+    dd* sx = mx + n;                              // (S X)_{:, j}
+    for (int i = 0; i < n; ++i) {
+      dd a = {0.0, 0.0}, b = {0.0, 0.0};
+      for (int k = 0; k < n; ++k) {
+        a = dd_fma(a, M[i * n + k], X[k * n + j]);
+        b = dd_fma(b, S[i * n + k], X[k * n + j]);
+      }
+      mx[i] = a;
+      sx[i] = b;
+    }
+    for (int i = 0; i < n; ++i) {
+      dd a = {0.0, 0.0}, b = {0.0, 0.0};
+      for (int k = 0; k < n; ++k) {
+        a = dd_fma_dd(a, X[k * n + i], mx[k]);
+        b = dd_fma_dd(b, X[k * n + i], sx[k]);
+      }
+      const dd r = dd_two_sum((i == j ? 1.0 : 0.0) - a.hi, -a.lo);
+      R[i * n + j] = r.hi + r.lo;
+      T[i * n + j] = b.hi + b.lo;
+    }
+  }
+  for (int i = 0; i < n; ++i) lam[i] = T[i * n + i] / (1.0 - R[i * n + i]);
+  if (!update) return;
+  double lmax = 0.0;
+  for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
+  // E overwrites T
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      const double gap = lam[j] - lam[i];
+      T[i * n + j] = (fabs(gap) > 1e-12 * lmax) ? (T[i * n + j] + lam[j] * R[i * n + j]) / gap : 0.0;
+    }
+  for (int i = 0; i < n; ++i) T[i * n + i] = 0.5 * R[i * n + i];
+  // X <- X + X E, row by row
+  for (int r = 0; r < n; ++r) {
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s = fma(X[r * n + k], T[k * n + j], s);
+      col[j] = s;
+    }
+    for (int j = 0; j < n; ++j) X[r * n + j] += col[j];
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // FP64 generalised symmetric eigensolver S psi = lambda M psi for one (N+1)^2 pencil:
-// Cholesky M = L L^T, C = L^{-1} S L^{-T}, cyclic Jacobi on C, Psi = L^{-T} Q.
-// Runs on a single lane; setup only.  work: 3 n^2 + n doubles; info: 1 + n ints.
+// Cholesky M = L L^T, C = L^{-1} S L^{-T}, cyclic Jacobi on C, Psi = L^{-T} Q, then two
+// refinement sweeps with double-double residuals, which bring the eigenbasis to FP64
+// rounding of the exact one (the FDM solve represents the element operator through
+// Psi and lambda, so their backward error is the solver's).
+// Runs on a single lane; setup only.  work: 3 n^2 + 5 n doubles; info: 1 + n ints.
 // ---------------------------------------------------------------------------------
 __global__ void k_eig_pencil(const double* __restrict__ M, const double* __restrict__ S, int n,
                              double* __restrict__ work, double* __restrict__ Psi,
@@ -138,8 +223,15 @@ __global__ void k_eig_pencil(const double* __restrict__ M, const double* __restr
       if (fabs(C[i * n + best]) > vmax * (1.0 + 1e-12)) { vmax = fabs(C[i * n + best]); imax = i; }
     const double sg = C[imax * n + best] < 0 ? -1.0 : 1.0;
     for (int i = 0; i < n; ++i) Psi[i * n + k] = sg * C[i * n + best];
-    lam[k] = (k == 0) ? 0.0 : D[best];   // the constant mode has lambda = 0 exactly
+    lam[k] = D[best];
   }
+  // refinement (L, C, Q and D are free now): R = work, T = work + n^2, col = work + 2 n^2
+  if (ok) {
+    for (int it = 0; it < 2; ++it)
+      eig_refine_sweep(M, S, n, Psi, lam, work, work + n * n, work + 2 * n * n, true);
+    eig_refine_sweep(M, S, n, Psi, lam, work, work + n * n, work + 2 * n * n, false);
+  }
+  lam[0] = 0.0;   // the constant mode has lambda = 0 exactly
   info[0] = ok;
 }
 

@@ -78,10 +78,37 @@ def grf(seed, X, Y, ell=0.1, kmax=10, clip=0.9):
     amp = rng.standard_normal(len(ks)) * np.sqrt(var)
     th = rng.uniform(0.0, 2 * np.pi, len(ks))
     Z = np.sqrt(0.5 * var.sum())
+    g = _cos_series(ks, amp, th, X, Y)
+    return np.clip(g / Z, -clip, clip)
+
+
+def _separable(X, Y):
+    """True when X, Y are [ny, nx, n1, n1] arrays with X a function of (ex, ix) only and
+    Y of (ey, iy) only (Cartesian node arrays)."""
+    X, Y = np.asarray(X), np.asarray(Y)
+    if X.ndim != 4 or X.shape != Y.shape:
+        return False
+    return (np.array_equal(X, np.broadcast_to(X[:1, :, :1, :], X.shape))
+            and np.array_equal(Y, np.broadcast_to(Y[:, :1, :, :1], Y.shape)))
+
+
+def _cos_series(ks, amp, th, X, Y):
+    """sum_k amp_k cos(2 pi (i_k X + j_k Y) + th_k).  On Cartesian node arrays the sum is
+    evaluated as one complex matrix product over the distinct x and y values."""
+    if _separable(X, Y):
+        ny, nx, n1, _ = X.shape
+        xs = X[0, :, 0, :].ravel()                       # (ex, ix)
+        ys = Y[:, 0, :, 0].ravel()                       # (ey, iy)
+        ki = np.array([k[0] for k in ks], dtype=np.float64)
+        kj = np.array([k[1] for k in ks], dtype=np.float64)
+        A = (amp * np.exp(1j * th))[None, :] * np.exp(2j * np.pi * ys[:, None] * kj[None, :])
+        B = np.exp(2j * np.pi * ki[:, None] * xs[None, :])
+        g = (A @ B).real.reshape(ny, n1, nx, n1)         # [ey, iy, ex, ix]
+        return np.ascontiguousarray(g.transpose(0, 2, 1, 3))
     g = np.zeros(np.broadcast(X, Y).shape)
     for (i, j), a, t in zip(ks, amp, th):
         g += a * np.cos(2 * np.pi * (i * X + j * Y) + t)
-    return np.clip(g / Z, -clip, clip)
+    return g
 
 
 def c2_field(seed, X, Y):
