@@ -106,11 +106,11 @@ class GenOps:
                 P = phi.reshape(m, m, m * m)
                 R = dr.reshape(m, m, m * m)
                 Sd = ds.reshape(m, m, m * m)
-                Mloc = np.einsum("ba,eba,bai,baj->eij", wq, J, P, P)
-                Sloc = (np.einsum("ba,eba,bai,baj->eij", wq, Krr, R, R)
-                        + np.einsum("ba,eba,bai,baj->eij", wq, Kss, Sd, Sd)
-                        + np.einsum("ba,eba,bai,baj->eij", wq, Krs, R, Sd)
-                        + np.einsum("ba,eba,bai,baj->eij", wq, Krs, Sd, R))
+                Mloc = np.einsum("ba,eba,bai,baj->eij", wq, J, P, P, optimize=True)
+                Sloc = (np.einsum("ba,eba,bai,baj->eij", wq, Krr, R, R, optimize=True)
+                        + np.einsum("ba,eba,bai,baj->eij", wq, Kss, Sd, Sd, optimize=True)
+                        + np.einsum("ba,eba,bai,baj->eij", wq, Krs, R, Sd, optimize=True)
+                        + np.einsum("ba,eba,bai,baj->eij", wq, Krs, Sd, R, optimize=True))
                 gidx = ((sy + np.arange(m))[:, None] * n1 + (sx + np.arange(m))[None, :]).ravel()
                 M[:, gidx[:, None], gidx[None, :]] += Mloc
                 S[:, gidx[:, None], gidx[None, :]] += Sloc
