@@ -217,6 +217,50 @@ gdw_status gdw_set_precond_mlp(gdw_ctx* ctx, gdw_mlp* mlp, void* stream);
  * preconditioner. */
 gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * Batches of independent problems (an addition for throughput on one GPU).
+ *
+ * A batch owns nprob contexts, created as by gdw_create from descs[i] (any mix of
+ * solvers, precisions, N and p).  Each RK stage of all problems runs as one grouped,
+ * persistent launch per kernel class (constant-coefficient problems grouped by
+ * precision and N+1, PCG problems by N+1), and the four stages of one step are captured
+ * once into a HIP graph that gdw_batch_run launches once per step.  Launch shapes
+ * (elements per workgroup, block size, grid size) are chosen per class by timing the
+ * candidates on the problems' own data (gdw_batch_tune).  Every problem advances exactly
+ * as gdw_run would advance it alone.
+ * --------------------------------------------------------------------------------- */
+typedef struct gdw_batch gdw_batch;
+
+/* Create the batch; 1 <= nprob <= 4096.  Errors: those of gdw_create for a problem
+ * (the message names it); nothing is left allocated on error. */
+gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_batch** out);
+
+/* Context of problem i, owned by the batch: set its coefficients and state, read its
+ * state, energy and counters with the single-problem calls.  Do not destroy it. */
+gdw_status gdw_batch_ctx(gdw_batch* batch, int i, gdw_ctx** ctx);
+
+/* Choose the launch shape of every class by timing candidates (stage 1 of the class's
+ * own problems, with scratch copies of the PCG warm starts), for the per-problem steps
+ * dt[nprob] (host array).  The problems' states are unchanged.  Synchronises `stream`.
+ * Every problem must have a state.  gdw_batch_run tunes on first use if this was not
+ * called. */
+gdw_status gdw_batch_tune(gdw_batch* batch, const double* dt, void* stream);
+
+/* Advance every problem i by `steps` RK4 steps of dt[i] (host array): one graph launch
+ * per step, asynchronous on `stream`.  The graph is rebuilt when dt changes. */
+gdw_status gdw_batch_run(gdw_batch* batch, const double* dt, int steps, void* stream);
+
+/* Durations (ms) of the n = steps steps of the last gdw_batch_run, from events recorded
+ * between the graph launches (synchronises on the last one). */
+gdw_status gdw_batch_step_times(gdw_batch* batch, float* ms, int n);
+
+/* Text: the chosen launch shape of every class and the timed candidates (empty before
+ * tuning).  Valid until the next tuning or gdw_batch_destroy. */
+const char* gdw_batch_plan(gdw_batch* batch);
+
+/* Destroy the batch and every context it owns (synchronises the device; NULL ignored). */
+void gdw_batch_destroy(gdw_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,8 +9,10 @@
 #include <new>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
+#include "ctx.h"
 #include "fdm.h"
 #include "gdw_internal.h"
 #include "mlp.h"
@@ -25,61 +27,6 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace gdw
 
 using namespace gdw;
-
-#define GDW_HIP(call)                                                                     \
-  do {                                                                                    \
-    hipError_t _e = (call);                                                               \
-    if (_e != hipSuccess) {                                                               \
-      set_error(std::string(#call) + ": " + hipGetErrorString(_e));                       \
-      return _e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;                           \
-    }                                                                                     \
-  } while (0)
-
-// "no failure" value of the PCG failure slot (hipMemset byte 0x7f); element ids are smaller
-static constexpr int kFailNone = 0x7f7f7f7f;
-
-struct gdw_ctx {
-  gdw_desc d{};
-  int n1 = 0;
-  long nel = 0;
-  size_t elem_bytes = 0;       // sizeof(T) of the time-loop arithmetic
-  double alpha = 0, beta = 0, tau = 0;
-  // device buffers (time-loop type T)
-  void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-  void* tr[2] = {nullptr, nullptr};
-  void* invL = nullptr;
-  void* lam = nullptr;
-  void* gh = nullptr;
-  // device FP64 tables for the nodal <-> modal maps
-  double* Psx = nullptr;
-  double* Psy = nullptr;
-  double* Px = nullptr;
-  double* Py = nullptr;
-  double* epart = nullptr;     // energy partial sums + result
-  unsigned int* nonfinite = nullptr;
-  int npart = 1024;
-  int trc = 0;                 // trace buffer holding the traces of y
-  long long steps_taken = 0;
-  int have_state = 0;
-  int solver = GDW_SOLVE_FDM;  // resolved solver
-  // ---- PCG path ----
-  PcgGeom g{};
-  PcgElem el{};
-  void* own[16] = {};          // device tables of g (freed with the context)
-  double* xS = nullptr;
-  double* xM = nullptr;
-  int* its = nullptr;
-  int* fail = nullptr;
-  double* coords = nullptr;    // Cartesian X, Y, constant c^2 when not given
-  int have_coeff = 0;
-  long long stages_since_state = 0;
-  double rtol = 1e-12;
-  int maxit = 200;
-  const int* fo = nullptr;     // full stencil row starts (device)
-  const int* dst = nullptr;    // full-rectangle destinations of the upper entries (device)
-  double* c2n = nullptr;       // nodal c^2 as given to set_coeff (network inputs)
-  const double* Bs = nullptr;  // [8][n1] basis values at the 8 sample centres
-};
 
 static void free_all(gdw_ctx* c) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
@@ -474,8 +421,51 @@ extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V
   return GDW_OK;
 }
 
+namespace gdw {
+
+// RK4 register roles per stage (both paths):
+//   stage 1: in = y;          out = Y;  traces t0 -> t1
+//   stage 2: in = Y, aux = y; out = Y, acc = A;  traces t1 -> t0
+//   stage 3: in = Y, aux = y; out = Y;  traces t0 -> t1
+//   stage 4: in = Y, aux = A; out = y;  traces t1 -> t0
+template <typename P>
+static void stage_roles(const gdw_ctx* c, int stage, P& a) {
+  using T = typename std::remove_const<typename std::remove_pointer<decltype(a.in_u)>::type>::type;
+  T* y_u = (T*)c->Y[0][0];
+  T* y_v = (T*)c->Y[0][1];
+  T* Y_u = (T*)c->Y[1][0];
+  T* Y_v = (T*)c->Y[1][1];
+  T* A_u = (T*)c->Y[2][0];
+  T* A_v = (T*)c->Y[2][1];
+  T* t0 = (T*)c->tr[c->trc];
+  T* t1 = (T*)c->tr[c->trc ^ 1];
+  a.aux_u = a.aux_v = nullptr;
+  a.acc_u = a.acc_v = nullptr;
+  switch (stage) {
+    case 1:
+      a.in_u = y_u; a.in_v = y_v; a.out_u = Y_u; a.out_v = Y_v;
+      a.tr_in = t0; a.tr_out = t1;
+      break;
+    case 2:
+      a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
+      a.out_u = Y_u; a.out_v = Y_v; a.acc_u = A_u; a.acc_v = A_v;
+      a.tr_in = t1; a.tr_out = t0;
+      break;
+    case 3:
+      a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
+      a.out_u = Y_u; a.out_v = Y_v;
+      a.tr_in = t0; a.tr_out = t1;
+      break;
+    default:
+      a.in_u = Y_u; a.in_v = Y_v; a.aux_u = A_u; a.aux_v = A_v;
+      a.out_u = y_u; a.out_v = y_v;
+      a.tr_in = t1; a.tr_out = t0;
+      break;
+  }
+}
+
 template <typename T>
-static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   StageArgs<T> a{};
   a.nel = c->nel;
   a.nx = c->d.nx;
@@ -489,40 +479,14 @@ static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   a.invL = (const T*)c->invL;
   a.lam = (const T*)c->lam;
   a.gh = (const T*)c->gh;
-  T* y_u = (T*)c->Y[0][0];
-  T* y_v = (T*)c->Y[0][1];
-  T* Y_u = (T*)c->Y[1][0];
-  T* Y_v = (T*)c->Y[1][1];
-  T* A_u = (T*)c->Y[2][0];
-  T* A_v = (T*)c->Y[2][1];
-  T* t0 = (T*)c->tr[c->trc];
-  T* t1 = (T*)c->tr[c->trc ^ 1];
-  hipError_t e;
-  for (int s = 0; s < steps; ++s) {
-    // stage 1: Y <- y + dt/2 L(y)
-    a.in_u = y_u; a.in_v = y_v; a.aux_u = nullptr; a.aux_v = nullptr;
-    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = nullptr; a.acc_v = nullptr;
-    a.tr_in = t0; a.tr_out = t1;
-    if ((e = launch_stage<T>(1, a, st)) != hipSuccess) return e;
-    // stage 2: Y <- y + dt/2 L(Y), A <- Yin + 2 Ynew - y
-    a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
-    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = A_u; a.acc_v = A_v;
-    a.tr_in = t1; a.tr_out = t0;
-    if ((e = launch_stage<T>(2, a, st)) != hipSuccess) return e;
-    // stage 3: Y <- y + dt L(Y)
-    a.acc_u = nullptr; a.acc_v = nullptr;
-    a.tr_in = t0; a.tr_out = t1;
-    if ((e = launch_stage<T>(3, a, st)) != hipSuccess) return e;
-    // stage 4: y <- (A + Yin)/3 + dt/6 L(Y)
-    a.aux_u = A_u; a.aux_v = A_v;
-    a.out_u = y_u; a.out_v = y_v;
-    a.tr_in = t1; a.tr_out = t0;
-    if ((e = launch_stage<T>(4, a, st)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  stage_roles(c, stage, a);
+  return a;
 }
 
-static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+template StageArgs<double> fdm_stage_args<double>(const gdw_ctx*, int, double);
+template StageArgs<float> fdm_stage_args<float>(const gdw_ctx*, int, double);
+
+PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   PcgStageArgs a{};
   a.g = c->g;
   a.el = c->el;
@@ -544,32 +508,30 @@ static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   a.mixed = 0;
   a.fo = c->fo;
   a.dst = c->dst;
-  double* y_u = (double*)c->Y[0][0];
-  double* y_v = (double*)c->Y[0][1];
-  double* Y_u = (double*)c->Y[1][0];
-  double* Y_v = (double*)c->Y[1][1];
-  double* A_u = (double*)c->Y[2][0];
-  double* A_v = (double*)c->Y[2][1];
-  double* t0 = (double*)c->tr[c->trc];
-  double* t1 = (double*)c->tr[c->trc ^ 1];
+  stage_roles(c, stage, a);
+  return a;
+}
+
+}  // namespace gdw
+
+template <typename T>
+static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+  StageArgs<T> a[4];
+  for (int k = 0; k < 4; ++k) a[k] = fdm_stage_args<T>(c, k + 1, dt);
   hipError_t e;
-  for (int s = 0; s < steps; ++s) {
-    a.in_u = y_u; a.in_v = y_v; a.aux_u = nullptr; a.aux_v = nullptr;
-    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = nullptr; a.acc_v = nullptr;
-    a.tr_in = t0; a.tr_out = t1;
-    if ((e = launch_pcg_stage(1, a, st)) != hipSuccess) return e;
-    a.in_u = Y_u; a.in_v = Y_v; a.aux_u = y_u; a.aux_v = y_v;
-    a.out_u = Y_u; a.out_v = Y_v; a.acc_u = A_u; a.acc_v = A_v;
-    a.tr_in = t1; a.tr_out = t0;
-    if ((e = launch_pcg_stage(2, a, st)) != hipSuccess) return e;
-    a.acc_u = nullptr; a.acc_v = nullptr;
-    a.tr_in = t0; a.tr_out = t1;
-    if ((e = launch_pcg_stage(3, a, st)) != hipSuccess) return e;
-    a.aux_u = A_u; a.aux_v = A_v;
-    a.out_u = y_u; a.out_v = y_v;
-    a.tr_in = t1; a.tr_out = t0;
-    if ((e = launch_pcg_stage(4, a, st)) != hipSuccess) return e;
-  }
+  for (int s = 0; s < steps; ++s)
+    for (int k = 0; k < 4; ++k)
+      if ((e = launch_stage<T>(k + 1, a[k], st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
+  PcgStageArgs a[4];
+  for (int k = 0; k < 4; ++k) a[k] = pcg_stage_args(c, k + 1, dt);
+  hipError_t e;
+  for (int s = 0; s < steps; ++s)
+    for (int k = 0; k < 4; ++k)
+      if ((e = launch_pcg_stage(k + 1, a[k], st)) != hipSuccess) return e;
   c->stages_since_state += 4LL * steps;
   return hipSuccess;
 }

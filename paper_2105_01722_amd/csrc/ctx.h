@@ -1,0 +1,81 @@
+// Context of one problem (the opaque gdw_ctx of the C ABI) and the stage-argument
+// builders shared by the single-problem time loop and the batched one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/gdw.h"
+#include "fdm.h"
+#include "gdw_internal.h"
+#include "pcg.h"
+
+#define GDW_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (call);                                                               \
+    if (_e != hipSuccess) {                                                               \
+      set_error(std::string(#call) + ": " + hipGetErrorString(_e));                       \
+      return _e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;                           \
+    }                                                                                     \
+  } while (0)
+
+// "no failure" value of the PCG failure slot (hipMemset byte 0x7f); element ids are smaller
+static constexpr int kFailNone = 0x7f7f7f7f;
+
+struct gdw_ctx {
+  gdw_desc d{};
+  int n1 = 0;
+  long nel = 0;
+  size_t elem_bytes = 0;       // sizeof(T) of the time-loop arithmetic
+  double alpha = 0, beta = 0, tau = 0;
+  // device buffers (time-loop type T)
+  void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void* tr[2] = {nullptr, nullptr};
+  void* invL = nullptr;
+  void* lam = nullptr;
+  void* gh = nullptr;
+  // device FP64 tables for the nodal <-> modal maps
+  double* Psx = nullptr;
+  double* Psy = nullptr;
+  double* Px = nullptr;
+  double* Py = nullptr;
+  double* epart = nullptr;     // energy partial sums + result
+  unsigned int* nonfinite = nullptr;
+  int npart = 1024;
+  int trc = 0;                 // trace buffer holding the traces of y
+  long long steps_taken = 0;
+  int have_state = 0;
+  int solver = GDW_SOLVE_FDM;  // resolved solver
+  // ---- PCG path ----
+  gdw::PcgGeom g{};
+  gdw::PcgElem el{};
+  void* own[16] = {};          // device tables of g (freed with the context)
+  double* xS = nullptr;
+  double* xM = nullptr;
+  int* its = nullptr;
+  int* fail = nullptr;
+  double* coords = nullptr;    // Cartesian X, Y, constant c^2 when not given
+  int have_coeff = 0;
+  long long stages_since_state = 0;
+  double rtol = 1e-12;
+  int maxit = 200;
+  const int* fo = nullptr;     // full stencil row starts (device)
+  const int* dst = nullptr;    // full-rectangle destinations of the upper entries (device)
+  double* c2n = nullptr;       // nodal c^2 as given to set_coeff (network inputs)
+  const double* Bs = nullptr;  // [8][n1] basis values at the 8 sample centres
+};
+
+
+namespace gdw {
+
+// Stage arguments of RK stage `stage` (1..4) of a constant-coefficient context (its
+// y / Y / accumulator registers and trace buffers; see fdm.hip for the roles).
+template <typename T>
+StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt);
+
+// Stage arguments of RK stage `stage` of a PCG context (full / Q / nnz_full left 0: the
+// launchers set them).
+PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt);
+
+}  // namespace gdw

@@ -45,4 +45,15 @@ hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int 
 template <typename T>
 hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStream_t st);
 
+// Grouped persistent stage launch over several problems of one class (T, n1, epb):
+// args[i] are problem i's stage arguments (device memory), problem i owns tiles
+// [tile_start[i], tile_start[i+1]) of epb elements; `grid` blocks stride over all tiles.
+template <typename T>
+hipError_t launch_stage_group(int stage, int n1, int epb, const StageArgs<T>* args,
+                              const long* tile_start, int nprob, unsigned grid, hipStream_t st);
+size_t stage_lds_bytes(int elem_bytes, int n1, int epb);
+// Resident blocks per CU of the grouped stage kernel (LDS and thread limits).
+template <typename T>
+int stage_group_occupancy(int stage, int n1, int epb);
+
 }  // namespace gdw

@@ -359,8 +359,9 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 // ky) sit in registers for the whole kernel, and the element loop is uniform across
 // the workgroup: state addresses are a scalar element base plus the thread's fixed
 // offset.
+// One tile (EPB consecutive elements, tile index `tile`) of one problem.
 template <typename T, int STAGE, int N1C, int EPB>
-__global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
+__device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   const int n1 = N1C > 0 ? N1C : a.n1;
   const int nn = n1 * n1;
   const int tid = threadIdx.x;                   // blockDim.x == nn
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
   T* sgh = reinterpret_cast<T*>(smem_raw);       // [8][n1] face tables
   T* sig = sgh + 8 * n1;                         // [EPB][8][n1] modal face fluxes
   T* snew = sig + EPB * 8 * n1;                  // [EPB][2][nn] new stage values
-  const long e0 = (long)blockIdx.x * EPB;
+  const long e0 = tile * EPB;
   const int ne = (int)min((long)EPB, a.nel - e0);
 
   // Issue the state loads of all EPB elements first, so that their HBM latency
@@ -467,6 +468,28 @@ __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
     const T* gg = sgh + f2 * n1;
     a.tr_out[e0 * 8 * n1 + i] =
         (f2 < 4) ? dot_row<T, N1C>(gg, F, j, n1) : dot_col<T, N1C>(gg, F, j, n1);
+  }
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+__global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
+  stage_tile<T, STAGE, N1C, EPB>(a, blockIdx.x);
+}
+
+// Grouped, persistent form: the tiles of several problems of one class (same T, N+1,
+// EPB) in one launch.  Problem i owns tiles [tile_start[i], tile_start[i+1]); block b
+// takes tiles b, b + gridDim.x, ... in increasing order, so its problem index only
+// moves forward.  Every tile of every problem is independent within a stage.
+template <typename T, int STAGE, int N1C, int EPB>
+__global__ __launch_bounds__(1024) void k_stage_group(const StageArgs<T>* __restrict__ args,
+                                                      const long* __restrict__ tile_start,
+                                                      int nprob) {
+  const long total = tile_start[nprob];
+  int pi = 0;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    while (pi + 1 < nprob && b >= tile_start[pi + 1]) ++pi;
+    stage_tile<T, STAGE, N1C, EPB>(args[pi], b - tile_start[pi]);
+    __syncthreads();   // the next tile reuses the LDS
   }
 }
 
@@ -602,6 +625,66 @@ hipError_t launch_stage(int stage, const StageArgs<T>& a, hipStream_t st) {
   }
 }
 
+size_t stage_lds_bytes(int elem_bytes, int n1, int epb) {
+  return (size_t)(8 * n1 + epb * 8 * n1 + epb * 2 * n1 * n1) * elem_bytes;
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+static hipError_t launch_group_t(const StageArgs<T>* args, const long* tile_start, int nprob,
+                                 int n1, unsigned grid, hipStream_t st) {
+  const size_t sh = stage_lds_bytes(sizeof(T), n1, EPB);
+  hipLaunchKernelGGL((k_stage_group<T, STAGE, N1C, EPB>), dim3(grid), dim3(n1 * n1), sh, st, args,
+                     tile_start, nprob);
+  return hipGetLastError();
+}
+
+template <typename T, int STAGE, int N1C>
+static hipError_t group_epb(int epb, const StageArgs<T>* args, const long* ts, int np, int n1,
+                            unsigned grid, hipStream_t st) {
+  switch (epb) {
+    case 1: return launch_group_t<T, STAGE, N1C, 1>(args, ts, np, n1, grid, st);
+    case 2: return launch_group_t<T, STAGE, N1C, 2>(args, ts, np, n1, grid, st);
+    case 4: return launch_group_t<T, STAGE, N1C, 4>(args, ts, np, n1, grid, st);
+    case 8: return launch_group_t<T, STAGE, N1C, 8>(args, ts, np, n1, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int STAGE>
+static hipError_t group_n1(int epb, const StageArgs<T>* args, const long* ts, int np, int n1,
+                           unsigned grid, hipStream_t st) {
+  switch (n1) {
+    case 9: return group_epb<T, STAGE, 9>(epb, args, ts, np, n1, grid, st);
+    case 13: return group_epb<T, STAGE, 13>(epb, args, ts, np, n1, grid, st);
+    case 17: return group_epb<T, STAGE, 17>(epb, args, ts, np, n1, grid, st);
+    default: return group_epb<T, STAGE, 0>(epb, args, ts, np, n1, grid, st);
+  }
+}
+
+template <typename T>
+hipError_t launch_stage_group(int stage, int n1, int epb, const StageArgs<T>* args,
+                              const long* tile_start, int nprob, unsigned grid, hipStream_t st) {
+  if (nprob <= 0 || grid == 0) return hipSuccess;
+  if (n1 * n1 > 1024 || stage_lds_bytes(sizeof(T), n1, epb) > 65536) return hipErrorInvalidValue;
+  switch (stage) {
+    case 1: return group_n1<T, 1>(epb, args, tile_start, nprob, n1, grid, st);
+    case 2: return group_n1<T, 2>(epb, args, tile_start, nprob, n1, grid, st);
+    case 3: return group_n1<T, 3>(epb, args, tile_start, nprob, n1, grid, st);
+    default: return group_n1<T, 4>(epb, args, tile_start, nprob, n1, grid, st);
+  }
+}
+
+template <typename T>
+int stage_group_occupancy(int stage, int n1, int epb) {
+  (void)stage;
+  // blocks per CU allowed by LDS (64 KiB per block at most, 160 KiB per CU) and threads
+  const size_t lds = stage_lds_bytes(sizeof(T), n1, epb);
+  int by_lds = (int)((160 * 1024) / (lds ? lds : 1));
+  int by_thr = 2048 / (((n1 * n1 + 63) / 64) * 64);
+  int b = by_lds < by_thr ? by_lds : by_thr;
+  return b < 1 ? 1 : b;
+}
+
 template <typename T>
 hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int n1, long nel,
                          double* part, int npart, double* out, hipStream_t st) {
@@ -630,7 +713,10 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
   template hipError_t launch_stage<T>(int, const StageArgs<T>&, hipStream_t);                    \
   template hipError_t launch_energy<T>(const T*, const T*, const T*, double, int, long, double*,  \
                                        int, double*, hipStream_t);                               \
-  template hipError_t launch_count_nonfinite<T>(const T*, long, unsigned int*, hipStream_t);
+  template hipError_t launch_count_nonfinite<T>(const T*, long, unsigned int*, hipStream_t);       \
+  template hipError_t launch_stage_group<T>(int, int, int, const StageArgs<T>*, const long*, int, \
+                                            unsigned, hipStream_t);                              \
+  template int stage_group_occupancy<T>(int, int, int);
 
 GDW_INST(double)
 GDW_INST(float)

@@ -72,6 +72,15 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
                              double* tr, long nel, hipStream_t st);
 hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st);
 size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);
+// LDS layout of the stage kernel for a block of `threads` threads: full-rectangle operator
+// or not, row split Q, full operator size and LDS bytes.
+void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_full, size_t* lds);
+// Grouped persistent stage launch over several problems (args in device memory; every
+// args[i].full / Q / nnz_full set for `threads`; lds >= every member's need).
+hipError_t launch_pcg_stage_group(int stage, const PcgStageArgs* args, const long* el_start,
+                                  int nprob, unsigned grid, int threads, size_t lds, hipStream_t st);
+// Allow the grouped stage kernels their full LDS (call before any graph capture).
+hipError_t pcg_group_prepare();
 hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
                              long nel, double* part, int npart, double* out, hipStream_t st);
 

@@ -561,11 +561,10 @@ __device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const doubl
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
+__device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long e) {
   extern __shared__ double shd[];
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
-  const long e = blockIdx.x;
   const bool own = t < nn;
   PcgShared W;
   W.full = a.full;
@@ -791,6 +790,27 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
   }
 }
 
+template <int STAGE>
+__global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
+  pcg_stage_elem<STAGE>(a, blockIdx.x);
+}
+
+// Grouped, persistent form over the elements of several problems (each with its own
+// geometry and LDS layout, all fitting the launch's LDS size and block size).  Problem i
+// owns elements [el_start[i], el_start[i+1]); block b takes b, b + gridDim.x, ...
+template <int STAGE>
+__global__ __launch_bounds__(1024) void k_pcg_stage_group(const PcgStageArgs* __restrict__ args,
+                                                          const long* __restrict__ el_start,
+                                                          int nprob) {
+  const long total = el_start[nprob];
+  int pi = 0;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    while (pi + 1 < nprob && b >= el_start[pi + 1]) ++pi;
+    pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+    __syncthreads();   // the next element reuses the LDS
+  }
+}
+
 // Energy sum_k 1/2 V^T M_J V + 1/2 U^T S_K U, one workgroup per element (partials), then a
 // fixed-order sum.
 __global__ __launch_bounds__(1024) void k_pcg_energy(PcgGeom g, PcgElem el,
@@ -890,6 +910,57 @@ static hipError_t launch_stage_k(const PcgStageArgs& a0, hipStream_t st) {
   const int threads = a.full ? 1024 : threads_for(a.g.nn);
   hipLaunchKernelGGL(k_pcg_stage<STAGE>, dim3((unsigned)a.nel), dim3(threads), sh, st, a);
   return hipGetLastError();
+}
+
+void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_full, size_t* lds) {
+  *full = stage_full(g);
+  *nnz_full = full_nnz(g);
+  int q = full_parts(g);
+  if (*full) {
+    const int qt = threads / g.nn;
+    if (q > qt) q = qt;
+    if (q < 1) q = 1;
+  }
+  *Q = q;
+  *lds = stage_lds(g, *full);
+}
+
+template <int STAGE>
+static hipError_t launch_group_k(const PcgStageArgs* args, const long* el_start, int nprob,
+                                 unsigned grid, int threads, size_t lds, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pcg_stage_group<STAGE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_pcg_stage_group<STAGE>, dim3(grid), dim3(threads), lds, st, args, el_start,
+                     nprob);
+  return hipGetLastError();
+}
+
+hipError_t pcg_group_prepare() {
+  hipError_t e;
+  const void* k[4] = {(const void*)k_pcg_stage_group<1>, (const void*)k_pcg_stage_group<2>,
+                      (const void*)k_pcg_stage_group<3>, (const void*)k_pcg_stage_group<4>};
+  for (int i = 0; i < 4; ++i)
+    if ((e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) !=
+        hipSuccess)
+      return e;
+  return hipSuccess;
+}
+
+hipError_t launch_pcg_stage_group(int stage, const PcgStageArgs* args, const long* el_start,
+                                  int nprob, unsigned grid, int threads, size_t lds, hipStream_t st) {
+  if (nprob <= 0 || grid == 0) return hipSuccess;
+  if (lds > 160 * 1024 || threads > 1024 || threads < 64) return hipErrorInvalidValue;
+  switch (stage) {
+    case 1: return launch_group_k<1>(args, el_start, nprob, grid, threads, lds, st);
+    case 2: return launch_group_k<2>(args, el_start, nprob, grid, threads, lds, st);
+    case 3: return launch_group_k<3>(args, el_start, nprob, grid, threads, lds, st);
+    default: return launch_group_k<4>(args, el_start, nprob, grid, threads, lds, st);
+  }
 }
 
 hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st) {

@@ -72,6 +72,13 @@ def _load():
         "gdw_precond_data": (I, [P, P, P, P]),
         "gdw_set_precond_mlp": (I, [P, P, P]),
         "gdw_set_precond_log": (I, [P, P, P]),
+        "gdw_batch_create": (I, [I, ctypes.POINTER(gdw_desc), ctypes.POINTER(P)]),
+        "gdw_batch_ctx": (I, [P, I, ctypes.POINTER(P)]),
+        "gdw_batch_tune": (I, [P, ctypes.POINTER(D), P]),
+        "gdw_batch_run": (I, [P, ctypes.POINTER(D), I, P]),
+        "gdw_batch_step_times": (I, [P, ctypes.POINTER(ctypes.c_float), I]),
+        "gdw_batch_plan": (ctypes.c_char_p, [P]),
+        "gdw_batch_destroy": (V, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -152,28 +159,44 @@ def gdw_destroy(ctx):
 
 
 # --- convenience wrapper -----------------------------------------------------------------
+def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", solver="auto",
+              Lx=1.0, Ly=1.0, x0=0.0, y0=0.0, coeff_variable=False, mapped=False,
+              pcg_rtol=1e-12, pcg_maxit=200):
+    """A gdw_desc from keyword arguments (names as in include/gdw.h)."""
+    d = gdw_desc()
+    d.nx, d.ny, d.N, d.p = nx, ny, N, p
+    d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
+    d.c2 = c2
+    d.flux = {"central": GDW_FLUX_CENTRAL, "upwind": GDW_FLUX_UPWIND}[flux]
+    d.xi = xi
+    d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32}[precision]
+    d.solver = {"auto": GDW_SOLVE_AUTO, "fdm": GDW_SOLVE_FDM, "pcg": GDW_SOLVE_PCG}[solver]
+    d.coeff_variable = int(bool(coeff_variable))
+    d.mapped = int(bool(mapped))
+    d.pcg_rtol = pcg_rtol
+    d.pcg_maxit = pcg_maxit
+    return d
+
+
 class Solver:
     """One problem: nx x ny periodic elements, N cells, odd degree p (see include/gdw.h)."""
 
-    def __init__(self, nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64",
-                 solver="auto", Lx=1.0, Ly=1.0, x0=0.0, y0=0.0, coeff_variable=False,
-                 mapped=False, pcg_rtol=1e-12, pcg_maxit=200):
-        d = gdw_desc()
-        d.nx, d.ny, d.N, d.p = nx, ny, N, p
-        d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
-        d.c2 = c2
-        d.flux = {"central": GDW_FLUX_CENTRAL, "upwind": GDW_FLUX_UPWIND}[flux]
-        d.xi = xi
-        d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32}[precision]
-        d.solver = {"auto": GDW_SOLVE_AUTO, "fdm": GDW_SOLVE_FDM, "pcg": GDW_SOLVE_PCG}[solver]
-        d.coeff_variable = int(bool(coeff_variable))
-        d.mapped = int(bool(mapped))
-        d.pcg_rtol = pcg_rtol
-        d.pcg_maxit = pcg_maxit
+    def __init__(self, nx, ny, N, p, **kw):
+        self._attach(make_desc(nx, ny, N, p, **kw), None)
+
+    def _attach(self, d, ctx):
         self.desc = d
-        self.shape = (ny, nx, N + 1, N + 1)
-        self.n = nx * ny * (N + 1) ** 2
-        self.ctx = gdw_create(d)
+        self.shape = (d.ny, d.nx, d.N + 1, d.N + 1)
+        self.n = d.nx * d.ny * (d.N + 1) ** 2
+        self._owned = ctx is None
+        self.ctx = gdw_create(d) if ctx is None else ctx
+
+    @classmethod
+    def view(cls, desc, ctx):
+        """A Solver on a context owned elsewhere (a batch member); close() does not free it."""
+        s = cls.__new__(cls)
+        s._attach(desc, ctx)
+        return s
 
     def set_state(self, U, V, stream=None):
         import torch
@@ -240,7 +263,8 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
-            gdw_destroy(self.ctx)
+            if self._owned:
+                gdw_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):
@@ -306,6 +330,61 @@ class Mlp:
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:
             lib.gdw_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems advanced together (include/gdw.h, gdw_batch_*).
+
+    problems: list of keyword dicts for make_desc (each with nx, ny, N, p, ...).
+    `self.problems[i]` is a Solver view of problem i (set_coeff / set_state / get_state /
+    energy / stats work on it as on a single problem)."""
+
+    def __init__(self, problems):
+        n = len(problems)
+        descs = (gdw_desc * n)(*[make_desc(**p) for p in problems])
+        self.h = ctypes.c_void_p()
+        _check(lib.gdw_batch_create(n, descs, ctypes.byref(self.h)), "gdw_batch_create")
+        self.problems = []
+        for i in range(n):
+            c = ctypes.c_void_p()
+            _check(lib.gdw_batch_ctx(self.h, i, ctypes.byref(c)), "gdw_batch_ctx")
+            self.problems.append(Solver.view(descs[i], c))
+        self._steps = 0
+
+    @staticmethod
+    def _dt(dt, n):
+        arr = (ctypes.c_double * n)(*[float(x) for x in dt])
+        return arr
+
+    def tune(self, dt, stream=None):
+        _check(lib.gdw_batch_tune(self.h, self._dt(dt, len(self.problems)), _stream(stream)),
+               "gdw_batch_tune")
+
+    def run(self, dt, steps, stream=None):
+        _check(lib.gdw_batch_run(self.h, self._dt(dt, len(self.problems)), int(steps),
+                                 _stream(stream)), "gdw_batch_run")
+        self._steps = int(steps)
+
+    def step_times(self):
+        ms = (ctypes.c_float * max(1, self._steps))()
+        _check(lib.gdw_batch_step_times(self.h, ms, self._steps), "gdw_batch_step_times")
+        return [ms[i] for i in range(self._steps)]
+
+    def plan(self):
+        return lib.gdw_batch_plan(self.h).decode()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            for p in self.problems:
+                p.ctx = None
+            lib.gdw_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -105,3 +105,19 @@ def test_mlp_and_precond_null_arguments():
     assert gdw.lib.gdw_set_precond_mlp(None, None, None) == gdw.GDW_EINVAL
     assert gdw.lib.gdw_set_coeff(None, None, None, None, None) == gdw.GDW_EINVAL
     gdw.lib.gdw_mlp_destroy(None)
+
+
+def test_batch_arguments_rejected_on_host():
+    import ctypes
+    from paper_2105_01722_amd import gdw
+    h = ctypes.c_void_p()
+    d = (gdw.gdw_desc * 1)(gdw.make_desc(2, 2, 8, 3))
+    assert gdw.lib.gdw_batch_create(0, d, ctypes.byref(h)) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_create(5000, d, ctypes.byref(h)) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_create(1, None, ctypes.byref(h)) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_ctx(None, 0, ctypes.byref(h)) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_run(None, None, 1, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_tune(None, None, None) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_step_times(None, None, 0) == gdw.GDW_EINVAL
+    assert gdw.lib.gdw_batch_plan(None) == b""
+    gdw.lib.gdw_batch_destroy(None)
