@@ -195,6 +195,93 @@ def _learned_section(steps, epochs=60, n_train=20000, seed_train=5000, seed_test
             "steps": steps, **res}
 
 
+# Time steps of the batched workload, as fractions of the cell width: about two thirds
+# of the largest RK4-stable value measured on the dense spectrum (upwind; Cartesian
+# constant c and the mapped variable-c^2 mesh respectively).
+BATCH_CFL_CONST = {3: 0.2, 5: 0.15, 7: 0.1}
+BATCH_CFL_VAR = {3: 0.12, 5: 0.09, 7: 0.06}
+
+
+def _batch_section(steps, seed=4, n_prob=64):
+    """Independent problems of uneven size and degree advanced together (one captured
+    graph launch per step): constant-coefficient problems in FP32 storage, variable
+    ones (mapped mesh, c^2 = 1 + 0.5 g) with FP64 PCG at rtol 1e-12."""
+    import torch
+    from paper_2105_01722_amd import gdw, inputs
+    specs = inputs.batch_specs(seed, n_prob)
+    probs, dts, kinds = [], [], []
+    for sp in specs:
+        n, N, p = sp["n"], sp["N"], sp["p"]
+        if sp["variable"]:
+            if N == 16 and p == 7:
+                p = 5          # the FP64 element operator of (16, 7) exceeds a workgroup's LDS
+            probs.append(dict(nx=n, ny=n, N=N, p=p, flux="upwind", solver="pcg",
+                              coeff_variable=True, mapped=True, pcg_rtol=1e-12))
+            dts.append(BATCH_CFL_VAR[p] / (n * N))
+        else:
+            probs.append(dict(nx=n, ny=n, N=N, p=p, flux="upwind", precision="fp32"))
+            dts.append(BATCH_CFL_CONST[p] / (n * N))
+        kinds.append(sp)
+    b = gdw.Batch(probs)
+    dof = []
+    for i, (kw, sp) in enumerate(zip(probs, specs)):
+        n, N = kw["nx"], kw["N"]
+        X, Y = inputs.node_coords(n, n, N)
+        if sp["variable"]:
+            c2 = inputs.c2_field(sp["grf_seed"], X, Y)
+            X, Y = inputs.mapped_coords(X, Y)
+            b.problems[i].set_coeff(c2, X, Y)
+        U0 = inputs.fourier_field(inputs.fourier_modes(sp["mode_seed"]), X, Y)
+        b.problems[i].set_state(U0, np.zeros_like(U0))
+        dof.append(n * n * (N + 1) ** 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.tune(dts)
+    tune_s = time.perf_counter() - t0
+    b.run(dts, 1)                                   # warm-up (graph build)
+    torch.cuda.synchronize()
+    b.run(dts, steps)
+    st = np.array(b.step_times())
+    total_ms = float(st.sum())
+    its = [b.problems[i].stats() for i in range(len(probs)) if probs[i].get("solver") == "pcg"]
+    # each problem alone, one step through gdw_run on the same context
+    solo = []
+    stream = torch.cuda.current_stream()
+    for i in range(len(probs)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.problems[i].run(dts[i], 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        solo.append(e0.elapsed_time(e1))
+    plan = b.plan().split("candidates:")[0].strip().splitlines()
+    b.close()
+    tot_dof = int(sum(dof))
+    return {
+        "workload": "%d independent periodic problems: n ~ U{16..128}^2 elements, N ~ U{8,12,16}, "
+                    "p ~ U{3,5,7} (seed %d); even-numbered: c = 1 Cartesian, FP32 storage; "
+                    "odd-numbered: mapped mesh, c^2 = 1 + 0.5 g, FP64 PCG rtol 1e-12 (p = 5 where "
+                    "N = 16, p = 7); upwind; dt = CFL h per problem" % (n_prob, seed),
+        "problems": len(probs), "dof_total": tot_dof, "steps": steps,
+        "value": tot_dof * steps / (total_ms * 1e-3), "unit": "DOF-updates/s",
+        "step_ms_p50": float(np.percentile(st, 50)), "step_ms_p99": float(np.percentile(st, 99)),
+        "step_ms_min": float(st.min()), "step_ms_max": float(st.max()),
+        "solo_sum_ms_per_step": float(sum(solo)),
+        "speedup_vs_solo_sequence": float(sum(solo) / (total_ms / steps)),
+        "pcg_mean_it_S": float(np.mean([s["mean_it_S"] for s in its])) if its else None,
+        "pcg_mean_it_M": float(np.mean([s["mean_it_M"] for s in its])) if its else None,
+        "tune_seconds": tune_s,
+        "plan": plan,
+        "per_problem": [
+            {"n": probs[i]["nx"], "N": probs[i]["N"], "p": probs[i]["p"],
+             "kind": "pcg-f64" if probs[i].get("solver") == "pcg" else "fdm-f32",
+             "dof": dof[i], "solo_ms_per_step": round(solo[i], 4),
+             "solo_dof_updates_per_s": dof[i] / (solo[i] * 1e-3)}
+            for i in range(len(probs))],
+    }
+
+
 def _cpu_baseline(w, n_patch=32, steps=10):
     """The FP64 oracle, as it is, on a bounded sample: a 32 x 32-element periodic patch
     of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps."""
@@ -230,6 +317,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
     ap.add_argument("--no-pcg", action="store_true", help="skip the variable-coefficient PCG workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems section")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="profiling aid: run only the batched-problems section")
     ap.add_argument("--pcg-only", action="store_true",
                     help="profiling aid: run only the PCG workload (prints its section only)")
     ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
@@ -256,6 +346,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.batch_only:
+        print(json.dumps({"batch": _batch_section(max(1, min(args.steps, 5)))}))
+        return
     if args.pcg_only:
         pw = _pcg_workload()
         ms, its = _time_pcg(pw, max(1, args.pcg_steps), 1)
@@ -321,6 +414,9 @@ def main():
     if not args.no_learned:
         out["learned"] = _learned_section(max(1, min(args.steps, 3)))
         print("bench: learned section done", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["batch"] = _batch_section(max(1, min(args.steps, 5)))
+        print("bench: batch section done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = _cpu_baseline(w)
         print("bench: cpu baseline done", file=sys.stderr, flush=True)

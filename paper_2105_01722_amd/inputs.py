@@ -121,6 +121,22 @@ def mapped_coords(X, Y, eps=0.05):
     return X + eps * s, Y + eps * s
 
 
+def batch_specs(seed=4, n_prob=64):
+    """Independent problems of uneven size and degree: n ~ U{16..128} elements per
+    direction, N ~ U{8, 12, 16}, p ~ U{3, 5, 7}, half of them (alternating) with a variable
+    coefficient on the mapped mesh.  Returns dicts (n, N, p, variable, grf_seed, mode_seed);
+    problem i uses coefficient seed 1000 + i and initial-data seed 2000 + i."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_prob):
+        n = int(rng.integers(16, 129))
+        N = int(rng.choice([8, 12, 16]))
+        p = int(rng.choice([3, 5, 7]))
+        out.append(dict(n=n, N=N, p=p, variable=(i % 2 == 1), grf_seed=1000 + i,
+                        mode_seed=2000 + i))
+    return out
+
+
 def cfl_dt(N, n, cfl=0.5, L=1.0):
     """dt = CFL * h with h = L / (n N) the cell width."""
     return cfl * L / (n * N)
