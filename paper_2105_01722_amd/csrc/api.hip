@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <random>
@@ -293,6 +294,17 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
     }
     if ((s = own_upload<int>(c, 13, dst, &c->dst)) != GDW_OK) return s;
   }
+  {
+    // column-block layout of the faster stage kernel, where it applies
+    std::vector<int> boff, bdst, jc;
+    if (pcg_block_tables(g, rowoff, boff, bdst, jc, &c->blk_K, &c->blk_CH, &c->blk_WB,
+                         &c->blk_nnz, &c->blk_threads)) {
+      if ((s = own_upload<int>(c, 15, boff, &c->blk_off)) != GDW_OK) return s;
+      if ((s = own_upload<int>(c, 16, bdst, &c->blk_dst)) != GDW_OK) return s;
+      if ((s = own_upload<int>(c, 17, jc, &c->blk_jc)) != GDW_OK) return s;
+      c->blk_v2 = 1;
+    }
+  }
   if (pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
     set_error("element operator does not fit the LDS of a workgroup (reduce N or p)");
     return GDW_EUNSUPPORTED;
@@ -508,6 +520,17 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.mixed = 0;
   a.fo = c->fo;
   a.dst = c->dst;
+  if (c->blk_v2) {
+    a.v2 = 1;
+    a.blk_off = c->blk_off;
+    a.blk_dst = c->blk_dst;
+    a.blk_jc = c->blk_jc;
+    a.blk_K = c->blk_K;
+    a.blk_CH = c->blk_CH;
+    a.blk_WB = c->blk_WB;
+    a.blk_threads = c->blk_threads;
+    a.nnz_full = c->blk_nnz;
+  }
   stage_roles(c, stage, a);
   return a;
 }

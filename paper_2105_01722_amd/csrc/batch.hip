@@ -131,7 +131,7 @@ static gdw_status upload_pcg_args(gdw_batch* b, PcgClass& c, int stage,
     const gdw_ctx* x = b->ctx[c.members[k]];
     PcgStageArgs a = pcg_stage_args(x, stage, dt[c.members[k]]);
     size_t l;
-    pcg_stage_shape(a.g, threads, &a.full, &a.Q, &a.nnz_full, &l);
+    if (!pcg_args_shape(a, threads, &l)) l = (size_t)-1;   // block too small: not a candidate
     lds = std::max(lds, l);
     if (scratch) {
       a.xS = (*scratch)[k].xS;
@@ -262,8 +262,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
   for (int i : c.members) nn_max = std::max(nn_max, b->ctx[i]->g.nn);
   const long els = pcg_elems(c, b->ctx);
   if (s == GDW_OK && (s = upload_pcg_el(c, b->ctx)) == GDW_OK) {
-    for (int thr : {1024, 512, 256}) {
-      if (thr < ((nn_max + 63) / 64) * 64) continue;
+    for (int thr : {1024, 768, 512, 256}) {
+      if (thr < ((nn_max + 63) / 64) * 64 || thr > pcg_group_max_threads(c.n1)) continue;
       size_t lds;
       if ((s = upload_pcg_args(b, c, 1, dt, thr, &scr, &lds)) != GDW_OK) break;
       if (lds > 160 * 1024) continue;
@@ -275,8 +275,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
       for (unsigned grid : grids) {
         float ms;
         s = time_launch([&]() {
-              return launch_pcg_stage_group(1, c.d_args[0], c.d_el, (int)c.members.size(), grid,
-                                            thr, lds, st);
+              return launch_pcg_stage_group(1, c.n1, c.d_args[0], c.d_el, (int)c.members.size(),
+                                            grid, thr, lds, st);
             }, st, 1, &ms);
         if (s != GDW_OK) break;
         std::snprintf(buf, sizeof buf, "  pcg n1=%d threads=%d grid=%u lds=%zu: %.4f ms\n", c.n1,
@@ -324,7 +324,7 @@ static gdw_status build_graph(gdw_batch* b, const std::vector<double>& dt) {
     }
     for (auto& c : b->pcg) {
       if (e != hipSuccess) break;
-      e = launch_pcg_stage_group(k, c.d_args[k - 1], c.d_el, (int)c.members.size(), c.grid,
+      e = launch_pcg_stage_group(k, c.n1, c.d_args[k - 1], c.d_el, (int)c.members.size(), c.grid,
                                  c.threads, c.lds, b->cap);
     }
   }

@@ -50,7 +50,7 @@ struct gdw_ctx {
   // ---- PCG path ----
   gdw::PcgGeom g{};
   gdw::PcgElem el{};
-  void* own[16] = {};          // device tables of g (freed with the context)
+  void* own[24] = {};          // device tables of g (freed with the context)
   double* xS = nullptr;
   double* xM = nullptr;
   int* its = nullptr;
@@ -64,6 +64,12 @@ struct gdw_ctx {
   const int* dst = nullptr;    // full-rectangle destinations of the upper entries (device)
   double* c2n = nullptr;       // nodal c^2 as given to set_coeff (network inputs)
   const double* Bs = nullptr;  // [8][n1] basis values at the 8 sample centres
+  // column-block operator layout (pcg.hip), used when blk_v2 = 1
+  int blk_v2 = 0;
+  const int* blk_off = nullptr;
+  const int* blk_dst = nullptr;
+  const int* blk_jc = nullptr;
+  int blk_K = 0, blk_CH = 0, blk_WB = 0, blk_nnz = 0, blk_threads = 0;
 };
 
 

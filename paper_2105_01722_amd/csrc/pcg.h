@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 namespace gdw {
 
 // Tables shared by every element of a problem (device pointers).
@@ -61,7 +63,19 @@ struct PcgStageArgs {
   const int* fo;        // [nn+1] row starts of the full stencil rectangles
   const int* dst;       // [nst][2] full-rectangle positions (i,j), (j,i) of upper entry h
   int full, Q, nnz_full;  // set by the launcher: LDS layout of the operator
+  // column-block layout (N + 1 in {9, 13, 17}; see pcg.hip); v2 = 0 selects the row layout
+  int v2;
+  const int* blk_off;   // [nn] start of block (ix, jy) at index jy*(N+1) + ix
+  const int* blk_dst;   // [nst][2] block-layout positions of upper entry h and its transpose
+  const int* blk_jc;    // [blk_K] work units jy | (c << 8)
+  int blk_K, blk_CH, blk_WB, blk_threads;
 };
+
+// Column-block layout tables for one geometry; returns 0 when the layout does not apply
+// (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.
+int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
+                     std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
+                     int* nnz, int* threads);
 
 hipError_t launch_assemble(const PcgGeom& g, const double* X, const double* Y, const double* C2,
                            const PcgElem& el, long nel, hipStream_t st);
@@ -75,10 +89,15 @@ size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);
 // LDS layout of the stage kernel for a block of `threads` threads: full-rectangle operator
 // or not, row split Q, full operator size and LDS bytes.
 void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_full, size_t* lds);
-// Grouped persistent stage launch over several problems (args in device memory; every
-// args[i].full / Q / nnz_full set for `threads`; lds >= every member's need).
-hipError_t launch_pcg_stage_group(int stage, const PcgStageArgs* args, const long* el_start,
+// Layout of a problem's stage for a block of `threads` threads (row layout: sets full, Q,
+// nnz_full); *lds = its LDS bytes.  Returns 0 if `threads` is too small for it.
+int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds);
+// Grouped persistent stage launch over several problems with N + 1 = n1 (args in device
+// memory, each shaped by pcg_args_shape for `threads`; lds >= every member's need).
+hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds, hipStream_t st);
+// Largest block size of the grouped stage kernel for problems with N + 1 = n1.
+int pcg_group_max_threads(int n1);
 // Allow the grouped stage kernels their full LDS (call before any graph capture).
 hipError_t pcg_group_prepare();
 hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,

@@ -19,7 +19,9 @@
 // preconditioner itself and is not stored.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "pcg.h"
 #include "stencil.h"
@@ -502,12 +504,17 @@ static int full_parts(const PcgGeom& g) {
   return q < 1 ? 1 : q;
 }
 
+// doubles / ints of the LDS part common to both operator layouts (Psi excluded)
+__host__ __device__ inline size_t common_doubles(const PcgGeom& g) {
+  return (size_t)4 * g.nn + g.n1 + 2 * g.N * g.m * g.m + g.m + 2 * g.n1 + 4 * g.nq * 3 +
+         4 * g.nq * 2 + 16 * g.n1 + 64;
+}
+__host__ __device__ inline size_t common_ints(const PcgGeom& g) { return (size_t)g.N + 2 * g.n1; }
+
 static size_t stage_lds(const PcgGeom& g, int full) {
   const size_t nd = (size_t)(full ? full_nnz(g) + full_parts(g) * g.nn : g.nst)  // A, part
-                    + 11 * g.nn + g.nn + g.n1                                    // vectors, Psi, lamr
-                    + 2 * g.N * g.m * g.m + g.m + 2 * g.n1                       // cb cd gw dL dR
-                    + 4 * g.nq * 3 + 4 * g.nq * 2 + 16 * g.n1 + 64;              // face, sigma, lines, red
-  const size_t ni = 2 * (g.nn + 1) + g.N + 2 * g.n1;                             // fo ho cs ck0 ck1
+                    + 8 * g.nn + common_doubles(g);        // x r z d q tmp b Psi + common
+  const size_t ni = 2 * (g.nn + 1) + common_ints(g);      // fo ho + common
   return nd * sizeof(double) + ni * sizeof(int);
 }
 
@@ -560,62 +567,56 @@ __device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const doubl
   }
 }
 
-template <int STAGE>
-__device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long e) {
-  extern __shared__ double shd[];
+// ---------------------------------------------------------------------------------
+// Parts of an RK stage that do not depend on the operator layout.
+// ---------------------------------------------------------------------------------
+struct StageCommon {
+  double *U, *V, *Fu, *rv, *lamr, *lines, *red;
+  FaceTabs T;
+  double ub, vb, yu, yv, xs0, xm0, wt;      // owner thread t < nn
+  double cw, kbr, kbs, d00, area;
+};
+
+
+// Carve the common part from sp / ip, load the tables and the element's data, and form
+// the lifts: Fu = F_u, rv = F_v (the caller subtracts S_K U).  Psi (stride ps) is loaded
+// too.  `after_first_barrier` runs once the tables are in LDS (operator load overlap).
+template <int STAGE, typename F>
+__device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long e, double*& sp,
+                                               int*& ip, double* Psi, int ps, StageCommon& C,
+                                               F&& after_first_barrier) {
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
   const bool own = t < nn;
-  PcgShared W;
-  W.full = a.full;
-  W.Q = a.full ? a.Q : 0;
-  double* sp = shd;
-  W.A = sp;            sp += a.full ? a.nnz_full : g.nst;
-  W.part = sp;         sp += W.Q * nn;
-  double* U = sp;      sp += nn;
-  double* V = sp;      sp += nn;
-  W.x = sp;            sp += nn;
-  W.r = sp;            sp += nn;
-  W.z = sp;            sp += nn;
-  W.d = sp;            sp += nn;
-  W.q = sp;            sp += nn;
-  W.tmp = sp;          sp += nn;
-  W.b = sp;            sp += nn;
-  double* Fu = sp;     sp += nn;
-  double* rv = sp;     sp += nn;
-  W.Psi = sp;          sp += nn;
-  double* lamr = sp;   sp += n1;
-  double* cb = sp;     sp += N * m * m;
-  double* cd = sp;     sp += N * m * m;
-  double* gw = sp;     sp += m;
-  double* dL = sp;     sp += n1;
-  double* dR = sp;     sp += n1;
-  double* fc = sp;     sp += 4 * nq * 3;
-  double* sig = sp;    sp += 4 * nq * 2;
-  double* lines = sp;  sp += 16 * n1;
-  W.red = sp;          sp += 64;
-  int* ip = reinterpret_cast<int*>(sp);
-  int* fo = ip;        ip += nn + 1;
-  int* ho = ip;        ip += nn + 1;
-  int* cs = ip;        ip += N;
-  int* ck0 = ip;       ip += n1;
-  int* ck1 = ip;
-  W.fo = fo;
-  W.ho = ho;
-  FaceTabs T{cb, cd, gw, dL, dR, fc, cs, ck0, ck1};
+  C.U = sp;        sp += nn;
+  C.V = sp;        sp += nn;
+  C.Fu = sp;       sp += nn;
+  C.rv = sp;       sp += nn;
+  C.lamr = sp;     sp += n1;
+  double* cb = sp; sp += N * m * m;
+  double* cd = sp; sp += N * m * m;
+  double* gw = sp; sp += m;
+  double* dL = sp; sp += n1;
+  double* dR = sp; sp += n1;
+  double* fc = sp; sp += 4 * nq * 3;
+  double* sig = sp; sp += 4 * nq * 2;
+  C.lines = sp;    sp += 16 * n1;
+  C.red = sp;      sp += 64;
+  int* cs = ip;    ip += N;
+  int* ck0 = ip;   ip += n1;
+  int* ck1 = ip;   ip += n1;
+  C.T = FaceTabs{cb, cd, gw, dL, dR, fc, cs, ck0, ck1};
 
-  // ---- tables and element data into LDS ------------------------------------------
-  for (int i = t; i <= nn; i += blockDim.x) {
-    fo[i] = a.fo[i];
-    ho[i] = g.rowoff[i];
+  for (int i = t; i < ps * ps; i += blockDim.x) {    // padding rows / columns set to 0
+    const int r = i / ps, k = i - (i / ps) * ps;
+    Psi[i] = (r < n1 && k < n1) ? g.Psi[r * n1 + k] : 0.0;
   }
-  for (int i = t; i < nn; i += blockDim.x) W.Psi[i] = g.Psi[i];
   for (int i = t; i < N * m * m; i += blockDim.x) {
     cb[i] = g.cb[i];
     cd[i] = g.cd[i];
   }
   for (int i = t; i < n1; i += blockDim.x) {
-    lamr[i] = g.lamr[i];
+    C.lamr[i] = g.lamr[i];
     dL[i] = g.dL[i];
     dR[i] = g.dR[i];
     ck0[i] = g.ck0[i];
@@ -625,25 +626,29 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
   for (int i = t; i < N; i += blockDim.x) cs[i] = g.cs[i];
   const double* fcg = a.el.face + e * 4 * nq * 3;
   for (int i = t; i < 4 * nq * 3; i += blockDim.x) fc[i] = fcg[i];
-  double ub = 0, vb = 0, yu = 0, yv = 0, xs0 = 0, xm0 = 0, wt = 0;
+  C.ub = C.vb = C.yu = C.yv = C.xs0 = C.xm0 = C.wt = 0.0;
   if (own) {
-    ub = a.in_u[e * nn + t];
-    vb = a.in_v[e * nn + t];
+    C.ub = a.in_u[e * nn + t];
+    C.vb = a.in_v[e * nn + t];
     if (STAGE > 1) {
-      yu = a.aux_u[e * nn + t];
-      yv = a.aux_v[e * nn + t];
+      C.yu = a.aux_u[e * nn + t];
+      C.yv = a.aux_v[e * nn + t];
     }
-    U[t] = ub;
-    V[t] = vb;
-    xs0 = a.xS[e * nn + t];
-    xm0 = a.xM[e * nn + t];
-    wt = a.el.w[e * nn + t];
+    C.U[t] = C.ub;
+    C.V[t] = C.vb;
+    C.xs0 = a.xS[e * nn + t];
+    C.xm0 = a.xM[e * nn + t];
+    C.wt = a.el.w[e * nn + t];
   }
   const double* sc = a.el.sc + e * 8;
-  const double cw = sc[0], kbr = sc[1], kbs = sc[2], d00 = sc[3], area = sc[4];
+  C.cw = sc[0];
+  C.kbr = sc[1];
+  C.kbs = sc[2];
+  C.d00 = sc[3];
+  C.area = sc[4];
   const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
   __syncthreads();
-  op_load(g, W, a.el.S + e * g.nst, a.dst);
+  after_first_barrier();
 
   // ---- face fluxes sigma_u, sigma_v at the face points (Sec. 2.2.1) ----------------
   for (int id = t; id < 4 * nq; id += blockDim.x) {
@@ -673,113 +678,74 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
       for (int qa = 0; qa < m; ++qa) {
         const int id = f * nq + k * m + qa;
         const double wq = gw[qa] / N;
-        const double* F = fc + id * 3;
-        const double kn = f < 2 ? F[0] : F[1], kt = f < 2 ? F[1] : F[0];
+        const double* Fq = fc + id * 3;
+        const double kn = f < 2 ? Fq[0] : Fq[1], kt = f < 2 ? Fq[1] : Fq[0];
         const double bj = cb[(k * m + qa) * m + j], dj = cd[(k * m + qa) * m + j];
         cB += wq * sig[id * 2] * kn * bj;
         cD += wq * sig[id * 2] * kt * dj;
-        cV += wq * F[2] * sig[id * 2 + 1] * bj;
+        cV += wq * Fq[2] * sig[id * 2 + 1] * bj;
       }
     }
-    lines[(f * 4 + 0) * n1 + l] = cB;
-    lines[(f * 4 + 1) * n1 + l] = cD;
-    lines[(f * 4 + 2) * n1 + l] = cV;
+    C.lines[(f * 4 + 0) * n1 + l] = cB;
+    C.lines[(f * 4 + 1) * n1 + l] = cD;
+    C.lines[(f * 4 + 2) * n1 + l] = cV;
   }
   __syncthreads();
   if (own) {
     const int ix = t % n1, iy = t / n1;
-    const double* LE = lines + 0 * 4 * n1;
-    const double* LW = lines + 1 * 4 * n1;
-    const double* LN = lines + 2 * 4 * n1;
-    const double* LS = lines + 3 * 4 * n1;
+    const double* LE = C.lines + 0 * 4 * n1;
+    const double* LW = C.lines + 1 * 4 * n1;
+    const double* LN = C.lines + 2 * 4 * n1;
+    const double* LS = C.lines + 3 * 4 * n1;
     double fu = dR[ix] * LE[iy] + dL[ix] * LW[iy] + dR[iy] * LN[ix] + dL[iy] * LS[ix];
     double fv = 0;
     if (ix == N) { fu += LE[n1 + iy]; fv += LE[2 * n1 + iy]; }
     if (ix == 0) { fu += LW[n1 + iy]; fv += LW[2 * n1 + iy]; }
     if (iy == N) { fu += LN[n1 + ix]; fv += LN[2 * n1 + ix]; }
     if (iy == 0) { fu += LS[n1 + ix]; fv += LS[2 * n1 + ix]; }
-    Fu[t] = fu;
-    rv[t] = fv;
+    C.Fu[t] = fu;
+    C.rv[t] = fv;
   }
-  // r = -S_K U + F_v   (op_apply starts with the operator / U complete: barrier above
-  // covers U and the operator load)
-  {
-    const double su = op_apply(g, W, U);
-    if (own) rv[t] -= su;
-  }
-  // ---- S_hat y = F_u ------------------------------------------------------------------
-  double dS = 1.0;
-  if (own) {
-    const int kx = t % n1, ky = t / n1;
-    dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
-    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
-    W.x[t] = xs0;
-    W.b[t] = Fu[t];
-  }
-  __syncthreads();
-  int itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
-  if (itS > a.maxit && a.el.dlog) {
-    // the corrected preconditioner failed: repeat with the plain one from the same start
-    if (own) {
-      const int kx = t % n1, ky = t / n1;
-      dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
-      W.x[t] = xs0;
-    }
-    __syncthreads();
-    itS = pcg_solve(g, W, cw, wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
-  }
-  const double y = own ? W.x[t] : 0.0;
-  __syncthreads();
-  // ---- M_J z = r --------------------------------------------------------------------
-  int itM;
-  if (a.mapped) {
-    op_load(g, W, a.el.M + e * g.nst, a.dst);
-    if (own) {
-      W.x[t] = xm0;
-      W.b[t] = rv[t];
-    }
-    __syncthreads();
-    itM = pcg_solve(g, W, 0.0, 0.0, own ? 1.0 / area : 0.0, a.rtol, a.maxit);
-  } else {
-    // Cartesian: M_J = |Omega| M_ref (x) M_ref = Psi_2^{-T} diag(|Omega|) Psi_2^{-1}, so the
-    // preconditioner is the exact inverse (one PCG iteration).
-    double bb1[1] = {own ? rv[t] * rv[t] : 0.0};
-    block_sum<1>(bb1, W.red, nn);
-    const double bb = bb1[0];
-    pinv_apply<double>(rv, W.tmp, W.x, W.Psi, 1.0 / area, n1, nn);
-    itM = bb > 0.0 ? 1 : 0;
-  }
-  const double z = own ? W.x[t] : 0.0;
-  __syncthreads();
-  // ---- RK stage update (as in the constant-coefficient path) ---------------------------
-  const double ku = vb + y, kv = z, dt = a.dt;
+}
+
+// RK stage update from dU/dt = V + y, dV/dt = z, outputs, warm starts, traces of the new
+// value and iteration counters.  Starts with a barrier-free register phase; y, z are the
+// owner thread's solution entries.
+template <int STAGE>
+__device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long e,
+                                               const StageCommon& C, double y, double z,
+                                               int itS, int itM) {
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn;
+  const bool own = t < nn;
+  const double ku = C.vb + y, kv = z, dt = a.dt;
   if (own) {
     const long gi = e * nn + t;
     double nu, nv;
     if (STAGE == 1) {
-      nu = ub + 0.5 * dt * ku;
-      nv = vb + 0.5 * dt * kv;
+      nu = C.ub + 0.5 * dt * ku;
+      nv = C.vb + 0.5 * dt * kv;
     } else if (STAGE == 2) {
-      nu = yu + 0.5 * dt * ku;
-      nv = yv + 0.5 * dt * kv;
-      a.acc_u[gi] = ub + 2.0 * nu - yu;
-      a.acc_v[gi] = vb + 2.0 * nv - yv;
+      nu = C.yu + 0.5 * dt * ku;
+      nv = C.yv + 0.5 * dt * kv;
+      a.acc_u[gi] = C.ub + 2.0 * nu - C.yu;
+      a.acc_v[gi] = C.vb + 2.0 * nv - C.yv;
     } else if (STAGE == 3) {
-      nu = yu + dt * ku;
-      nv = yv + dt * kv;
+      nu = C.yu + dt * ku;
+      nv = C.yv + dt * kv;
     } else {
-      nu = (yu + ub) * (1.0 / 3.0) + dt * (1.0 / 6.0) * ku;
-      nv = (yv + vb) * (1.0 / 3.0) + dt * (1.0 / 6.0) * kv;
+      nu = (C.yu + C.ub) * (1.0 / 3.0) + dt * (1.0 / 6.0) * ku;
+      nv = (C.yv + C.vb) * (1.0 / 3.0) + dt * (1.0 / 6.0) * kv;
     }
     a.out_u[gi] = nu;
     a.out_v[gi] = nv;
     a.xS[gi] = y;
     a.xM[gi] = z;
-    U[t] = nu;
-    V[t] = nv;
+    C.U[t] = nu;
+    C.V[t] = nv;
   }
   __syncthreads();
-  face_traces_lds(g, T, U, V, lines, a.tr_out + e * 4 * nq * 2);
+  face_traces_lds(g, C.T, C.U, C.V, C.lines, a.tr_out + e * 4 * g.nq * 2);
   if (t == 0) {
     int* its = a.its + e * 4;
     its[0] += itS > a.maxit ? a.maxit : itS;
@@ -790,6 +756,398 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Stage with the row-rectangle operator layout (any N, p; FULL or HALF).
+// ---------------------------------------------------------------------------------
+template <int STAGE>
+__device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long e) {
+  extern __shared__ double shd[];
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
+  const bool own = t < nn;
+  PcgShared W;
+  W.full = a.full;
+  W.Q = a.full ? a.Q : 0;
+  double* sp = shd;
+  W.A = sp;            sp += a.full ? a.nnz_full : g.nst;
+  W.part = sp;         sp += W.Q * nn;
+  W.x = sp;            sp += nn;
+  W.r = sp;            sp += nn;
+  W.z = sp;            sp += nn;
+  W.d = sp;            sp += nn;
+  W.q = sp;            sp += nn;
+  W.tmp = sp;          sp += nn;
+  W.b = sp;            sp += nn;
+  W.Psi = sp;          sp += nn;
+  // ints after all doubles
+  int* ip = reinterpret_cast<int*>(shd + (a.full ? a.nnz_full : g.nst) + W.Q * nn + 8 * nn +
+                                   common_doubles(g));
+  int* fo = ip;        ip += nn + 1;
+  int* ho = ip;        ip += nn + 1;
+  W.fo = fo;
+  W.ho = ho;
+  for (int i = t; i <= nn; i += blockDim.x) {
+    fo[i] = a.fo[i];
+    ho[i] = g.rowoff[i];
+  }
+  StageCommon C;
+  stage_prologue<STAGE>(a, e, sp, ip, W.Psi, n1, C,
+                        [&]() { op_load(g, W, a.el.S + e * g.nst, a.dst); });
+  W.red = C.red;
+  // r = -S_K U + F_v   (op_apply starts with the operator / U complete: the barriers of
+  // the prologue cover U and the operator load)
+  {
+    const double su = op_apply(g, W, C.U);
+    if (own) C.rv[t] -= su;
+  }
+  // ---- S_hat y = F_u ------------------------------------------------------------------
+  double dS = 1.0;
+  if (own) {
+    const int kx = t % n1, ky = t / n1;
+    dS = t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky];
+    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
+    W.x[t] = C.xs0;
+    W.b[t] = C.Fu[t];
+  }
+  __syncthreads();
+  int itS = pcg_solve(g, W, C.cw, C.wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  if (itS > a.maxit && a.el.dlog) {
+    // the corrected preconditioner failed: repeat with the plain one from the same start
+    if (own) {
+      const int kx = t % n1, ky = t / n1;
+      dS = t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky];
+      W.x[t] = C.xs0;
+    }
+    __syncthreads();
+    itS = pcg_solve(g, W, C.cw, C.wt, own ? 1.0 / dS : 0.0, a.rtol, a.maxit);
+  }
+  const double y = own ? W.x[t] : 0.0;
+  __syncthreads();
+  // ---- M_J z = r --------------------------------------------------------------------
+  int itM;
+  if (a.mapped) {
+    op_load(g, W, a.el.M + e * g.nst, a.dst);
+    if (own) {
+      W.x[t] = C.xm0;
+      W.b[t] = C.rv[t];
+    }
+    __syncthreads();
+    itM = pcg_solve(g, W, 0.0, 0.0, own ? 1.0 / C.area : 0.0, a.rtol, a.maxit);
+  } else {
+    // Cartesian: M_J = |Omega| M_ref (x) M_ref = Psi_2^{-T} diag(|Omega|) Psi_2^{-1}, so the
+    // preconditioner is the exact inverse (one PCG iteration).
+    double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
+    block_sum<1>(bb1, W.red, nn);
+    const double bb = bb1[0];
+    pinv_apply<double>(C.rv, W.tmp, W.x, W.Psi, 1.0 / C.area, n1, nn);
+    itM = bb > 0.0 ? 1 : 0;
+  }
+  const double z = own ? W.x[t] : 0.0;
+  __syncthreads();
+  stage_epilogue<STAGE>(a, e, C, y, z, itS, itM);
+}
+
+// ---------------------------------------------------------------------------------
+// Stage with the column-block operator layout (N + 1 in {9, 13, 17}, FP64 operator in LDS).
+//
+// The operator is stored as blocks B(ix, jy) = { A[(ix, iy), (jx, jy)] : iy in band(jy),
+// jx in band(ix) } (rows of length w(ix)).  A work unit (ix, jy, c) takes rows
+// iy = lo(jy) + c*CH ... of its block: it reads the w(ix) values x[jy][band(ix)] once and
+// forms CH partial row sums, which go to slot jy - lo(iy) of row (ix, iy); each row then
+// adds its w(iy) partials in a fixed order.  Vectors of the solve are stored on an
+// (N+2) x (N+2) padded grid (rows of even length), so the preconditioner's transforms run
+// on 2 x 2 output blocks per thread without bounds tests.  The PCG recurrence is the
+// single-reduction form of Chronopoulos and Gear: one workgroup reduction per iteration.
+// ---------------------------------------------------------------------------------
+template <int N1C>
+struct BlockSolve {
+  double *A, *P, *R, *U, *T, *Z, *DI, *Psi;
+  const int *boff, *jc;
+  int K, CH, WB, p, N;
+};
+
+template <int N1C>
+__device__ __forceinline__ double blk_apply(const BlockSolve<N1C>& W, const double* __restrict__ x) {
+  constexpr int n1 = N1C, NP = N1C + 1, WM = N1C < 15 ? N1C : 15;
+  const int t = threadIdx.x;
+  if (t < n1 * W.K) {
+    const int k = t / n1, ix = t - k * n1;
+    const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
+    const int lox = st_lo(ix, W.p), wx = st_w(ix, W.p, W.N);
+    const int loy = st_lo(jy, W.p), wy = st_w(jy, W.p, W.N);
+    const int i0 = c * W.CH;
+    const int ni = min(W.CH, wy - i0);
+    double xs[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) xs[q] = q < wx ? x[jy * NP + lox + q] : 0.0;
+    const double* Ab = W.A + W.boff[jy * n1 + ix] + i0 * wx;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i < ni) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < WM; ++q)
+          if (q < wx) acc += Ab[i * wx + q] * xs[q];
+        const int iy = loy + i0 + i;
+        W.P[(iy * n1 + ix) * W.WB + (jy - st_lo(iy, W.p))] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  double y = 0.0;
+  if (t < n1 * n1) {
+    const int iy = t / n1;
+    const int wiy = st_w(iy, W.p, W.N);
+    const double* pr = W.P + t * W.WB;
+    for (int q = 0; q < wiy; ++q) y += pr[q];
+  }
+  return y;
+}
+
+// out = Psi_2 diag(DI) Psi_2^T R on the padded grid; ends with a barrier.  Each of the
+// four 1D transforms gives every output (a, b) to SP adjacent lanes (one quad), which
+// split its sum over the contracted index and combine the parts with DPP lane moves, so
+// that one batch of LDS loads per lane covers a phase.
+template <int N1C>
+__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C>& W, const double* __restrict__ R,
+                                double* __restrict__ out) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  constexpr int SP = 4 * nn <= 1024 ? 4 : 2;
+  constexpr int NT = (n1 + SP - 1) / SP;          // terms per lane
+  const int t = threadIdx.x;
+  const int o = t / SP, part = t - o * SP;
+  const bool act = o < nn;
+  const int a = act ? o / n1 : 0, b = act ? o - (o / n1) * n1 : 0;
+  const double* Ps = W.Psi;
+  auto combine = [&](double v) {
+    v += dpp_mov<0xb1, 0xf, false>(v);                       // lanes ^1
+    if constexpr (SP == 4) v += dpp_mov<0x4e, 0xf, false>(v);  // lanes ^2
+    return v;
+  };
+  double s = 0.0;
+  // T[a][b] = sum_i Psi[i][a] R[i][b]
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int i = part + k * SP;
+    if (act && i < n1) s += Ps[i * NP + a] * R[i * NP + b];
+  }
+  s = combine(s);
+  if (act && part == 0) W.T[a * NP + b] = s;
+  __syncthreads();
+  // Z[a][b] = DI[a][b] sum_i T[a][i] Psi[i][b]
+  s = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int i = part + k * SP;
+    if (act && i < n1) s += W.T[a * NP + i] * Ps[i * NP + b];
+  }
+  s = combine(s);
+  if (act && part == 0) W.Z[a * NP + b] = s * W.DI[a * NP + b];
+  __syncthreads();
+  // T[a][b] = sum_k Psi[a][k] Z[k][b]
+  s = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int i = part + k * SP;
+    if (act && i < n1) s += Ps[a * NP + i] * W.Z[i * NP + b];
+  }
+  s = combine(s);
+  if (act && part == 0) W.T[a * NP + b] = s;
+  __syncthreads();
+  // out[a][b] = sum_k T[a][k] Psi[b][k]
+  s = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int i = part + k * SP;
+    if (act && i < n1) s += W.T[a * NP + i] * Ps[b * NP + i];
+  }
+  s = combine(s);
+  if (act && part == 0) out[a * NP + b] = s;
+  __syncthreads();
+}
+
+// PCG (single-reduction recurrence) on (A_op + cw w w^T) x = b; owner thread t < nn holds
+// x (in/out, warm start on entry), b and w.  Iteration count as pcg_solve.
+template <int N1C>
+__device__ __forceinline__ int blk_solve(const BlockSolve<N1C>& W, double* red, double& x, double bval, double cw,
+                         double wt, double rtol, int maxit) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  if (own) W.U[pidx] = x;
+  __syncthreads();
+  const double ax = blk_apply(W, W.U);
+  double s2[2] = {own ? wt * x : 0.0, own ? bval * bval : 0.0};
+  block_sum<2>(s2, red, nn);
+  const double bb = s2[1];
+  if (bb == 0.0) {
+    x = 0.0;
+    return 0;
+  }
+  double r = own ? bval - ax - cw * s2[0] * wt : 0.0;
+  if (own) W.R[pidx] = r;
+  __syncthreads();
+  blk_pinv(W, W.R, W.U);
+  double u = own ? W.U[pidx] : 0.0;
+  double q = blk_apply(W, W.U);
+  double s4[4] = {r * u, q * u, wt * u, r * r};
+  block_sum<4>(s4, red, nn);
+  const double tol2 = rtol * rtol * bb;
+  if (s4[3] <= tol2) return 0;
+  double gam = s4[0];
+  double alpha = gam / (s4[1] + cw * s4[2] * s4[2]);
+  double pv = u, sv = q + cw * s4[2] * wt;
+  for (int it = 1; it <= maxit; ++it) {
+    x += alpha * pv;
+    r -= alpha * sv;
+    if (own) W.R[pidx] = r;
+    __syncthreads();
+    blk_pinv(W, W.R, W.U);
+    u = own ? W.U[pidx] : 0.0;
+    q = blk_apply(W, W.U);
+    double sr[4] = {r * u, q * u, wt * u, r * r};
+    block_sum<4>(sr, red, nn);
+    if (sr[3] <= tol2) return it;
+    const double gn = sr[0];
+    const double dn = sr[1] + cw * sr[2] * sr[2];
+    const double beta = gn / gam;
+    alpha = gn / (dn - beta * gn / alpha);
+    pv = u + beta * pv;
+    sv = (q + cw * sr[2] * wt) + beta * sv;
+    gam = gn;
+  }
+  return maxit + 1;
+}
+
+// Copy one element operator from its HBM upper half into the block layout.
+__device__ __forceinline__ void blk_load(const int nst, double* A, const double* __restrict__ half,
+                                const int* __restrict__ dst) {
+  // all loads of a lane first (8 per batch), then the LDS stores
+  const int step = blockDim.x;
+  for (int h0 = threadIdx.x; h0 < nst; h0 += 8 * step) {
+    double v[8];
+    int2 d2[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int h = h0 + k * step;
+      if (h < nst) {
+        v[k] = half[h];
+        d2[k] = reinterpret_cast<const int2*>(dst)[h];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int h = h0 + k * step;
+      if (h < nst) {
+        A[d2[k].x] = v[k];
+        A[d2[k].y] = v[k];
+      }
+    }
+  }
+}
+
+template <int N1C>
+__host__ __device__ inline size_t blk_lds_doubles(const PcgGeom& g, int nnz_full, int WB) {
+  constexpr int NP = N1C + 1;
+  return (size_t)nnz_full + (size_t)g.nn * WB + 6 * NP * NP + common_doubles(g);
+}
+
+template <int STAGE, int N1C>
+__device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const long e) {
+  extern __shared__ double shd[];
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  BlockSolve<N1C> W;
+  W.K = a.blk_K;
+  W.CH = a.blk_CH;
+  W.WB = a.blk_WB;
+  W.p = g.p;
+  W.N = g.N;
+  double* sp = shd;
+  W.A = sp;    sp += a.nnz_full;
+  W.P = sp;    sp += nn * W.WB;
+  W.R = sp;    sp += NP * NP;
+  W.U = sp;    sp += NP * NP;
+  W.T = sp;    sp += NP * NP;
+  W.Z = sp;    sp += NP * NP;
+  W.DI = sp;   sp += NP * NP;
+  W.Psi = sp;  sp += NP * NP;
+  double* zero_from = W.R;
+  int* ip = reinterpret_cast<int*>(shd + blk_lds_doubles<N1C>(g, a.nnz_full, W.WB));
+  int* boff = ip;  ip += nn;
+  int* jc = ip;    ip += W.K;
+  W.boff = boff;
+  W.jc = jc;
+  for (int i = t; i < nn; i += blockDim.x) boff[i] = a.blk_off[i];
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  StageCommon C;
+  double* const Aop = W.A;
+  const double* const Shalf = a.el.S + e * g.nst;
+  const int* const bdst = a.blk_dst;
+  const int nst = g.nst;
+  stage_prologue<STAGE>(a, e, sp, ip, W.Psi, NP, C, [zero_from, Aop, Shalf, bdst, nst]() {
+    for (int i = threadIdx.x; i < 5 * NP * NP; i += blockDim.x) zero_from[i] = 0.0;  // R U T Z DI
+    blk_load(nst, Aop, Shalf, bdst);
+  });
+  // r = -S_K U + F_v   (operator, tables, U complete after the prologue's barriers)
+  if (own) W.U[pidx] = C.U[t];
+  __syncthreads();
+  {
+    const double su = blk_apply(W, W.U);
+    if (own) C.rv[t] -= su;
+  }
+  // ---- S_hat y = F_u ------------------------------------------------------------------
+  double dS = 1.0;
+  if (own) {
+    const int kx = t % n1, ky = t / n1;
+    dS = t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky];
+    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
+    W.DI[pidx] = 1.0 / dS;
+  }
+  double y = C.xs0;
+  int itS = blk_solve(W, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit);
+  if (itS > a.maxit && a.el.dlog) {
+    if (own) {
+      const int kx = t % n1, ky = t / n1;
+      W.DI[pidx] = 1.0 / (t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky]);
+    }
+    y = C.xs0;
+    itS = blk_solve(W, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit);
+  }
+  __syncthreads();
+  // ---- M_J z = r --------------------------------------------------------------------
+  int itM;
+  double z;
+  if (own) W.DI[pidx] = 1.0 / C.area;
+  if (a.mapped) {
+    blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
+    z = C.xm0;
+    itM = blk_solve(W, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit);
+  } else {
+    // Cartesian: the preconditioner is the exact inverse of M_J
+    double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
+    if (own) W.R[pidx] = C.rv[t];
+    block_sum<1>(bb1, C.red, nn);
+    blk_pinv(W, W.R, W.U);
+    z = own ? W.U[pidx] : 0.0;
+    itM = bb1[0] > 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM);
+}
+
+// At most 768 threads (12 waves, 3 per SIMD), so that a lane may hold 170 VGPRs.
+constexpr int kBlkMaxThreads = 768;
+
+template <int STAGE, int N1C>
+__global__ __launch_bounds__(kBlkMaxThreads) void k_pcg2_stage(PcgStageArgs a) {
+  pcg2_stage_elem<STAGE, N1C>(a, blockIdx.x);
+}
+
 template <int STAGE>
 __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
   pcg_stage_elem<STAGE>(a, blockIdx.x);
@@ -798,15 +1156,22 @@ __global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
 // Grouped, persistent form over the elements of several problems (each with its own
 // geometry and LDS layout, all fitting the launch's LDS size and block size).  Problem i
 // owns elements [el_start[i], el_start[i+1]); block b takes b, b + gridDim.x, ...
-template <int STAGE>
-__global__ __launch_bounds__(1024) void k_pcg_stage_group(const PcgStageArgs* __restrict__ args,
+// N1C > 0: every member has N + 1 = N1C (column-block members run that kernel body).
+template <int STAGE, int N1C>
+__global__ __launch_bounds__(N1C > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_group(
+    const PcgStageArgs* __restrict__ args,
                                                           const long* __restrict__ el_start,
                                                           int nprob) {
   const long total = el_start[nprob];
   int pi = 0;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
     while (pi + 1 < nprob && b >= el_start[pi + 1]) ++pi;
-    pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+    if constexpr (N1C > 0) {
+      if (args[pi].v2) pcg2_stage_elem<STAGE, N1C>(args[pi], b - el_start[pi]);
+      else pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+    } else {
+      pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+    }
     __syncthreads();   // the next element reuses the LDS
   }
 }
@@ -912,6 +1277,69 @@ static hipError_t launch_stage_k(const PcgStageArgs& a0, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------
+// Column-block layout (host): tables, eligibility, LDS size.
+// ---------------------------------------------------------------------------------
+static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K) {
+  size_t nd;
+  switch (g.n1) {
+    case 9: nd = blk_lds_doubles<9>(g, nnz_full, WB); break;
+    case 13: nd = blk_lds_doubles<13>(g, nnz_full, WB); break;
+    case 17: nd = blk_lds_doubles<17>(g, nnz_full, WB); break;
+    default: return (size_t)-1;
+  }
+  return nd * sizeof(double) + ((size_t)g.nn + K + common_ints(g)) * sizeof(int);
+}
+
+int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
+                     std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
+                     int* nnz, int* threads) {
+  const int n1 = g.n1, N = g.N, p = g.p, nn = g.nn;
+  if (n1 != 9 && n1 != 13 && n1 != 17) return 0;
+  boff.assign(nn, 0);
+  int off = 0, wb = 0;
+  for (int jy = 0; jy < n1; ++jy)
+    for (int ix = 0; ix < n1; ++ix) {
+      boff[jy * n1 + ix] = off;
+      off += st_w(ix, p, N) * st_w(jy, p, N);
+    }
+  for (int k = 0; k < n1; ++k) wb = std::max(wb, st_w(k, p, N));
+  int ch = 1, kk = 0;
+  for (ch = 1; ch <= 4; ++ch) {
+    kk = 0;
+    for (int jy = 0; jy < n1; ++jy) kk += (st_w(jy, p, N) + ch - 1) / ch;
+    if (n1 * kk <= kBlkMaxThreads) break;
+  }
+  if (ch > 4 || kk > 255) return 0;
+  jc.clear();
+  for (int jy = 0; jy < n1; ++jy) {
+    const int nc = (st_w(jy, p, N) + ch - 1) / ch;
+    for (int c = 0; c < nc; ++c) jc.push_back(jy | (c << 8));
+  }
+  dst.assign((size_t)2 * g.nst, 0);
+  for (int i = 0; i < nn; ++i) {
+    const int ix = i % n1, iy = i / n1;
+    for (int j = i; j < nn; ++j) {
+      const int jx = j % n1, jy = j / n1;
+      if (!st_in_upper(ix, iy, jx, jy, p, N)) continue;
+      const int h = rowoff[i] + st_pos(ix, iy, jx, jy, p, N);
+      // A[(ix,iy),(jx,jy)] in block (ix, jy), row iy, column jx; and its transpose
+      dst[2 * h] = boff[jy * n1 + ix] + (iy - st_lo(jy, p)) * st_w(ix, p, N) + (jx - st_lo(ix, p));
+      dst[2 * h + 1] = boff[iy * n1 + jx] + (jy - st_lo(iy, p)) * st_w(jx, p, N) + (ix - st_lo(jx, p));
+    }
+  }
+  const size_t lds = blk_lds_bytes(g, off, wb, kk);
+  if (lds > 160 * 1024) return 0;
+  *K = kk;
+  *CH = ch;
+  *WB = wb;
+  *nnz = off;
+  const int sp = 4 * nn <= 1024 ? 4 : 2;        // lanes per output in blk_pinv
+  *threads = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
+  if (*threads > kBlkMaxThreads) return 0;
+  return 1;
+}
+
 void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_full, size_t* lds) {
   *full = stage_full(g);
   *nnz_full = full_nnz(g);
@@ -925,25 +1353,40 @@ void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_
   *lds = stage_lds(g, *full);
 }
 
-template <int STAGE>
+int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds) {
+  if (a.v2) {
+    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
+    return threads >= a.blk_threads;
+  }
+  pcg_stage_shape(a.g, threads, &a.full, &a.Q, &a.nnz_full, lds);
+  return threads >= ((a.g.nn + 63) / 64) * 64;
+}
+
+template <int STAGE, int N1C>
 static hipError_t launch_group_k(const PcgStageArgs* args, const long* el_start, int nprob,
                                  unsigned grid, int threads, size_t lds, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pcg_stage_group<STAGE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_pcg_stage_group<STAGE>, dim3(grid), dim3(threads), lds, st, args, el_start,
-                     nprob);
+  hipLaunchKernelGGL((k_pcg_stage_group<STAGE, N1C>), dim3(grid), dim3(threads), lds, st, args,
+                     el_start, nprob);
   return hipGetLastError();
 }
 
-hipError_t pcg_group_prepare() {
+template <int STAGE>
+static hipError_t launch_group_n1(int n1, const PcgStageArgs* args, const long* el_start,
+                                  int nprob, unsigned grid, int threads, size_t lds,
+                                  hipStream_t st) {
+  switch (n1) {
+    case 9: return launch_group_k<STAGE, 9>(args, el_start, nprob, grid, threads, lds, st);
+    case 13: return launch_group_k<STAGE, 13>(args, el_start, nprob, grid, threads, lds, st);
+    case 17: return launch_group_k<STAGE, 17>(args, el_start, nprob, grid, threads, lds, st);
+    default: return launch_group_k<STAGE, 0>(args, el_start, nprob, grid, threads, lds, st);
+  }
+}
+
+template <int N1C>
+static hipError_t group_attrs() {
   hipError_t e;
-  const void* k[4] = {(const void*)k_pcg_stage_group<1>, (const void*)k_pcg_stage_group<2>,
-                      (const void*)k_pcg_stage_group<3>, (const void*)k_pcg_stage_group<4>};
+  const void* k[4] = {(const void*)k_pcg_stage_group<1, N1C>, (const void*)k_pcg_stage_group<2, N1C>,
+                      (const void*)k_pcg_stage_group<3, N1C>, (const void*)k_pcg_stage_group<4, N1C>};
   for (int i = 0; i < 4; ++i)
     if ((e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)) !=
         hipSuccess)
@@ -951,19 +1394,68 @@ hipError_t pcg_group_prepare() {
   return hipSuccess;
 }
 
-hipError_t launch_pcg_stage_group(int stage, const PcgStageArgs* args, const long* el_start,
+hipError_t pcg_group_prepare() {
+  hipError_t e;
+  if ((e = group_attrs<0>()) != hipSuccess) return e;
+  if ((e = group_attrs<9>()) != hipSuccess) return e;
+  if ((e = group_attrs<13>()) != hipSuccess) return e;
+  return group_attrs<17>();
+}
+
+int pcg_group_max_threads(int n1) {
+  return (n1 == 9 || n1 == 13 || n1 == 17) ? kBlkMaxThreads : 1024;
+}
+
+hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds, hipStream_t st) {
   if (nprob <= 0 || grid == 0) return hipSuccess;
-  if (lds > 160 * 1024 || threads > 1024 || threads < 64) return hipErrorInvalidValue;
+  if (lds > 160 * 1024 || threads > pcg_group_max_threads(n1) || threads < 64)
+    return hipErrorInvalidValue;
   switch (stage) {
-    case 1: return launch_group_k<1>(args, el_start, nprob, grid, threads, lds, st);
-    case 2: return launch_group_k<2>(args, el_start, nprob, grid, threads, lds, st);
-    case 3: return launch_group_k<3>(args, el_start, nprob, grid, threads, lds, st);
-    default: return launch_group_k<4>(args, el_start, nprob, grid, threads, lds, st);
+    case 1: return launch_group_n1<1>(n1, args, el_start, nprob, grid, threads, lds, st);
+    case 2: return launch_group_n1<2>(n1, args, el_start, nprob, grid, threads, lds, st);
+    case 3: return launch_group_n1<3>(n1, args, el_start, nprob, grid, threads, lds, st);
+    default: return launch_group_n1<4>(n1, args, el_start, nprob, grid, threads, lds, st);
+  }
+}
+
+template <int STAGE, int N1C>
+static hipError_t launch_blk_k(const PcgStageArgs& a, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pcg2_stage<STAGE, N1C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const size_t sh = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
+  constexpr int SP = 4 * N1C * N1C <= 1024 ? 4 : 2;
+  if (sh > 160 * 1024 || a.blk_threads > kBlkMaxThreads || a.blk_threads < N1C * a.blk_K ||
+      a.blk_threads < SP * N1C * N1C)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pcg2_stage<STAGE, N1C>), dim3((unsigned)a.nel), dim3(a.blk_threads), sh, st, a);
+  return hipGetLastError();
+}
+
+template <int STAGE>
+static hipError_t launch_blk_n1(const PcgStageArgs& a, hipStream_t st) {
+  switch (a.g.n1) {
+    case 9: return launch_blk_k<STAGE, 9>(a, st);
+    case 13: return launch_blk_k<STAGE, 13>(a, st);
+    case 17: return launch_blk_k<STAGE, 17>(a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st) {
+  if (a.v2 && a.nel > 0) {
+    switch (stage) {
+      case 1: return launch_blk_n1<1>(a, st);
+      case 2: return launch_blk_n1<2>(a, st);
+      case 3: return launch_blk_n1<3>(a, st);
+      default: return launch_blk_n1<4>(a, st);
+    }
+  }
   if (a.nel == 0) return hipSuccess;
   if (pcg_stage_lds_bytes(a.g, a.mixed) > 160 * 1024) return hipErrorInvalidValue;
   if (a.fo == nullptr || a.dst == nullptr) return hipErrorInvalidValue;
