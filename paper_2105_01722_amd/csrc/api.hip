@@ -37,6 +37,13 @@ static void free_all(gdw_ctx* c) {
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.S32); F(c->el.M32); F(c->el.w); F(c->el.sc); F(c->el.face);
   F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
+  F(c->d_pargs); F(c->d_pel);
+}
+
+// The stage arguments derived from the context (pointers of the element data) changed.
+static void args_changed(gdw_ctx* c) {
+  c->pargs_ok = 0;
+  ++c->args_epoch;
 }
 
 extern "C" const char* gdw_version(void) { return "gdw 0.1 (gfx950)"; }
@@ -329,6 +336,13 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   GDW_HIP(hipMalloc(&c->xS, nodal));
   GDW_HIP(hipMalloc(&c->xM, nodal));
   GDW_HIP(hipMalloc(&c->its, (size_t)nel * 4 * sizeof(int)));
+  GDW_HIP(hipMalloc(&c->d_pargs, 4 * sizeof(PcgStageArgs)));
+  GDW_HIP(hipMalloc(&c->d_pel, 2 * sizeof(long)));
+  {
+    const long pel[2] = {0, nel};
+    GDW_HIP(hipMemcpy(c->d_pel, pel, sizeof(pel), hipMemcpyHostToDevice));
+  }
+  GDW_HIP(pcg_group_prepare());
   GDW_HIP(hipMalloc(&c->fail, sizeof(int)));
   GDW_HIP(hipMalloc(&c->epart, (size_t)(nel + 1) * sizeof(double)));
   GDW_HIP(hipMalloc(&c->nonfinite, sizeof(unsigned int)));
@@ -549,12 +563,31 @@ static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
 }
 
 static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
-  PcgStageArgs a[4];
-  for (int k = 0; k < 4; ++k) a[k] = pcg_stage_args(c, k + 1, dt);
   hipError_t e;
+  if (!c->pargs_ok || c->pargs_dt != dt) {
+    // the argument blocks are read by kernels still queued on the stream: replace them
+    // only after those have run
+    if (c->pargs_used && (e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    for (int k = 0; k < 4; ++k) {
+      c->h_pargs[k] = pcg_stage_args(c, k + 1, dt);
+      if (!pcg_single_shape(c->h_pargs[k], &c->p_threads, &c->p_lds)) return hipErrorInvalidValue;
+    }
+    if ((e = hipMemcpyAsync(c->d_pargs, c->h_pargs, sizeof(c->h_pargs), hipMemcpyHostToDevice,
+                            st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    c->pargs_dt = dt;
+    c->pargs_ok = 1;
+  }
+  c->pargs_used = 1;
+  const int key = pcg_group_key(c->h_pargs[0]);
   for (int s = 0; s < steps; ++s)
-    for (int k = 0; k < 4; ++k)
-      if ((e = launch_pcg_stage(k + 1, a[k], st)) != hipSuccess) return e;
+    for (int k = 0; k < 4; ++k) {
+      const unsigned grid = pcg_group_grid(k + 1, key, c->p_threads, c->p_lds, c->nel);
+      if ((e = launch_pcg_stage_group(k + 1, key, c->d_pargs + k, c->d_pel, 1, grid, c->p_threads,
+                                      c->p_lds, st)) != hipSuccess)
+        return e;
+    }
   c->stages_since_state += 4LL * steps;
   return hipSuccess;
 }
@@ -867,7 +900,10 @@ extern "C" gdw_status gdw_precond_data(gdw_ctx* c, float* samples, float* target
 }
 
 static gdw_status ensure_dlog(gdw_ctx* c) {
-  if (!c->el.dlog) GDW_HIP(hipMalloc(&c->el.dlog, (size_t)c->nel * c->g.nn * sizeof(float)));
+  if (!c->el.dlog) {
+    GDW_HIP(hipMalloc(&c->el.dlog, (size_t)c->nel * c->g.nn * sizeof(float)));
+    args_changed(c);
+  }
   return GDW_OK;
 }
 
@@ -879,6 +915,7 @@ extern "C" gdw_status gdw_set_precond_log(gdw_ctx* c, const float* log_scale, vo
     GDW_HIP(hipStreamSynchronize(st));
     if (c->el.dlog) (void)hipFree(c->el.dlog);
     c->el.dlog = nullptr;
+    args_changed(c);
     return GDW_OK;
   }
   gdw_status s = ensure_dlog(c);

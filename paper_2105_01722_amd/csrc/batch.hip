@@ -55,6 +55,7 @@ struct gdw_batch {
   std::vector<FdmClass> fdm;
   std::vector<PcgClass> pcg;
   std::vector<double> dt;      // per-problem dt of the instantiated graph
+  long long epoch = -1;        // sum of the members' argument epochs at graph build
   hipStream_t cap = nullptr;   // private stream used for graph capture
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -259,7 +260,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
   size_t best_lds = 0;
   char buf[160];
   int nn_max = 0;
-  for (int i : c.members) nn_max = std::max(nn_max, b->ctx[i]->g.nn);
+  for (int i : c.members)
+    nn_max = std::max(nn_max, std::max(b->ctx[i]->g.nn, b->ctx[i]->blk_threads));
   const long els = pcg_elems(c, b->ctx);
   if (s == GDW_OK && (s = upload_pcg_el(c, b->ctx)) == GDW_OK) {
     for (int thr : {1024, 768, 512, 256}) {
@@ -279,8 +281,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
                                             grid, thr, lds, st);
             }, st, 1, &ms);
         if (s != GDW_OK) break;
-        std::snprintf(buf, sizeof buf, "  pcg n1=%d threads=%d grid=%u lds=%zu: %.4f ms\n", c.n1,
-                      thr, grid, lds, ms);
+        std::snprintf(buf, sizeof buf, "  pcg %s%d threads=%d grid=%u lds=%zu: %.4f ms\n",
+                      c.n1 ? "blocks n1=" : "rows ", c.n1, thr, grid, lds, ms);
         log += buf;
         if (ms < best) { best = ms; best_thr = thr; best_grid = grid; best_lds = lds; }
       }
@@ -338,6 +340,8 @@ static gdw_status build_graph(gdw_batch* b, const std::vector<double>& dt) {
   b->graph = g;
   GDW_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   b->dt = dt;
+  b->epoch = 0;
+  for (const gdw_ctx* c : b->ctx) b->epoch += c->args_epoch;
   return GDW_OK;
 }
 
@@ -350,8 +354,8 @@ static void make_plan(gdw_batch* b, const std::string& log) {
     p += buf;
   }
   for (auto& c : b->pcg) {
-    std::snprintf(buf, sizeof buf, "pcg n1=%d: %zu problems, threads=%d grid=%u lds=%zu\n", c.n1,
-                  c.members.size(), c.threads, c.grid, c.lds);
+    std::snprintf(buf, sizeof buf, "pcg %s%d: %zu problems, threads=%d grid=%u lds=%zu\n",
+                  c.n1 ? "blocks n1=" : "rows ", c.n1, c.members.size(), c.threads, c.grid, c.lds);
     p += buf;
   }
   b->plan = p + "candidates:\n" + log;
@@ -386,8 +390,10 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
     for (int i = 0; i < nprob; ++i) {
       const gdw_ctx* c = b->ctx[i];
       if (c->solver == GDW_SOLVE_PCG) {
-        auto key = std::make_pair(c->n1, 0);
-        if (!pk.count(key)) { pk[key] = b->pcg.size(); b->pcg.emplace_back(); b->pcg.back().n1 = c->n1; }
+        // kernel family: N + 1 for the column-block layout, 0 for the row layout
+        const int fam = c->blk_v2 ? c->n1 : 0;
+        auto key = std::make_pair(fam, 0);
+        if (!pk.count(key)) { pk[key] = b->pcg.size(); b->pcg.emplace_back(); b->pcg.back().n1 = fam; }
         b->pcg[pk[key]].members.push_back(i);
       } else {
         auto key = std::make_pair((int)c->elem_bytes, c->n1);
@@ -460,7 +466,9 @@ extern "C" gdw_status gdw_batch_run(gdw_batch* b, const double* dt, int steps, v
   hipStream_t st = (hipStream_t)stream;
   if (!b->tuned && (s = gdw_batch_tune(b, dt, stream)) != GDW_OK) return s;
   std::vector<double> d(dt, dt + b->ctx.size());
-  if (!b->exec || d != b->dt) {
+  long long ep = 0;
+  for (const gdw_ctx* c : b->ctx) ep += c->args_epoch;
+  if (!b->exec || d != b->dt || ep != b->epoch) {
     GDW_HIP(hipStreamSynchronize(st));
     if ((s = build_graph(b, d)) != GDW_OK) return s;
   }

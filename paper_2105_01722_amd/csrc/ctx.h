@@ -70,6 +70,16 @@ struct gdw_ctx {
   const int* blk_dst = nullptr;
   const int* blk_jc = nullptr;
   int blk_K = 0, blk_CH = 0, blk_WB = 0, blk_nnz = 0, blk_threads = 0;
+  // stage arguments of the PCG time loop in device memory (the grouped kernel, one problem)
+  gdw::PcgStageArgs* d_pargs = nullptr;   // [4]
+  long* d_pel = nullptr;                  // {0, nel}
+  gdw::PcgStageArgs h_pargs[4] = {};
+  double pargs_dt = -1.0;
+  int pargs_ok = 0;                       // h_pargs / d_pargs match the context
+  int pargs_used = 0;                     // kernels reading d_pargs have been queued
+  int args_epoch = 0;                     // bumped whenever stage arguments change
+  int p_threads = 0;
+  size_t p_lds = 0;
 };
 
 

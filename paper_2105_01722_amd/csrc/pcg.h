@@ -84,7 +84,14 @@ hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, 
 hipError_t launch_to_f32(const double* a, float* b, long n, hipStream_t st);
 hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,
                              double* tr, long nel, hipStream_t st);
-hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st);
+// Kernel family of a problem for the grouped launch: N + 1 for the column-block layout,
+// 0 for the row layout.
+int pcg_group_key(const PcgStageArgs& a);
+// Block size and LDS of a problem launched alone (sets full / Q / nnz_full of the row
+// layout); 0 if it does not fit a workgroup.
+int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds);
+// Persistent grid of the grouped kernel of family `key` for nel elements.
+unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel);
 size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);
 // LDS layout of the stage kernel for a block of `threads` threads: full-rectangle operator
 // or not, row split Q, full operator size and LDS bytes.
@@ -92,12 +99,13 @@ void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_
 // Layout of a problem's stage for a block of `threads` threads (row layout: sets full, Q,
 // nnz_full); *lds = its LDS bytes.  Returns 0 if `threads` is too small for it.
 int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds);
-// Grouped persistent stage launch over several problems with N + 1 = n1 (args in device
-// memory, each shaped by pcg_args_shape for `threads`; lds >= every member's need).
-hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, const long* el_start,
+// Grouped persistent stage launch over several problems of one kernel family `key` (args
+// in device memory, each shaped by pcg_args_shape for `threads`; lds >= every member's
+// need).  A single problem is the group of one.
+hipError_t launch_pcg_stage_group(int stage, int key, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds, hipStream_t st);
-// Largest block size of the grouped stage kernel for problems with N + 1 = n1.
-int pcg_group_max_threads(int n1);
+// Largest block size of the grouped stage kernel of family `key`.
+int pcg_group_max_threads(int key);
 // Allow the grouped stage kernels their full LDS (call before any graph capture).
 hipError_t pcg_group_prepare();
 hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,

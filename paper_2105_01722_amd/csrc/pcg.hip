@@ -571,23 +571,17 @@ __device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const doubl
 // Parts of an RK stage that do not depend on the operator layout.
 // ---------------------------------------------------------------------------------
 struct StageCommon {
-  double *U, *V, *Fu, *rv, *lamr, *lines, *red;
+  double *U, *V, *Fu, *rv, *lamr, *lines, *red, *sig;
   FaceTabs T;
   double ub, vb, yu, yv, xs0, xm0, wt;      // owner thread t < nn
   double cw, kbr, kbs, d00, area;
 };
 
 
-// Carve the common part from sp / ip, load the tables and the element's data, and form
-// the lifts: Fu = F_u, rv = F_v (the caller subtracts S_K U).  Psi (stride ps) is loaded
-// too.  `after_first_barrier` runs once the tables are in LDS (operator load overlap).
-template <int STAGE, typename F>
-__device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long e, double*& sp,
-                                               int*& ip, double* Psi, int ps, StageCommon& C,
-                                               F&& after_first_barrier) {
-  const PcgGeom& g = a.g;
-  const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
-  const bool own = t < nn;
+// Carve the common part from sp / ip (pointer arithmetic only).
+__device__ __forceinline__ void stage_carve(const PcgGeom& g, double*& sp, int*& ip,
+                                            StageCommon& C) {
+  const int nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
   C.U = sp;        sp += nn;
   C.V = sp;        sp += nn;
   C.Fu = sp;       sp += nn;
@@ -599,15 +593,29 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   double* dL = sp; sp += n1;
   double* dR = sp; sp += n1;
   double* fc = sp; sp += 4 * nq * 3;
-  double* sig = sp; sp += 4 * nq * 2;
+  C.sig = sp;      sp += 4 * nq * 2;
   C.lines = sp;    sp += 16 * n1;
   C.red = sp;      sp += 64;
   int* cs = ip;    ip += N;
   int* ck0 = ip;   ip += n1;
   int* ck1 = ip;   ip += n1;
   C.T = FaceTabs{cb, cd, gw, dL, dR, fc, cs, ck0, ck1};
+}
 
-  for (int i = t; i < ps * ps; i += blockDim.x) {    // padding rows / columns set to 0
+// Load the element-independent tables into the carved places (Psi with stride ps,
+// padding rows / columns 0).  Visible to all threads after the next barrier.
+__device__ __forceinline__ void stage_load_tables(const PcgGeom& g, double* Psi, int ps,
+                                                  const StageCommon& C) {
+  const int t = threadIdx.x, n1 = g.n1, N = g.N, m = g.m;
+  double* cb = const_cast<double*>(C.T.cb);
+  double* cd = const_cast<double*>(C.T.cd);
+  double* gw = const_cast<double*>(C.T.gw);
+  double* dL = const_cast<double*>(C.T.dL);
+  double* dR = const_cast<double*>(C.T.dR);
+  int* cs = const_cast<int*>(C.T.cs);
+  int* ck0 = const_cast<int*>(C.T.ck0);
+  int* ck1 = const_cast<int*>(C.T.ck1);
+  for (int i = t; i < ps * ps; i += blockDim.x) {
     const int r = i / ps, k = i - (i / ps) * ps;
     Psi[i] = (r < n1 && k < n1) ? g.Psi[r * n1 + k] : 0.0;
   }
@@ -624,6 +632,33 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   }
   for (int i = t; i < m; i += blockDim.x) gw[i] = g.gw[i];
   for (int i = t; i < N; i += blockDim.x) cs[i] = g.cs[i];
+}
+
+// sum over aligned groups of 8 lanes (DPP); every lane of a group returns the sum
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_mov<0xb1, 0xf, false>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4e, 0xf, false>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141, 0xf, false>(v);   // row_half_mirror
+  return v;
+}
+
+// Load the element's data and form the lifts: Fu = F_u, rv = F_v (the caller subtracts
+// S_K U).  `after_first_barrier` runs once the element data are in LDS (operator load
+// overlap).  Tables from stage_tables must be in place.
+template <int STAGE, typename F>
+__device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long e,
+                                               StageCommon& C, F&& after_first_barrier) {
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1, N = g.N, m = g.m, nq = g.nq;
+  const bool own = t < nn;
+  const double* cb = C.T.cb;
+  const double* cd = C.T.cd;
+  const double* gw = C.T.gw;
+  double* fc = const_cast<double*>(C.T.fc);
+  double* sig = C.sig;
+  const int* cs = C.T.cs;
+  const int* ck0 = C.T.ck0;
+  const int* ck1 = C.T.ck1;
   const double* fcg = a.el.face + e * 4 * nq * 3;
   for (int i = t; i < 4 * nq * 3; i += blockDim.x) fc[i] = fcg[i];
   C.ub = C.vb = C.yu = C.yv = C.xs0 = C.xm0 = C.wt = 0.0;
@@ -670,27 +705,46 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   // lifts: per face and node l along the face,
   //   cB[l] = sum_q wq sigma_u (K Nh)_normal B[q][l],  cD[l] = sum_q wq sigma_u (K Nh)_tangent D[q][l],
   //   cV[l] = sum_q wq c^2 s_J sigma_v B[q][l]
-  if (t < 4 * n1) {
-    const int f = t / n1, l = t - (t / n1) * n1;
+  // over the face cells k whose window holds l; 8 lanes per (face, node), lane kk takes
+  // cell ck0[l] + kk (at most p + 1 <= 8 cells), the lanes' parts are added by DPP.
+  for (int base = 0; base < 4 * n1 * 8; base += blockDim.x) {
+    const int fl = (base + t) >> 3, kk = (base + t) & 7;
     double cB = 0, cD = 0, cV = 0;
-    for (int k = ck0[l]; k <= ck1[l]; ++k) {
-      const int j = l - cs[k];
-      for (int qa = 0; qa < m; ++qa) {
-        const int id = f * nq + k * m + qa;
-        const double wq = gw[qa] / N;
-        const double* Fq = fc + id * 3;
-        const double kn = f < 2 ? Fq[0] : Fq[1], kt = f < 2 ? Fq[1] : Fq[0];
-        const double bj = cb[(k * m + qa) * m + j], dj = cd[(k * m + qa) * m + j];
-        cB += wq * sig[id * 2] * kn * bj;
-        cD += wq * sig[id * 2] * kt * dj;
-        cV += wq * Fq[2] * sig[id * 2 + 1] * bj;
+    int f = 0, l = 0;
+    if (fl < 4 * n1) {
+      f = fl / n1;
+      l = fl - f * n1;
+      const int k = ck0[l] + kk;
+      if (k <= ck1[l]) {
+        const int j = l - cs[k];
+#pragma unroll 2
+        for (int qa = 0; qa < m; ++qa) {
+          {
+            const int id = f * nq + k * m + qa;
+            const double wq = gw[qa] / N;
+            const double* Fq = fc + id * 3;
+            const double kn = f < 2 ? Fq[0] : Fq[1], kt = f < 2 ? Fq[1] : Fq[0];
+            const double bj = cb[(k * m + qa) * m + j], dj = cd[(k * m + qa) * m + j];
+            const double su = wq * sig[id * 2];
+            cB += su * kn * bj;
+            cD += su * kt * dj;
+            cV += wq * Fq[2] * sig[id * 2 + 1] * bj;
+          }
+        }
       }
     }
-    C.lines[(f * 4 + 0) * n1 + l] = cB;
-    C.lines[(f * 4 + 1) * n1 + l] = cD;
-    C.lines[(f * 4 + 2) * n1 + l] = cV;
+    cB = sum8(cB);
+    cD = sum8(cD);
+    cV = sum8(cV);
+    if (fl < 4 * n1 && kk == 0) {
+      C.lines[(f * 4 + 0) * n1 + l] = cB;
+      C.lines[(f * 4 + 1) * n1 + l] = cD;
+      C.lines[(f * 4 + 2) * n1 + l] = cV;
+    }
   }
   __syncthreads();
+  const double* dL = C.T.dL;
+  const double* dR = C.T.dR;
   if (own) {
     const int ix = t % n1, iy = t / n1;
     const double* LE = C.lines + 0 * 4 * n1;
@@ -759,13 +813,11 @@ __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long
 // ---------------------------------------------------------------------------------
 // Stage with the row-rectangle operator layout (any N, p; FULL or HALF).
 // ---------------------------------------------------------------------------------
-template <int STAGE>
-__device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long e) {
+__device__ __forceinline__ void pcg_stage_carve(const PcgStageArgs& a, PcgShared& W,
+                                                StageCommon& C) {
   extern __shared__ double shd[];
   const PcgGeom& g = a.g;
-  const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
-  const bool own = t < nn;
-  PcgShared W;
+  const int nn = g.nn;
   W.full = a.full;
   W.Q = a.full ? a.Q : 0;
   double* sp = shd;
@@ -782,18 +834,31 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
   // ints after all doubles
   int* ip = reinterpret_cast<int*>(shd + (a.full ? a.nnz_full : g.nst) + W.Q * nn + 8 * nn +
                                    common_doubles(g));
-  int* fo = ip;        ip += nn + 1;
-  int* ho = ip;        ip += nn + 1;
-  W.fo = fo;
-  W.ho = ho;
-  for (int i = t; i <= nn; i += blockDim.x) {
+  W.fo = ip;           ip += nn + 1;
+  W.ho = ip;           ip += nn + 1;
+  stage_carve(g, sp, ip, C);
+  W.red = C.red;
+}
+
+__device__ __forceinline__ void pcg_stage_load_tables(const PcgStageArgs& a, const PcgShared& W,
+                                                      const StageCommon& C) {
+  const PcgGeom& g = a.g;
+  int* fo = const_cast<int*>(W.fo);
+  int* ho = const_cast<int*>(W.ho);
+  for (int i = threadIdx.x; i <= g.nn; i += blockDim.x) {
     fo[i] = a.fo[i];
     ho[i] = g.rowoff[i];
   }
-  StageCommon C;
-  stage_prologue<STAGE>(a, e, sp, ip, W.Psi, n1, C,
-                        [&]() { op_load(g, W, a.el.S + e * g.nst, a.dst); });
-  W.red = C.red;
+  stage_load_tables(g, W.Psi, g.n1, C);
+}
+
+template <int STAGE>
+__device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long e,
+                                               PcgShared& W, StageCommon& C) {
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
+  const bool own = t < nn;
+  stage_prologue<STAGE>(a, e, C, [&]() { op_load(g, W, a.el.S + e * g.nst, a.dst); });
   // r = -S_K U + F_v   (op_apply starts with the operator / U complete: the barriers of
   // the prologue cover U and the operator load)
   {
@@ -1053,15 +1118,12 @@ __host__ __device__ inline size_t blk_lds_doubles(const PcgGeom& g, int nnz_full
   return (size_t)nnz_full + (size_t)g.nn * WB + 6 * NP * NP + common_doubles(g);
 }
 
-template <int STAGE, int N1C>
-__device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const long e) {
+template <int N1C>
+__device__ __forceinline__ void pcg2_stage_carve(const PcgStageArgs& a, BlockSolve<N1C>& W,
+                                                 StageCommon& C) {
   extern __shared__ double shd[];
-  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  constexpr int NP = N1C + 1, nn = N1C * N1C;
   const PcgGeom& g = a.g;
-  const int t = threadIdx.x;
-  const bool own = t < nn;
-  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
-  BlockSolve<N1C> W;
   W.K = a.blk_K;
   W.CH = a.blk_CH;
   W.WB = a.blk_WB;
@@ -1076,23 +1138,39 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
   W.Z = sp;    sp += NP * NP;
   W.DI = sp;   sp += NP * NP;
   W.Psi = sp;  sp += NP * NP;
-  double* zero_from = W.R;
   int* ip = reinterpret_cast<int*>(shd + blk_lds_doubles<N1C>(g, a.nnz_full, W.WB));
-  int* boff = ip;  ip += nn;
-  int* jc = ip;    ip += W.K;
-  W.boff = boff;
-  W.jc = jc;
+  W.boff = ip;  ip += nn;
+  W.jc = ip;    ip += W.K;
+  stage_carve(g, sp, ip, C);
+}
+
+template <int N1C>
+__device__ __forceinline__ void pcg2_stage_load_tables(const PcgStageArgs& a,
+                                                       const BlockSolve<N1C>& W,
+                                                       const StageCommon& C) {
+  constexpr int NP = N1C + 1, nn = N1C * N1C;
+  const int t = threadIdx.x;
+  int* boff = const_cast<int*>(W.boff);
+  int* jc = const_cast<int*>(W.jc);
   for (int i = t; i < nn; i += blockDim.x) boff[i] = a.blk_off[i];
   for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
-  StageCommon C;
+  for (int i = t; i < 5 * NP * NP; i += blockDim.x) W.R[i] = 0.0;   // R U T Z DI (padding)
+  stage_load_tables(a.g, W.Psi, NP, C);
+}
+
+template <int STAGE, int N1C>
+__device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const long e,
+                                                BlockSolve<N1C>& W, StageCommon& C) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
   double* const Aop = W.A;
   const double* const Shalf = a.el.S + e * g.nst;
   const int* const bdst = a.blk_dst;
   const int nst = g.nst;
-  stage_prologue<STAGE>(a, e, sp, ip, W.Psi, NP, C, [zero_from, Aop, Shalf, bdst, nst]() {
-    for (int i = threadIdx.x; i < 5 * NP * NP; i += blockDim.x) zero_from[i] = 0.0;  // R U T Z DI
-    blk_load(nst, Aop, Shalf, bdst);
-  });
+  stage_prologue<STAGE>(a, e, C, [Aop, Shalf, bdst, nst]() { blk_load(nst, Aop, Shalf, bdst); });
   // r = -S_K U + F_v   (operator, tables, U complete after the prologue's barriers)
   if (own) W.U[pidx] = C.U[t];
   __syncthreads();
@@ -1143,34 +1221,38 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
 // At most 768 threads (12 waves, 3 per SIMD), so that a lane may hold 170 VGPRs.
 constexpr int kBlkMaxThreads = 768;
 
-template <int STAGE, int N1C>
-__global__ __launch_bounds__(kBlkMaxThreads) void k_pcg2_stage(PcgStageArgs a) {
-  pcg2_stage_elem<STAGE, N1C>(a, blockIdx.x);
-}
-
-template <int STAGE>
-__global__ __launch_bounds__(1024) void k_pcg_stage(PcgStageArgs a) {
-  pcg_stage_elem<STAGE>(a, blockIdx.x);
-}
-
 // Grouped, persistent form over the elements of several problems (each with its own
 // geometry and LDS layout, all fitting the launch's LDS size and block size).  Problem i
 // owns elements [el_start[i], el_start[i+1]); block b takes b, b + gridDim.x, ...
-// N1C > 0: every member has N + 1 = N1C (column-block members run that kernel body).
+// N1C > 0: every member uses the column-block layout with N + 1 = N1C; N1C = 0: every
+// member uses the row layout.
 template <int STAGE, int N1C>
 __global__ __launch_bounds__(N1C > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_group(
     const PcgStageArgs* __restrict__ args,
                                                           const long* __restrict__ el_start,
                                                           int nprob) {
   const long total = el_start[nprob];
-  int pi = 0;
+  int pi = 0, cur = -1;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
     while (pi + 1 < nprob && b >= el_start[pi + 1]) ++pi;
+    const PcgStageArgs& a = args[pi];
+    StageCommon C;
     if constexpr (N1C > 0) {
-      if (args[pi].v2) pcg2_stage_elem<STAGE, N1C>(args[pi], b - el_start[pi]);
-      else pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+      BlockSolve<N1C> W;
+      pcg2_stage_carve<N1C>(a, W, C);
+      if (pi != cur) {               // a new problem: its tables
+        pcg2_stage_load_tables<N1C>(a, W, C);
+        cur = pi;
+      }
+      pcg2_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
     } else {
-      pcg_stage_elem<STAGE>(args[pi], b - el_start[pi]);
+      PcgShared W;
+      pcg_stage_carve(a, W, C);
+      if (pi != cur) {
+        pcg_stage_load_tables(a, W, C);
+        cur = pi;
+      }
+      pcg_stage_elem<STAGE>(a, b - el_start[pi], W, C);
     }
     __syncthreads();   // the next element reuses the LDS
   }
@@ -1222,6 +1304,25 @@ __global__ __launch_bounds__(256) void k_sum_part(const double* __restrict__ par
 }
 
 // ---------------------------------------------------------------------------------
+// Blocks of a persistent launch: every CU filled to the kernel's occupancy, at most one
+// block per element.
+static unsigned persistent_grid(const void* kernel, int threads, size_t lds, long nel) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 256;
+  }
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, lds) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  const long g = (long)ncu * occ;
+  return (unsigned)(nel < g ? nel : g);
+}
+
 static int threads_for(int nn) {
   int b = ((nn + 63) / 64) * 64;
   return b < 256 ? 256 : b;
@@ -1255,25 +1356,6 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
   const size_t sh = (2 * g.nn + 4 * g.n1) * sizeof(double);
   hipLaunchKernelGGL(k_pcg_traces, dim3((unsigned)nel), dim3(threads_for(g.nn)), sh, st, g, el, U,
                      V, tr, nel);
-  return hipGetLastError();
-}
-
-template <int STAGE>
-static hipError_t launch_stage_k(const PcgStageArgs& a0, hipStream_t st) {
-  PcgStageArgs a = a0;
-  a.full = stage_full(a.g);
-  a.Q = full_parts(a.g);
-  a.nnz_full = full_nnz(a.g);
-  const size_t sh = stage_lds(a.g, a.full);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pcg_stage<STAGE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const int threads = a.full ? 1024 : threads_for(a.g.nn);
-  hipLaunchKernelGGL(k_pcg_stage<STAGE>, dim3((unsigned)a.nel), dim3(threads), sh, st, a);
   return hipGetLastError();
 }
 
@@ -1419,52 +1501,34 @@ hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, c
   }
 }
 
-template <int STAGE, int N1C>
-static hipError_t launch_blk_k(const PcgStageArgs& a, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pcg2_stage<STAGE, N1C>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const size_t sh = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
-  constexpr int SP = 4 * N1C * N1C <= 1024 ? 4 : 2;
-  if (sh > 160 * 1024 || a.blk_threads > kBlkMaxThreads || a.blk_threads < N1C * a.blk_K ||
-      a.blk_threads < SP * N1C * N1C)
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_pcg2_stage<STAGE, N1C>), dim3((unsigned)a.nel), dim3(a.blk_threads), sh, st, a);
-  return hipGetLastError();
-}
-
 template <int STAGE>
-static hipError_t launch_blk_n1(const PcgStageArgs& a, hipStream_t st) {
-  switch (a.g.n1) {
-    case 9: return launch_blk_k<STAGE, 9>(a, st);
-    case 13: return launch_blk_k<STAGE, 13>(a, st);
-    case 17: return launch_blk_k<STAGE, 17>(a, st);
-    default: return hipErrorInvalidValue;
+static const void* group_kernel_n1(int key) {
+  switch (key) {
+    case 9: return (const void*)k_pcg_stage_group<STAGE, 9>;
+    case 13: return (const void*)k_pcg_stage_group<STAGE, 13>;
+    case 17: return (const void*)k_pcg_stage_group<STAGE, 17>;
+    default: return (const void*)k_pcg_stage_group<STAGE, 0>;
   }
 }
 
-hipError_t launch_pcg_stage(int stage, const PcgStageArgs& a, hipStream_t st) {
-  if (a.v2 && a.nel > 0) {
-    switch (stage) {
-      case 1: return launch_blk_n1<1>(a, st);
-      case 2: return launch_blk_n1<2>(a, st);
-      case 3: return launch_blk_n1<3>(a, st);
-      default: return launch_blk_n1<4>(a, st);
-    }
+unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel) {
+  const void* k = stage == 1 ? group_kernel_n1<1>(key) : stage == 2 ? group_kernel_n1<2>(key)
+                : stage == 3 ? group_kernel_n1<3>(key) : group_kernel_n1<4>(key);
+  return persistent_grid(k, threads, lds, nel);
+}
+
+int pcg_group_key(const PcgStageArgs& a) { return a.v2 ? a.g.n1 : 0; }
+
+int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds) {
+  if (a.v2) {
+    *threads = a.blk_threads;
+    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
+  } else {
+    if (a.fo == nullptr || a.dst == nullptr) return 0;
+    *threads = stage_full(a.g) ? 1024 : threads_for(a.g.nn);
+    if (!pcg_args_shape(a, *threads, lds)) return 0;
   }
-  if (a.nel == 0) return hipSuccess;
-  if (pcg_stage_lds_bytes(a.g, a.mixed) > 160 * 1024) return hipErrorInvalidValue;
-  if (a.fo == nullptr || a.dst == nullptr) return hipErrorInvalidValue;
-  switch (stage) {
-    case 1: return launch_stage_k<1>(a, st);
-    case 2: return launch_stage_k<2>(a, st);
-    case 3: return launch_stage_k<3>(a, st);
-    default: return launch_stage_k<4>(a, st);
-  }
+  return *lds <= 160 * 1024;
 }
 
 hipError_t launch_pcg_energy(const PcgGeom& g, const PcgElem& el, const double* U, const double* V,

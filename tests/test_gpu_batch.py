@@ -87,7 +87,7 @@ def test_batch_equals_solo_runs_and_rebuilds_on_new_dt():
     b.tune(dts)
     plan = b.plan()
     _say(plan.split("candidates:")[0])
-    assert "fdm n1=9" in plan and "pcg n1=13" in plan
+    assert "fdm n1=9" in plan and "pcg blocks n1=13" in plan
     b.run(dts, 3)
     times = b.step_times()
     assert len(times) == 3 and all(t > 0 for t in times)
