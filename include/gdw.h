@@ -50,8 +50,12 @@ typedef enum {
 typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1 } gdw_flux;
 
 /* Arithmetic of the time loop.  GDW_FP64: state, tables and arithmetic in FP64.
- * GDW_MIXED_FP32: state and tables stored and computed in FP32; the eigenbasis is
- * built and the energy is accumulated in FP64. */
+ * GDW_MIXED_FP32, constant-coefficient path: state and tables stored and computed in FP32;
+ * the eigenbasis is built and the energy is accumulated in FP64.  GDW_MIXED_FP32, PCG
+ * path: the state stays FP64; the element operator is split into FP32 parts
+ * hi = fl32(A), lo = fl32(A - hi); the inner PCG iterations use hi, and every solve is
+ * refined with FP64 residuals b - (hi + lo) x until the FP64 residual meets pcg_rtol
+ * (requires N + 1 in {9, 13, 17}; else EUNSUPPORTED). */
 typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1 } gdw_precision;
 
 /* Local solve.  FDM: simultaneous diagonalisation (Sec. 3.2), constant c^2 on
@@ -143,6 +147,8 @@ typedef struct {
   double mean_it_M;          /* PCG: mean iterations per M_J solve (dV/dt)          */
   int max_it_S, max_it_M;    /* PCG: largest single-solve counts                   */
   long long solves;          /* PCG: element solves of each kind since set_state   */
+  double mean_refine;        /* PCG, GDW_MIXED_FP32: mean FP64 refinement sweeps per
+                                solve (residual evaluations after the first)         */
 } gdw_stats;
 
 /* Counters of the context.  Synchronises `stream`.  Returns ENOCONV (with

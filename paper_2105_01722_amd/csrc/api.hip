@@ -35,7 +35,8 @@ static void free_all(gdw_ctx* c) {
   F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh);
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
-  F(c->el.S); F(c->el.M); F(c->el.S32); F(c->el.M32); F(c->el.w); F(c->el.sc); F(c->el.face);
+  F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
+  F(c->el.w); F(c->el.sc); F(c->el.face);
   F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
 }
@@ -75,7 +76,6 @@ static gdw_status validate(const gdw_desc* d) {
   }
   const bool pcg = d->solver == GDW_SOLVE_PCG || general;
   if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
-  if (pcg && d->precision != GDW_FP64) { set_error("the PCG path runs in FP64 in this build"); return GDW_EUNSUPPORTED; }
   if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
   if (nel > 4.0e9) { set_error("problem too large"); return GDW_EINVAL; }
@@ -304,12 +304,17 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   {
     // column-block layout of the faster stage kernel, where it applies
     std::vector<int> boff, bdst, jc;
+    const int mixed = d->precision == GDW_MIXED_FP32;
     if (pcg_block_tables(g, rowoff, boff, bdst, jc, &c->blk_K, &c->blk_CH, &c->blk_WB,
-                         &c->blk_nnz, &c->blk_threads)) {
+                         &c->blk_nnz, &c->blk_threads, mixed)) {
       if ((s = own_upload<int>(c, 15, boff, &c->blk_off)) != GDW_OK) return s;
       if ((s = own_upload<int>(c, 16, bdst, &c->blk_dst)) != GDW_OK) return s;
       if ((s = own_upload<int>(c, 17, jc, &c->blk_jc)) != GDW_OK) return s;
       c->blk_v2 = 1;
+    } else if (mixed) {
+      set_error("mixed-precision PCG needs N + 1 in {9, 13, 17} and an FP32 element operator "
+                "that fits a workgroup's LDS");
+      return GDW_EUNSUPPORTED;
     }
   }
   if (pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
@@ -335,7 +340,16 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   }
   GDW_HIP(hipMalloc(&c->xS, nodal));
   GDW_HIP(hipMalloc(&c->xM, nodal));
-  GDW_HIP(hipMalloc(&c->its, (size_t)nel * 4 * sizeof(int)));
+  GDW_HIP(hipMalloc(&c->its, (size_t)nel * kItsPer * sizeof(int)));
+  if (d->precision == GDW_MIXED_FP32) {
+    const size_t nb = (size_t)nel * c->blk_nnz * sizeof(float);
+    GDW_HIP(hipMalloc(&c->el.Shi, nb));
+    GDW_HIP(hipMalloc(&c->el.Slo, nb));
+    if (d->mapped) {
+      GDW_HIP(hipMalloc(&c->el.Mhi, nb));
+      GDW_HIP(hipMalloc(&c->el.Mlo, nb));
+    }
+  }
   GDW_HIP(hipMalloc(&c->d_pargs, 4 * sizeof(PcgStageArgs)));
   GDW_HIP(hipMalloc(&c->d_pel, 2 * sizeof(long)));
   {
@@ -410,6 +424,13 @@ extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* 
   GDW_HIP(hipMemcpyAsync(c->c2n, Cd, (size_t)c->nel * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
   GDW_HIP(launch_assemble(c->g, Xd, Yd, Cd, c->el, c->nel, st));
   GDW_HIP(launch_face_geom(c->g, Xd, Yd, Cd, c->el, c->nel, st));
+  if (c->el.Shi) {
+    GDW_HIP(launch_split_hilo(c->el.S, c->blk_dst, c->g.nst, c->blk_nnz, c->nel, c->el.Shi,
+                              c->el.Slo, st));
+    if (c->el.M)
+      GDW_HIP(launch_split_hilo(c->el.M, c->blk_dst, c->g.nst, c->blk_nnz, c->nel, c->el.Mhi,
+                                c->el.Mlo, st));
+  }
   c->have_coeff = 1;
   return GDW_OK;
 }
@@ -434,7 +455,7 @@ extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V
     GDW_HIP(hipMemcpyAsync(c->Y[0][1], V, nodal, hipMemcpyDeviceToDevice, st));
     GDW_HIP(hipMemsetAsync(c->xS, 0, nodal, st));
     GDW_HIP(hipMemsetAsync(c->xM, 0, nodal, st));
-    GDW_HIP(hipMemsetAsync(c->its, 0, (size_t)c->nel * 4 * sizeof(int), st));
+    GDW_HIP(hipMemsetAsync(c->its, 0, (size_t)c->nel * kItsPer * sizeof(int), st));
     GDW_HIP(hipMemsetAsync(c->fail, 0x7f, sizeof(int), st));
     c->trc = 0;
     c->stages_since_state = 0;
@@ -531,7 +552,7 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.rtol = c->rtol;
   a.rtol_inner = 1e-6;
   a.maxit = c->maxit;
-  a.mixed = 0;
+  a.mixed = c->d.precision == GDW_MIXED_FP32 ? 1 : 0;
   a.fo = c->fo;
   a.dst = c->dst;
   if (c->blk_v2) {
@@ -671,19 +692,21 @@ extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
   int fail = kFailNone;
   std::vector<int> its;
   if (c->solver == GDW_SOLVE_PCG) {
-    its.resize((size_t)c->nel * 4);
+    its.resize((size_t)c->nel * kItsPer);
     GDW_HIP(hipMemcpyAsync(its.data(), c->its, its.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     GDW_HIP(hipMemcpyAsync(&fail, c->fail, sizeof(int), hipMemcpyDeviceToHost, st));
   }
   GDW_HIP(hipStreamSynchronize(st));
   if (c->solver == GDW_SOLVE_PCG) {
-    long long sS = 0, sM = 0;
+    long long sS = 0, sM = 0, sw = 0;
     int mS = 0, mM = 0;
     for (long e = 0; e < c->nel; ++e) {
-      sS += its[e * 4];
-      sM += its[e * 4 + 1];
-      mS = std::max(mS, its[e * 4 + 2]);
-      mM = std::max(mM, its[e * 4 + 3]);
+      const int* it = &its[(size_t)e * kItsPer];
+      sS += it[0];
+      sM += it[1];
+      mS = std::max(mS, it[2]);
+      mM = std::max(mM, it[3]);
+      sw += it[4] + it[5];
     }
     const long long solves = c->stages_since_state * c->nel;
     out->solves = solves;
@@ -691,6 +714,7 @@ extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
     out->mean_it_M = solves ? (double)sM / solves : 0.0;
     out->max_it_S = mS;
     out->max_it_M = mM;
+    out->mean_refine = solves ? (double)sw / (2.0 * solves) : 0.0;
     if (fail != kFailNone) {
       out->fail_elem = fail;
       set_error("a PCG element solve reached pcg_maxit");

@@ -241,7 +241,7 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
     const size_t nodal = (size_t)x->nel * x->g.nn * sizeof(double);
     PcgScratch p{};
     if (hipMalloc(&p.xS, nodal) != hipSuccess || hipMalloc(&p.xM, nodal) != hipSuccess ||
-        hipMalloc(&p.its, (size_t)x->nel * 4 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&p.its, (size_t)x->nel * kItsPer * sizeof(int)) != hipSuccess ||
         hipMalloc(&p.fail, sizeof(int)) != hipSuccess) {
       scr.push_back(p);
       s = GDW_ENOMEM;
@@ -251,7 +251,7 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
     scr.push_back(p);
     (void)hipMemcpyAsync(p.xS, x->xS, nodal, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(p.xM, x->xM, nodal, hipMemcpyDeviceToDevice, st);
-    (void)hipMemsetAsync(p.its, 0, (size_t)x->nel * 4 * sizeof(int), st);
+    (void)hipMemsetAsync(p.its, 0, (size_t)x->nel * kItsPer * sizeof(int), st);
     (void)hipMemsetAsync(p.fail, 0x7f, sizeof(int), st);
   }
   float best = 1e30f;
@@ -282,7 +282,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
             }, st, 1, &ms);
         if (s != GDW_OK) break;
         std::snprintf(buf, sizeof buf, "  pcg %s%d threads=%d grid=%u lds=%zu: %.4f ms\n",
-                      c.n1 ? "blocks n1=" : "rows ", c.n1, thr, grid, lds, ms);
+                      c.n1 > 32 ? "mixed n1=" : c.n1 ? "blocks n1=" : "rows ", c.n1 & 31, thr,
+                      grid, lds, ms);
         log += buf;
         if (ms < best) { best = ms; best_thr = thr; best_grid = grid; best_lds = lds; }
       }
@@ -355,7 +356,8 @@ static void make_plan(gdw_batch* b, const std::string& log) {
   }
   for (auto& c : b->pcg) {
     std::snprintf(buf, sizeof buf, "pcg %s%d: %zu problems, threads=%d grid=%u lds=%zu\n",
-                  c.n1 ? "blocks n1=" : "rows ", c.n1, c.members.size(), c.threads, c.grid, c.lds);
+                  c.n1 > 32 ? "mixed n1=" : c.n1 ? "blocks n1=" : "rows ", c.n1 & 31,
+                  c.members.size(), c.threads, c.grid, c.lds);
     p += buf;
   }
   b->plan = p + "candidates:\n" + log;
@@ -391,7 +393,7 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
       const gdw_ctx* c = b->ctx[i];
       if (c->solver == GDW_SOLVE_PCG) {
         // kernel family: N + 1 for the column-block layout, 0 for the row layout
-        const int fam = c->blk_v2 ? c->n1 : 0;
+        const int fam = c->blk_v2 ? c->n1 + (c->d.precision == GDW_MIXED_FP32 ? 32 : 0) : 0;
         auto key = std::make_pair(fam, 0);
         if (!pk.count(key)) { pk[key] = b->pcg.size(); b->pcg.emplace_back(); b->pcg.back().n1 = fam; }
         b->pcg[pk[key]].members.push_back(i);

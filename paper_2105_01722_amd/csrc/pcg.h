@@ -8,6 +8,10 @@
 
 namespace gdw {
 
+// Per-element PCG counters: sum of S_hat iterations, sum of M_J iterations, largest of each,
+// sum of refinement sweeps of each (mixed precision).
+constexpr int kItsPer = 6;
+
 // Tables shared by every element of a problem (device pointers).
 struct PcgGeom {
   int N, p, n1, nn, m, nq, nst;
@@ -29,8 +33,10 @@ struct PcgGeom {
 struct PcgElem {
   double* S;            // [nel][nst] upper half of S_K
   double* M;            // [nel][nst] upper half of M_J (mapped meshes only)
-  float* S32;           // [nel][nst] FP32 copy of S_K (mixed precision)
-  float* M32;           // [nel][nst] FP32 copy of M_J (mixed precision, mapped)
+  float* Shi;           // [nel][nnz_blk] mixed precision: fl32(S_K), column-block layout
+  float* Slo;           // [nel][nnz_blk] fl32(S_K - Shi)
+  float* Mhi;           // the same for M_J (mapped meshes)
+  float* Mlo;
   double* w;            // [nel][nn] int phi_i J
   double* sc;           // [nel][8]: kappa/area, kbar_rr, kbar_ss, kappa*area, area, int c^2 J
   double* face;         // [nel][4][nq][3]: (K Nh)_r, (K Nh)_s, c^2 s_J at face points
@@ -59,7 +65,7 @@ struct PcgStageArgs {
   int mapped;
   double dt, alpha, beta, tau, rtol, rtol_inner;
   int maxit;
-  int mixed;            // 1: FP32 inner PCG with FP64 residual refinement
+  int mixed;            // 1: FP32 operator for the inner PCG, FP64 residual refinement
   const int* fo;        // [nn+1] row starts of the full stencil rectangles
   const int* dst;       // [nst][2] full-rectangle positions (i,j), (j,i) of upper entry h
   int full, Q, nnz_full;  // set by the launcher: LDS layout of the operator
@@ -75,7 +81,10 @@ struct PcgStageArgs {
 // (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
                      std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
-                     int* nnz, int* threads);
+                     int* nnz, int* threads, int mixed);
+// FP32 hi / lo split of the upper-half operators into the column-block layout.
+hipError_t launch_split_hilo(const double* half, const int* dst, int nst, int nnz, long nel,
+                             float* hi, float* lo, hipStream_t st);
 
 hipError_t launch_assemble(const PcgGeom& g, const double* X, const double* Y, const double* C2,
                            const PcgElem& el, long nel, hipStream_t st);

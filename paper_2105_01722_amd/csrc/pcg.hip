@@ -311,6 +311,24 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, lo
   if (i < n) b[i] = (float)a[i];
 }
 
+// Upper-half FP64 operators [nel][nst] -> FP32 block layout hi = fl32(a), lo = fl32(a - hi),
+// both positions (i, j) and (j, i) of entry h (dst[2h], dst[2h+1]).
+__global__ void k_split_hilo(const double* __restrict__ half, const int* __restrict__ dst, int nst,
+                             int nnz, long nel, float* __restrict__ hi, float* __restrict__ lo) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nel * nst) return;
+  const long e = id / nst;
+  const int h = (int)(id - e * nst);
+  const double v = half[id];
+  const float vh = (float)v;
+  const float vl = (float)(v - (double)vh);
+  const int2 d2 = reinterpret_cast<const int2*>(dst)[h];
+  hi[e * nnz + d2.x] = vh;
+  hi[e * nnz + d2.y] = vh;
+  lo[e * nnz + d2.x] = vl;
+  lo[e * nnz + d2.y] = vl;
+}
+
 // ---------------------------------------------------------------------------------
 // (a, v) traces at the face points of a nodal state held in LDS (U, V), written to
 // tr[4][nq][2].  G: 4*n1 doubles of scratch.
@@ -572,6 +590,7 @@ __device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const doubl
 // ---------------------------------------------------------------------------------
 struct StageCommon {
   double *U, *V, *Fu, *rv, *lamr, *lines, *red, *sig;
+  bool gtab;                                 // cb, cd, face data read from global memory
   FaceTabs T;
   double ub, vb, yu, yv, xs0, xm0, wt;      // owner thread t < nn
   double cw, kbr, kbs, d00, area;
@@ -600,6 +619,34 @@ __device__ __forceinline__ void stage_carve(const PcgGeom& g, double*& sp, int*&
   int* ck0 = ip;   ip += n1;
   int* ck1 = ip;   ip += n1;
   C.T = FaceTabs{cb, cd, gw, dL, dR, fc, cs, ck0, ck1};
+  C.gtab = false;
+}
+
+// Smaller common part: cb, cd and the face data stay in global memory (read through the
+// caches) and sig lives in the caller's region `sigbuf` (4 nq * 2 doubles).
+__device__ __forceinline__ void stage_carve_small(const PcgGeom& g, double*& sp, int*& ip,
+                                                  double* sigbuf, StageCommon& C) {
+  const int nn = g.nn, n1 = g.n1, N = g.N, m = g.m;
+  C.U = sp;        sp += nn;
+  C.V = sp;        sp += nn;
+  C.Fu = sp;       sp += nn;
+  C.rv = sp;       sp += nn;
+  C.lamr = sp;     sp += n1;
+  double* gw = sp; sp += m;
+  double* dL = sp; sp += n1;
+  double* dR = sp; sp += n1;
+  C.lines = sp;    sp += 16 * n1;
+  C.red = sp;      sp += 64;
+  C.sig = sigbuf;
+  int* cs = ip;    ip += N;
+  int* ck0 = ip;   ip += n1;
+  int* ck1 = ip;   ip += n1;
+  C.T = FaceTabs{g.cb, g.cd, gw, dL, dR, nullptr, cs, ck0, ck1};
+  C.gtab = true;
+}
+
+__host__ __device__ inline size_t common_small_doubles(const PcgGeom& g) {
+  return (size_t)4 * g.nn + g.n1 + g.m + 2 * g.n1 + 16 * g.n1 + 64;
 }
 
 // Load the element-independent tables into the carved places (Psi with stride ps,
@@ -619,10 +666,11 @@ __device__ __forceinline__ void stage_load_tables(const PcgGeom& g, double* Psi,
     const int r = i / ps, k = i - (i / ps) * ps;
     Psi[i] = (r < n1 && k < n1) ? g.Psi[r * n1 + k] : 0.0;
   }
-  for (int i = t; i < N * m * m; i += blockDim.x) {
-    cb[i] = g.cb[i];
-    cd[i] = g.cd[i];
-  }
+  if (!C.gtab)
+    for (int i = t; i < N * m * m; i += blockDim.x) {
+      cb[i] = g.cb[i];
+      cd[i] = g.cd[i];
+    }
   for (int i = t; i < n1; i += blockDim.x) {
     C.lamr[i] = g.lamr[i];
     dL[i] = g.dL[i];
@@ -654,13 +702,18 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   const double* cb = C.T.cb;
   const double* cd = C.T.cd;
   const double* gw = C.T.gw;
-  double* fc = const_cast<double*>(C.T.fc);
   double* sig = C.sig;
   const int* cs = C.T.cs;
   const int* ck0 = C.T.ck0;
   const int* ck1 = C.T.ck1;
   const double* fcg = a.el.face + e * 4 * nq * 3;
-  for (int i = t; i < 4 * nq * 3; i += blockDim.x) fc[i] = fcg[i];
+  if (C.gtab) {
+    C.T.fc = fcg;
+  } else {
+    double* fcl = const_cast<double*>(C.T.fc);
+    for (int i = t; i < 4 * nq * 3; i += blockDim.x) fcl[i] = fcg[i];
+  }
+  const double* fc = C.T.fc;
   C.ub = C.vb = C.yu = C.yv = C.xs0 = C.xm0 = C.wt = 0.0;
   if (own) {
     C.ub = a.in_u[e * nn + t];
@@ -768,7 +821,7 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
 template <int STAGE>
 __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long e,
                                                const StageCommon& C, double y, double z,
-                                               int itS, int itM) {
+                                               int itS, int itM, int swS = 0, int swM = 0) {
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn;
   const bool own = t < nn;
@@ -801,11 +854,13 @@ __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long
   __syncthreads();
   face_traces_lds(g, C.T, C.U, C.V, C.lines, a.tr_out + e * 4 * g.nq * 2);
   if (t == 0) {
-    int* its = a.its + e * 4;
+    int* its = a.its + e * kItsPer;
     its[0] += itS > a.maxit ? a.maxit : itS;
     its[1] += itM > a.maxit ? a.maxit : itM;
     if (itS > its[2]) its[2] = itS;
     if (itM > its[3]) its[3] = itM;
+    its[4] += swS;
+    its[5] += swM;
     if (itS > a.maxit || itM > a.maxit) atomicMin(a.fail, (int)e);
   }
 }
@@ -924,15 +979,18 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
 // on 2 x 2 output blocks per thread without bounds tests.  The PCG recurrence is the
 // single-reduction form of Chronopoulos and Gear: one workgroup reduction per iteration.
 // ---------------------------------------------------------------------------------
-template <int N1C>
+template <int N1C, typename TA = double>
 struct BlockSolve {
-  double *A, *P, *R, *U, *T, *Z, *DI, *Psi;
+  TA* A;                                     // operator (block layout)
+  double *P;                                 // row partials
+  double *R, *U, *T, *Z, *DI, *Psi;
   const int *boff, *jc;
   int K, CH, WB, p, N;
 };
 
-template <int N1C>
-__device__ __forceinline__ double blk_apply(const BlockSolve<N1C>& W, const double* __restrict__ x) {
+template <int N1C, typename TA>
+__device__ __forceinline__ double blk_apply(const BlockSolve<N1C, TA>& W,
+                                            const double* __restrict__ x) {
   constexpr int n1 = N1C, NP = N1C + 1, WM = N1C < 15 ? N1C : 15;
   const int t = threadIdx.x;
   if (t < n1 * W.K) {
@@ -945,14 +1003,14 @@ __device__ __forceinline__ double blk_apply(const BlockSolve<N1C>& W, const doub
     double xs[WM];
 #pragma unroll
     for (int q = 0; q < WM; ++q) xs[q] = q < wx ? x[jy * NP + lox + q] : 0.0;
-    const double* Ab = W.A + W.boff[jy * n1 + ix] + i0 * wx;
+    const TA* Ab = W.A + W.boff[jy * n1 + ix] + i0 * wx;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (i < ni) {
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < WM; ++q)
-          if (q < wx) acc += Ab[i * wx + q] * xs[q];
+          if (q < wx) acc += (double)Ab[i * wx + q] * xs[q];
         const int iy = loy + i0 + i;
         W.P[(iy * n1 + ix) * W.WB + (jy - st_lo(iy, W.p))] = acc;
       }
@@ -973,8 +1031,8 @@ __device__ __forceinline__ double blk_apply(const BlockSolve<N1C>& W, const doub
 // four 1D transforms gives every output (a, b) to SP adjacent lanes (one quad), which
 // split its sum over the contracted index and combine the parts with DPP lane moves, so
 // that one batch of LDS loads per lane covers a phase.
-template <int N1C>
-__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C>& W, const double* __restrict__ R,
+template <int N1C, typename TA>
+__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA>& W, const double* __restrict__ R,
                                 double* __restrict__ out) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
   constexpr int SP = 4 * nn <= 1024 ? 4 : 2;
@@ -1032,17 +1090,22 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C>& W, const double*
 }
 
 // PCG (single-reduction recurrence) on (A_op + cw w w^T) x = b; owner thread t < nn holds
-// x (in/out, warm start on entry), b and w.  Iteration count as pcg_solve.
-template <int N1C>
-__device__ __forceinline__ int blk_solve(const BlockSolve<N1C>& W, double* red, double& x, double bval, double cw,
-                         double wt, double rtol, int maxit) {
+// x (in/out, warm start on entry), b and w.  Iteration count as pcg_solve.  zero_start:
+// x = 0 on entry (the first product is skipped).
+template <int N1C, typename TA, typename App>
+__device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA>& W, App&& apply, double* red,
+                                           double& x, double bval, double cw, double wt,
+                                           double rtol, int maxit, bool zero_start) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
   const int t = threadIdx.x;
   const bool own = t < nn;
   const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
-  if (own) W.U[pidx] = x;
-  __syncthreads();
-  const double ax = blk_apply(W, W.U);
+  double ax = 0.0;
+  if (!zero_start) {
+    if (own) W.U[pidx] = x;
+    __syncthreads();
+    ax = apply(W.U);
+  }
   double s2[2] = {own ? wt * x : 0.0, own ? bval * bval : 0.0};
   block_sum<2>(s2, red, nn);
   const double bb = s2[1];
@@ -1055,7 +1118,7 @@ __device__ __forceinline__ int blk_solve(const BlockSolve<N1C>& W, double* red, 
   __syncthreads();
   blk_pinv(W, W.R, W.U);
   double u = own ? W.U[pidx] : 0.0;
-  double q = blk_apply(W, W.U);
+  double q = apply(W.U);
   double s4[4] = {r * u, q * u, wt * u, r * r};
   block_sum<4>(s4, red, nn);
   const double tol2 = rtol * rtol * bb;
@@ -1070,7 +1133,7 @@ __device__ __forceinline__ int blk_solve(const BlockSolve<N1C>& W, double* red, 
     __syncthreads();
     blk_pinv(W, W.R, W.U);
     u = own ? W.U[pidx] : 0.0;
-    q = blk_apply(W, W.U);
+    q = apply(W.U);
     double sr[4] = {r * u, q * u, wt * u, r * r};
     block_sum<4>(sr, red, nn);
     if (sr[3] <= tol2) return it;
@@ -1083,6 +1146,14 @@ __device__ __forceinline__ int blk_solve(const BlockSolve<N1C>& W, double* red, 
     gam = gn;
   }
   return maxit + 1;
+}
+
+template <int N1C, typename TA>
+__device__ __forceinline__ int blk_solve(const BlockSolve<N1C, TA>& W, double* red, double& x,
+                                         double bval, double cw, double wt, double rtol, int maxit,
+                                         bool zero_start = false) {
+  return blk_solve_g(W, [&W](const double* v) { return blk_apply(W, v); }, red, x, bval, cw, wt,
+                     rtol, maxit, zero_start);
 }
 
 // Copy one element operator from its HBM upper half into the block layout.
@@ -1118,6 +1189,108 @@ __host__ __device__ inline size_t blk_lds_doubles(const PcgGeom& g, int nnz_full
   return (size_t)nnz_full + (size_t)g.nn * WB + 6 * NP * NP + common_doubles(g);
 }
 
+// ---------------------------------------------------------------------------------
+// Mixed precision (FP32 operator for the inner iterations, FP64 residual refinement).
+//
+// The operator is split as A = A_hi + A_lo, A_hi = fl32(A), A_lo = fl32(A - A_hi) (their sum
+// holds A to about 2^-48).  The inner PCG runs on A_hi, kept in LDS in FP32 (half the
+// bytes of the FP64 operator, so that two elements fit a CU); the outer loop forms the
+// true residual b - (A_hi + A_lo) x in FP64 with A_lo read from global memory and solves
+// for the correction until the FP64 residual meets rtol.
+// ---------------------------------------------------------------------------------
+constexpr int kMaxSweeps = 8;
+constexpr double kInnerTol = 1e-6;
+
+// region sizes (in doubles) of the mixed layout
+template <int N1C>
+__host__ __device__ inline int mix_a_doubles(int nnz) { return (nnz + 1) / 2; }
+template <int N1C>
+__host__ __device__ inline int mix_p_doubles(const PcgGeom& g, int WB) {
+  const int pf = g.nn * WB;                         // row partials
+  const int sg = 4 * g.nq * 2;                      // face fluxes (prologue only)
+  return pf > sg ? pf : sg;
+}
+template <int N1C>
+__host__ __device__ inline size_t mix_lds_doubles(const PcgGeom& g, int nnz_full, int WB) {
+  constexpr int NP = N1C + 1;
+  return (size_t)mix_a_doubles<N1C>(nnz_full) + mix_p_doubles<N1C>(g, WB) + 6 * NP * NP +
+         common_small_doubles(g);
+}
+
+// y_t = ((A_hi + A_lo) x)_t in FP64 for owner threads (row (ix, iy)); x padded, in LDS.
+template <int N1C>
+__device__ __forceinline__ double blk_apply64(const BlockSolve<N1C, float>& W,
+                                              const float* __restrict__ lo,
+                                              const double* __restrict__ x) {
+  constexpr int n1 = N1C, NP = N1C + 1;
+  const int t = threadIdx.x;
+  double y = 0.0;
+  if (t < n1 * n1) {
+    const int iy = t / n1, ix = t - (t / n1) * n1;
+    const int lox = st_lo(ix, W.p), wx = st_w(ix, W.p, W.N);
+    const int loyi = st_lo(iy, W.p), hiyi = st_hi(iy, W.p, W.N);
+    for (int jy = loyi; jy <= hiyi; ++jy) {
+      const int off = W.boff[jy * n1 + ix] + (iy - st_lo(jy, W.p)) * wx;
+      for (int q = 0; q < wx; ++q)
+        y += ((double)W.A[off + q] + (double)lo[off + q]) * x[jy * NP + lox + q];
+    }
+  }
+  return y;
+}
+
+// Refined solve of (A + cw w w^T) x = b: FP64 residuals, inner PCG on A_hi.  Returns the
+// total inner iteration count (maxit + 1 on failure); *sweeps = residual evaluations - 1.
+// The refinement contracts by about kappa(A) 2^-24 per sweep (entrywise rounding of an
+// operator with strongly cancelling rows); where that stalls, the solve continues from the
+// refined iterate as plain PCG with the FP64-accurate product (hi + lo) x.
+template <int N1C>
+__device__ __forceinline__ int blk_solve_mixed(const BlockSolve<N1C, float>& W,
+                                               const float* __restrict__ lo, double* red,
+                                               double& x, double bval, double cw, double wt,
+                                               double rtol, int maxit, int* sweeps) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  double sb[1] = {own ? bval * bval : 0.0};
+  block_sum<1>(sb, red, nn);
+  const double bb = sb[0];
+  *sweeps = 0;
+  if (bb == 0.0) {
+    x = 0.0;
+    return 0;
+  }
+  const double tol2 = rtol * rtol * bb;
+  int total = 0, sw = 0;
+  for (; sw < kMaxSweeps; ++sw) {
+    if (own) W.U[pidx] = x;
+    __syncthreads();
+    const double ax = blk_apply64(W, lo, W.U);
+    double s1[1] = {own ? wt * x : 0.0};
+    block_sum<1>(s1, red, nn);
+    const double r = own ? bval - ax - cw * s1[0] * wt : 0.0;
+    double s2[1] = {r * r};
+    block_sum<1>(s2, red, nn);
+    if (s2[0] <= tol2) {
+      *sweeps = sw;
+      return total;
+    }
+    const double sc = 1.0 / sqrt(s2[0]);
+    // inner tolerance: what is left to reach rtol, but not below the FP32 operator's floor
+    const double tin = fmax(kInnerTol, 0.5 * sqrt(tol2 / s2[0]));
+    double c = 0.0;
+    const int its = blk_solve<N1C, float>(W, red, c, r * sc, cw, wt, tin, maxit, true);
+    total += its > maxit ? maxit : its;
+    if (its > maxit || total > maxit) break;
+    x += c / sc;
+  }
+  *sweeps = sw + 1;
+  // fallback: PCG with the accurate product from the current iterate
+  const int its = blk_solve_g(W, [&W, lo](const double* v) { return blk_apply64(W, lo, v); }, red,
+                              x, bval, cw, wt, rtol, maxit, false);
+  return its > maxit ? maxit + 1 : total + its;
+}
+
 template <int N1C>
 __device__ __forceinline__ void pcg2_stage_carve(const PcgStageArgs& a, BlockSolve<N1C>& W,
                                                  StageCommon& C) {
@@ -1142,20 +1315,6 @@ __device__ __forceinline__ void pcg2_stage_carve(const PcgStageArgs& a, BlockSol
   W.boff = ip;  ip += nn;
   W.jc = ip;    ip += W.K;
   stage_carve(g, sp, ip, C);
-}
-
-template <int N1C>
-__device__ __forceinline__ void pcg2_stage_load_tables(const PcgStageArgs& a,
-                                                       const BlockSolve<N1C>& W,
-                                                       const StageCommon& C) {
-  constexpr int NP = N1C + 1, nn = N1C * N1C;
-  const int t = threadIdx.x;
-  int* boff = const_cast<int*>(W.boff);
-  int* jc = const_cast<int*>(W.jc);
-  for (int i = t; i < nn; i += blockDim.x) boff[i] = a.blk_off[i];
-  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
-  for (int i = t; i < 5 * NP * NP; i += blockDim.x) W.R[i] = 0.0;   // R U T Z DI (padding)
-  stage_load_tables(a.g, W.Psi, NP, C);
 }
 
 template <int STAGE, int N1C>
@@ -1218,6 +1377,127 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
   stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM);
 }
 
+template <int N1C>
+__device__ __forceinline__ void pcg2m_stage_carve(const PcgStageArgs& a, BlockSolve<N1C, float>& W,
+                                                  StageCommon& C) {
+  extern __shared__ double shd[];
+  constexpr int NP = N1C + 1, nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  W.K = a.blk_K;
+  W.CH = a.blk_CH;
+  W.WB = a.blk_WB;
+  W.p = g.p;
+  W.N = g.N;
+  double* sp = shd;
+  W.A = reinterpret_cast<float*>(sp);  sp += mix_a_doubles<N1C>(a.nnz_full);
+  double* preg = sp;
+  W.P = sp;    sp += mix_p_doubles<N1C>(g, W.WB);
+  W.R = sp;    sp += NP * NP;
+  W.U = sp;    sp += NP * NP;
+  W.T = sp;    sp += NP * NP;
+  W.Z = sp;    sp += NP * NP;
+  W.DI = sp;   sp += NP * NP;
+  W.Psi = sp;  sp += NP * NP;
+  int* ip = reinterpret_cast<int*>(shd + mix_lds_doubles<N1C>(g, a.nnz_full, W.WB));
+  W.boff = ip;  ip += nn;
+  W.jc = ip;    ip += W.K;
+  stage_carve_small(g, sp, ip, preg, C);
+}
+
+template <int N1C, typename TA>
+__device__ __forceinline__ void blk_load_tables(const PcgStageArgs& a, const BlockSolve<N1C, TA>& W,
+                                                const StageCommon& C) {
+  constexpr int NP = N1C + 1, nn = N1C * N1C;
+  const int t = threadIdx.x;
+  int* boff = const_cast<int*>(W.boff);
+  int* jc = const_cast<int*>(W.jc);
+  for (int i = t; i < nn; i += blockDim.x) boff[i] = a.blk_off[i];
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  for (int i = t; i < 5 * NP * NP; i += blockDim.x) W.R[i] = 0.0;   // R U T Z DI (padding)
+  stage_load_tables(a.g, W.Psi, NP, C);
+}
+
+// Copy an FP32 block-layout operator (nnz entries) from global memory into LDS.
+__device__ __forceinline__ void blk_load32(int nnz, float* A, const float* __restrict__ src) {
+  const int step = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < nnz; i0 += 8 * step) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * step;
+      v[k] = i < nnz ? src[i] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * step;
+      if (i < nnz) A[i] = v[k];
+    }
+  }
+}
+
+template <int STAGE, int N1C>
+__device__ __forceinline__ void pcg2m_stage_elem(const PcgStageArgs& a, const long e,
+                                                 BlockSolve<N1C, float>& W, StageCommon& C) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  const int nnz = a.nnz_full;
+  float* const Aop = W.A;
+  const float* const Shi = a.el.Shi + e * nnz;
+  const float* const Slo = a.el.Slo + e * nnz;
+  stage_prologue<STAGE>(a, e, C, [Aop, Shi, nnz]() { blk_load32(nnz, Aop, Shi); });
+  // r = -S_K U + F_v in FP64
+  if (own) W.U[pidx] = C.U[t];
+  __syncthreads();
+  {
+    const double su = blk_apply64(W, Slo, W.U);
+    if (own) C.rv[t] -= su;
+  }
+  // ---- S_hat y = F_u ------------------------------------------------------------------
+  double dS = 1.0;
+  if (own) {
+    const int kx = t % n1, ky = t / n1;
+    dS = t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky];
+    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
+    W.DI[pidx] = 1.0 / dS;
+  }
+  double y = C.xs0;
+  int swS = 0, swM = 0;
+  int itS = blk_solve_mixed(W, Slo, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit,
+                            &swS);
+  if (itS > a.maxit && a.el.dlog) {
+    if (own) {
+      const int kx = t % n1, ky = t / n1;
+      W.DI[pidx] = 1.0 / (t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky]);
+    }
+    y = C.xs0;
+    itS = blk_solve_mixed(W, Slo, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit,
+                          &swS);
+  }
+  __syncthreads();
+  // ---- M_J z = r --------------------------------------------------------------------
+  int itM;
+  double z;
+  if (own) W.DI[pidx] = 1.0 / C.area;
+  if (a.mapped) {
+    blk_load32(nnz, W.A, a.el.Mhi + e * nnz);
+    z = C.xm0;
+    itM = blk_solve_mixed(W, a.el.Mlo + e * nnz, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol,
+                          a.maxit, &swM);
+  } else {
+    // Cartesian: the preconditioner is the exact inverse of M_J (FP64 transforms)
+    double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
+    if (own) W.R[pidx] = C.rv[t];
+    block_sum<1>(bb1, C.red, nn);
+    blk_pinv(W, W.R, W.U);
+    z = own ? W.U[pidx] : 0.0;
+    itM = bb1[0] > 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM, swS, swM);
+}
+
 // At most 768 threads (12 waves, 3 per SIMD), so that a lane may hold 170 VGPRs.
 constexpr int kBlkMaxThreads = 768;
 
@@ -1226,26 +1506,18 @@ constexpr int kBlkMaxThreads = 768;
 // owns elements [el_start[i], el_start[i+1]); block b takes b, b + gridDim.x, ...
 // N1C > 0: every member uses the column-block layout with N + 1 = N1C; N1C = 0: every
 // member uses the row layout.
-template <int STAGE, int N1C>
-__global__ __launch_bounds__(N1C > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_group(
-    const PcgStageArgs* __restrict__ args,
-                                                          const long* __restrict__ el_start,
-                                                          int nprob) {
+template <int STAGE, int KEY>
+__global__ __launch_bounds__(KEY > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_group(
+    const PcgStageArgs* __restrict__ args, const long* __restrict__ el_start, int nprob) {
+  constexpr int N1C = KEY & 31;            // N + 1 of the column-block families
+  constexpr bool MIX = KEY >= 32;          // FP32 operator + FP64 refinement
   const long total = el_start[nprob];
   int pi = 0, cur = -1;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
     while (pi + 1 < nprob && b >= el_start[pi + 1]) ++pi;
     const PcgStageArgs& a = args[pi];
     StageCommon C;
-    if constexpr (N1C > 0) {
-      BlockSolve<N1C> W;
-      pcg2_stage_carve<N1C>(a, W, C);
-      if (pi != cur) {               // a new problem: its tables
-        pcg2_stage_load_tables<N1C>(a, W, C);
-        cur = pi;
-      }
-      pcg2_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
-    } else {
+    if constexpr (KEY == 0) {
       PcgShared W;
       pcg_stage_carve(a, W, C);
       if (pi != cur) {
@@ -1253,6 +1525,22 @@ __global__ __launch_bounds__(N1C > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_g
         cur = pi;
       }
       pcg_stage_elem<STAGE>(a, b - el_start[pi], W, C);
+    } else if constexpr (MIX) {
+      BlockSolve<N1C, float> W;
+      pcg2m_stage_carve<N1C>(a, W, C);
+      if (pi != cur) {                     // a new problem: its tables
+        blk_load_tables<N1C, float>(a, W, C);
+        cur = pi;
+      }
+      pcg2m_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
+    } else {
+      BlockSolve<N1C> W;
+      pcg2_stage_carve<N1C>(a, W, C);
+      if (pi != cur) {
+        blk_load_tables<N1C, double>(a, W, C);
+        cur = pi;
+      }
+      pcg2_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
     }
     __syncthreads();   // the next element reuses the LDS
   }
@@ -1344,6 +1632,15 @@ hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, 
   return hipGetLastError();
 }
 
+hipError_t launch_split_hilo(const double* half, const int* dst, int nst, int nnz, long nel,
+                             float* hi, float* lo, hipStream_t st) {
+  const long n = nel * nst;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_hilo, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, half, dst,
+                     nst, nnz, nel, hi, lo);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double* a, float* b, long n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
@@ -1362,12 +1659,12 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
 // ---------------------------------------------------------------------------------
 // Column-block layout (host): tables, eligibility, LDS size.
 // ---------------------------------------------------------------------------------
-static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K) {
+static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K, int mixed = 0) {
   size_t nd;
   switch (g.n1) {
-    case 9: nd = blk_lds_doubles<9>(g, nnz_full, WB); break;
-    case 13: nd = blk_lds_doubles<13>(g, nnz_full, WB); break;
-    case 17: nd = blk_lds_doubles<17>(g, nnz_full, WB); break;
+    case 9: nd = mixed ? mix_lds_doubles<9>(g, nnz_full, WB) : blk_lds_doubles<9>(g, nnz_full, WB); break;
+    case 13: nd = mixed ? mix_lds_doubles<13>(g, nnz_full, WB) : blk_lds_doubles<13>(g, nnz_full, WB); break;
+    case 17: nd = mixed ? mix_lds_doubles<17>(g, nnz_full, WB) : blk_lds_doubles<17>(g, nnz_full, WB); break;
     default: return (size_t)-1;
   }
   return nd * sizeof(double) + ((size_t)g.nn + K + common_ints(g)) * sizeof(int);
@@ -1375,7 +1672,7 @@ static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K) {
 
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
                      std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
-                     int* nnz, int* threads) {
+                     int* nnz, int* threads, int mixed) {
   const int n1 = g.n1, N = g.N, p = g.p, nn = g.nn;
   if (n1 != 9 && n1 != 13 && n1 != 17) return 0;
   boff.assign(nn, 0);
@@ -1410,7 +1707,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
       dst[2 * h + 1] = boff[iy * n1 + jx] + (jy - st_lo(iy, p)) * st_w(jx, p, N) + (ix - st_lo(jx, p));
     }
   }
-  const size_t lds = blk_lds_bytes(g, off, wb, kk);
+  const size_t lds = blk_lds_bytes(g, off, wb, kk, mixed);
   if (lds > 160 * 1024) return 0;
   *K = kk;
   *CH = ch;
@@ -1437,7 +1734,7 @@ void pcg_stage_shape(const PcgGeom& g, int threads, int* full, int* Q, int* nnz_
 
 int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds) {
   if (a.v2) {
-    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
+    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K, a.mixed);
     return threads >= a.blk_threads;
   }
   pcg_stage_shape(a.g, threads, &a.full, &a.Q, &a.nnz_full, lds);
@@ -1460,6 +1757,9 @@ static hipError_t launch_group_n1(int n1, const PcgStageArgs* args, const long* 
     case 9: return launch_group_k<STAGE, 9>(args, el_start, nprob, grid, threads, lds, st);
     case 13: return launch_group_k<STAGE, 13>(args, el_start, nprob, grid, threads, lds, st);
     case 17: return launch_group_k<STAGE, 17>(args, el_start, nprob, grid, threads, lds, st);
+    case 9 + 32: return launch_group_k<STAGE, 41>(args, el_start, nprob, grid, threads, lds, st);
+    case 13 + 32: return launch_group_k<STAGE, 45>(args, el_start, nprob, grid, threads, lds, st);
+    case 17 + 32: return launch_group_k<STAGE, 49>(args, el_start, nprob, grid, threads, lds, st);
     default: return launch_group_k<STAGE, 0>(args, el_start, nprob, grid, threads, lds, st);
   }
 }
@@ -1481,12 +1781,13 @@ hipError_t pcg_group_prepare() {
   if ((e = group_attrs<0>()) != hipSuccess) return e;
   if ((e = group_attrs<9>()) != hipSuccess) return e;
   if ((e = group_attrs<13>()) != hipSuccess) return e;
-  return group_attrs<17>();
+  if ((e = group_attrs<17>()) != hipSuccess) return e;
+  if ((e = group_attrs<41>()) != hipSuccess) return e;
+  if ((e = group_attrs<45>()) != hipSuccess) return e;
+  return group_attrs<49>();
 }
 
-int pcg_group_max_threads(int n1) {
-  return (n1 == 9 || n1 == 13 || n1 == 17) ? kBlkMaxThreads : 1024;
-}
+int pcg_group_max_threads(int key) { return key > 0 ? kBlkMaxThreads : 1024; }
 
 hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds, hipStream_t st) {
@@ -1507,6 +1808,9 @@ static const void* group_kernel_n1(int key) {
     case 9: return (const void*)k_pcg_stage_group<STAGE, 9>;
     case 13: return (const void*)k_pcg_stage_group<STAGE, 13>;
     case 17: return (const void*)k_pcg_stage_group<STAGE, 17>;
+    case 41: return (const void*)k_pcg_stage_group<STAGE, 41>;
+    case 45: return (const void*)k_pcg_stage_group<STAGE, 45>;
+    case 49: return (const void*)k_pcg_stage_group<STAGE, 49>;
     default: return (const void*)k_pcg_stage_group<STAGE, 0>;
   }
 }
@@ -1517,12 +1821,12 @@ unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel) {
   return persistent_grid(k, threads, lds, nel);
 }
 
-int pcg_group_key(const PcgStageArgs& a) { return a.v2 ? a.g.n1 : 0; }
+int pcg_group_key(const PcgStageArgs& a) { return a.v2 ? a.g.n1 + (a.mixed ? 32 : 0) : 0; }
 
 int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds) {
   if (a.v2) {
     *threads = a.blk_threads;
-    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K);
+    *lds = blk_lds_bytes(a.g, a.nnz_full, a.blk_WB, a.blk_K, a.mixed);
   } else {
     if (a.fo == nullptr || a.dst == nullptr) return 0;
     *threads = stage_full(a.g) ? 1024 : threads_for(a.g.nn);

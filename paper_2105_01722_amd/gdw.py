@@ -35,7 +35,7 @@ class gdw_stats(ctypes.Structure):
                 ("n1", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
                 ("fail_elem", ctypes.c_int), ("mean_it_S", ctypes.c_double),
                 ("mean_it_M", ctypes.c_double), ("max_it_S", ctypes.c_int), ("max_it_M", ctypes.c_int),
-                ("solves", ctypes.c_longlong)]
+                ("solves", ctypes.c_longlong), ("mean_refine", ctypes.c_double)]
 
 
 class GdwError(RuntimeError):

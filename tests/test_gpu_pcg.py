@@ -36,10 +36,10 @@ def _problem(n, N, p, mapped, variable, seed=3, kmax=4):
 
 
 def _gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, mapped, variable, flux="upwind", rtol=1e-13,
-         maxit=200, give_coords=True):
+         maxit=200, give_coords=True, precision="fp64"):
     from paper_2105_01722_amd import gdw
     s = gdw.Solver(n, n, N, p, flux=flux, xi=1.0, solver="pcg", coeff_variable=variable,
-                   mapped=mapped, pcg_rtol=rtol, pcg_maxit=maxit)
+                   mapped=mapped, pcg_rtol=rtol, pcg_maxit=maxit, precision=precision)
     s.set_coeff(c2 if variable else None, Xm if (mapped or give_coords) else None,
                 Ym if (mapped or give_coords) else None)
     s.set_state(U0, V0)
@@ -124,3 +124,37 @@ def test_pcg_maxit_reports_enoconv():
     Xm, Ym, c2, U0, V0 = _problem(n, N, p, True, True)
     _, _, _, st = _gpu(n, N, p, Xm, Ym, c2, U0, V0, 0.01, 1, True, True, rtol=1e-13, maxit=2)
     assert st["status"] == gdw.GDW_ENOCONV and 0 <= st["fail_elem"] < n * n
+
+
+@pytest.mark.parametrize("n,N,p,mapped,variable", [(3, 12, 5, True, True), (3, 8, 3, True, True),
+                                                   (2, 16, 3, False, True), (2, 8, 7, True, True)])
+def test_pcg_mixed_matches_dense_oracle(n, N, p, mapped, variable):
+    """Mixed precision (FP32 operator in the inner iterations, FP64 residual refinement with
+    A = hi + lo): the refined solution meets the same FP64 residual tolerance with an
+    operator represented to about 2^-48 (3.6e-15) instead of 2^-53, so the state is
+    compared with the dense oracle at 1e-10 (the FP64 bar of 1e-12 times that ratio,
+    with margin); at least one refinement sweep must have run."""
+    _say("case: pcg mixed vs dense", n, N, p, mapped, variable)
+    Xm, Ym, c2, U0, V0 = _problem(n, N, p, mapped, variable)
+    dt, steps = 0.1 / (n * N), 3
+    Ug, Vg, Eg, st = _gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, mapped, variable,
+                          precision="mixed")
+    assert st["status"] == 0
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind"), Xm, Ym, c2)
+    Uo, Vo = general.run(U0, V0, ops, dt, steps)
+    eu, ev = _rel(Ug, Uo), _rel(Vg, Vo)
+    _say("  rel U %.2e V %.2e  its S %.2f M %.2f refine %.2f"
+         % (eu, ev, st["mean_it_S"], st["mean_it_M"], st["mean_refine"]))
+    assert eu <= 1e-10 and ev <= 1e-10
+    Eo = general.energy(Uo, Vo, ops)
+    assert abs(Eg - Eo) <= 1e-10 * abs(Eo)
+    assert st["mean_refine"] >= 1.0
+
+
+def test_pcg_mixed_unsupported_size():
+    """Mixed precision needs N + 1 in {9, 13, 17}: other sizes are refused at creation."""
+    from paper_2105_01722_amd import gdw
+    with pytest.raises(gdw.GdwError) as ei:
+        gdw.Solver(2, 2, 10, 5, flux="upwind", solver="pcg", coeff_variable=True,
+                   precision="mixed")
+    assert ei.value.status == gdw.GDW_EUNSUPPORTED
