@@ -31,7 +31,7 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
 # by a plain device copy's reading of the same counters (x2.0 read, x1.0 write); the
 # summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.  Set to None
 # whenever that kernel changes until the counters are taken again.
-FDM_STAGE_TRAFFIC = (302909.0 * 2.0 + 439582.25) * 1024.0
+FDM_STAGE_TRAFFIC = (319437.89 * 2.0 + 468754.90) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -95,12 +95,12 @@ def _pcg_flops_per_step(st, nel, N, p):
     return 4 * per_stage
 
 
-def _time_pcg(w, steps, warmup, rtol=1e-12):
+def _time_pcg(w, steps, warmup, rtol=1e-12, precision="fp64"):
     import torch
     from paper_2105_01722_amd import gdw
     n, N, p = w["n"], w["N"], w["p"]
     s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
-                   mapped=True, pcg_rtol=rtol)
+                   mapped=True, pcg_rtol=rtol, precision=precision)
     s.set_coeff(w["c2"], w["X"], w["Y"])
     U0 = torch.from_numpy(w["U0"]).cuda()
     s.set_state(U0, torch.zeros_like(U0))
@@ -117,14 +117,17 @@ def _time_pcg(w, steps, warmup, rtol=1e-12):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     st = s.stats()
+    U, V = s.get_state()
+    U, V = U.cpu().numpy(), V.cpu().numpy()
     s.close()
     # iteration means of the timed steps only
     tot = st["solves"]
     prev = st0["solves"]
     mS = (st["mean_it_S"] * tot - st0["mean_it_S"] * prev) / (tot - prev)
     mM = (st["mean_it_M"] * tot - st0["mean_it_M"] * prev) / (tot - prev)
+    mR = (st["mean_refine"] * tot - st0["mean_refine"] * prev) / (tot - prev)
     return ms, {"mean_it_S": mS, "mean_it_M": mM, "max_it_S": st["max_it_S"],
-                "max_it_M": st["max_it_M"]}
+                "max_it_M": st["max_it_M"], "mean_refine": mR}, (U, V)
 
 
 def _learned_section(steps, epochs=60, n_train=20000, seed_train=5000, seed_test=6):
@@ -323,6 +326,8 @@ def main():
     ap.add_argument("--pcg-only", action="store_true",
                     help="profiling aid: run only the PCG workload (prints its section only)")
     ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
+    ap.add_argument("--pcg-precision", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the PCG solves under --pcg-only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (HBM counter "
                          "calibration under rocprofv3 --pmc)")
@@ -351,7 +356,7 @@ def main():
         return
     if args.pcg_only:
         pw = _pcg_workload()
-        ms, its = _time_pcg(pw, max(1, args.pcg_steps), 1)
+        ms, its, _ = _time_pcg(pw, max(1, args.pcg_steps), 1, precision=args.pcg_precision)
         print(json.dumps({"pcg_ms_per_step": ms / max(1, args.pcg_steps), **its}))
         return
     w = _workload()
@@ -396,8 +401,11 @@ def main():
         pn, pN = pw["n"], pw["N"]
         pdof = pn * pn * (pN + 1) ** 2
         ksteps = max(1, min(args.steps, args.pcg_steps))
-        ms, its = _time_pcg(pw, ksteps, 1)
+        ms, its, st64 = _time_pcg(pw, ksteps, 1)
         print("bench: pcg fp64 %.3f ms/step" % (ms / ksteps), file=sys.stderr, flush=True)
+        msm, itm, stm = _time_pcg(pw, ksteps, 1, precision="mixed")
+        print("bench: pcg mixed %.3f ms/step" % (msm / ksteps), file=sys.stderr, flush=True)
+        dmix = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(stm, st64))
         flops = _pcg_flops_per_step(its, pn * pn, pN, pw["p"]) * ksteps / (ms * 1e-3)
         out["pcg"] = {
             "workload": "128x128 mapped elements (X = x + 0.05 sin(2 pi x) sin(2 pi y), same for Y), "
@@ -409,7 +417,13 @@ def main():
             "max_it_S": its["max_it_S"], "max_it_M": its["max_it_M"],
             "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": 78.6,
                          "unit": "TFLOP/s", "frac": flops / 78.6e12, "traffic": None,
-                         "kernel": "k_pcg_stage<*> (4 stage variants)"},
+                         "kernel": "k_pcg_stage_group<*,13> (4 stage variants)"},
+            "mixed": {"ms_per_step": msm / ksteps, "value": pdof * ksteps / (msm * 1e-3),
+                      "speedup_vs_fp64": ms / msm, "mean_it_S": itm["mean_it_S"],
+                      "mean_it_M": itm["mean_it_M"], "mean_refine_sweeps": itm["mean_refine"],
+                      "rel_diff_vs_fp64_state": dmix,
+                      "note": "FP32 operator for the inner CG iterations, FP64 residual refinement "
+                              "to the same rtol; same final tolerance as the FP64 path"},
         }
     if not args.no_learned:
         out["learned"] = _learned_section(max(1, min(args.steps, 3)))

@@ -360,6 +360,22 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 // the workgroup: state addresses are a scalar element base plus the thread's fixed
 // offset.
 // One tile (EPB consecutive elements, tile index `tile`) of one problem.
+// Streaming access to the per-element state.  Each state word is read once and
+// written once per stage, so in FP64 the loads and stores bypass the cache
+// hierarchy's normal allocation (nontemporal): measured at the 256x256, N = 16
+// workload this saves about 3% per stage.  FP32 tiles are half as large and run
+// faster with ordinary accesses, so they keep them.
+template <typename T>
+__device__ __forceinline__ T ld_state(const T* p) {
+  if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_state(T* p, T v) {
+  if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 template <typename T, int STAGE, int N1C, int EPB>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   const int n1 = N1C > 0 ? N1C : a.n1;
@@ -383,11 +399,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     ru[l] = rv[l] = xu[l] = xv[l] = T(0);
     if (l < ne) {
       const long g = (e0 + l) * nn + tid;
-      ru[l] = a.in_u[g];
-      rv[l] = a.in_v[g];
+      ru[l] = ld_state(&a.in_u[g]);
+      rv[l] = ld_state(&a.in_v[g]);
       if (STAGE > 1) {
-        xu[l] = a.aux_u[g];
-        xv[l] = a.aux_v[g];
+        xu[l] = ld_state(&a.aux_u[g]);
+        xv[l] = ld_state(&a.aux_v[g]);
       }
     }
   }
@@ -443,8 +459,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     } else if (STAGE == 2) {   // yu, yv = y
       nu = yu + T(0.5) * dt * ku;
       nv = yv + T(0.5) * dt * kv;
-      a.acc_u[g] = ub + T(2) * nu - yu;
-      a.acc_v[g] = vb + T(2) * nv - yv;
+      st_state(&a.acc_u[g], ub + T(2) * nu - yu);
+      st_state(&a.acc_v[g], vb + T(2) * nv - yv);
     } else if (STAGE == 3) {   // yu, yv = y
       nu = yu + dt * ku;
       nv = yv + dt * kv;
@@ -452,8 +468,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
       nu = (yu + ub) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * ku;
       nv = (yv + vb) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * kv;
     }
-    a.out_u[g] = nu;
-    a.out_v[g] = nv;
+    st_state(&a.out_u[g], nu);
+    st_state(&a.out_v[g], nv);
     snew[(l * 2) * nn + tid] = nu;
     snew[(l * 2 + 1) * nn + tid] = nv;
   }
