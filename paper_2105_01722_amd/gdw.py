@@ -48,6 +48,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libgdw.so is not built (run `python -m paper_2105_01722_amd.build`); "
                           "there is no CPU fallback")
+    # The library receives torch's device pointers and streams, so it must run on the HIP
+    # runtime torch has loaded.  torch ships its own libamdhip64.so.7 and HSA runtime;
+    # importing torch first makes the dynamic loader bind the library's libamdhip64.so.7
+    # dependency to that copy.  Loaded the other way round, the process would hold two HSA
+    # runtimes, and the second one to start reports that no GPU is present.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, None
     sig = {

@@ -3,6 +3,7 @@ declares, and rejects invalid descriptors before touching the device."""
 import ctypes
 import os
 import subprocess
+import sys
 
 import pytest
 
@@ -87,6 +88,23 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_one_hip_runtime_in_the_process():
+    """Importing the binding first (before anything else imports torch) must leave one HIP
+    runtime and one HSA runtime in the process: torch's, which owns the tensors the library
+    is handed.  Two HSA runtimes in one process make the second report no GPU."""
+    code = ("from paper_2105_01722_amd import gdw\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps')\n"
+            "        if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+            "print('\\n'.join(sorted(libs)))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = out.stdout.split()
+    assert sum("libamdhip64" in l for l in libs) == 1, libs
+    assert sum("libhsa-runtime64" in l for l in libs) == 1, libs
 
 
 @pytest.mark.parametrize("args", [(0, 16, 8, 1, 64), (64, 0, 8, 1, 64), (64, 16, 0, 1, 64),
