@@ -281,9 +281,8 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
                                             grid, thr, lds, st);
             }, st, 1, &ms);
         if (s != GDW_OK) break;
-        std::snprintf(buf, sizeof buf, "  pcg %s%d threads=%d grid=%u lds=%zu: %.4f ms\n",
-                      c.n1 > 32 ? "mixed n1=" : c.n1 ? "blocks n1=" : "rows ", c.n1 & 31, thr,
-                      grid, lds, ms);
+        std::snprintf(buf, sizeof buf, "  pcg key=%d threads=%d grid=%u lds=%zu: %.4f ms\n",
+                      c.n1, thr, grid, lds, ms);
         log += buf;
         if (ms < best) { best = ms; best_thr = thr; best_grid = grid; best_lds = lds; }
       }
@@ -355,8 +354,12 @@ static void make_plan(gdw_batch* b, const std::string& log) {
     p += buf;
   }
   for (auto& c : b->pcg) {
-    std::snprintf(buf, sizeof buf, "pcg %s%d: %zu problems, threads=%d grid=%u lds=%zu\n",
-                  c.n1 > 32 ? "mixed n1=" : c.n1 ? "blocks n1=" : "rows ", c.n1 & 31,
+    char fam[48];
+    if (c.n1 == 0) std::snprintf(fam, sizeof fam, "rows");
+    else if (c.n1 & 64) std::snprintf(fam, sizeof fam, "blocks n1=%d (registers, p=%d)", c.n1 & 31, c.n1 >> 7);
+    else if (c.n1 & 32) std::snprintf(fam, sizeof fam, "mixed n1=%d", c.n1 & 31);
+    else std::snprintf(fam, sizeof fam, "blocks n1=%d", c.n1 & 31);
+    std::snprintf(buf, sizeof buf, "pcg %s: %zu problems, threads=%d grid=%u lds=%zu\n", fam,
                   c.members.size(), c.threads, c.grid, c.lds);
     p += buf;
   }
@@ -392,8 +395,10 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
     for (int i = 0; i < nprob; ++i) {
       const gdw_ctx* c = b->ctx[i];
       if (c->solver == GDW_SOLVE_PCG) {
-        // kernel family: N + 1 for the column-block layout, 0 for the row layout
-        const int fam = c->blk_v2 ? c->n1 + (c->d.precision == GDW_MIXED_FP32 ? 32 : 0) : 0;
+        // kernel family (the grouped kernel's key): layout, precision and, for the
+        // register-operator kernels, the degree
+        const int fam = pcg_family_key(c->n1, c->d.p, c->blk_v2,
+                                       c->d.precision == GDW_MIXED_FP32);
         auto key = std::make_pair(fam, 0);
         if (!pk.count(key)) { pk[key] = b->pcg.size(); b->pcg.emplace_back(); b->pcg.back().n1 = fam; }
         b->pcg[pk[key]].members.push_back(i);

@@ -95,6 +95,9 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
                              double* tr, long nel, hipStream_t st);
 // Kernel family of a problem for the grouped launch: N + 1 for the column-block layout,
 // 0 for the row layout.
+// Key of the grouped stage kernel for a problem: 0 (row layout), N + 1 (column blocks),
+// N + 1 + 32 (mixed), or N + 1 + 64 + 128 p (FP64 operator held in registers).
+int pcg_family_key(int n1, int p, int v2, int mixed);
 int pcg_group_key(const PcgStageArgs& a);
 // Block size and LDS of a problem launched alone (sets full / Q / nnz_full of the row
 // layout); 0 if it does not fit a workgroup.

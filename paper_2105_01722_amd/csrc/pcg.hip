@@ -979,7 +979,20 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
 // on 2 x 2 output blocks per thread without bounds tests.  The PCG recurrence is the
 // single-reduction form of Chronopoulos and Gear: one workgroup reduction per iteration.
 // ---------------------------------------------------------------------------------
-template <int N1C, typename TA = double>
+// At most 768 threads (12 waves, 3 per SIMD), so that a lane may hold 170 VGPRs.
+constexpr int kBlkMaxThreads = 768;
+
+// Lanes per output of the preconditioner's transforms for nn outputs on at most maxt
+// threads.
+__host__ __device__ constexpr int blk_pinv_split(int nn, int maxt) {
+  return 4 * nn <= maxt ? 4 : 2 * nn <= maxt ? 2 : 1;
+}
+
+// Block size of the register-operator kernels: 8 waves (2 per SIMD), so that a lane may
+// hold 256 VGPRs.
+constexpr int kRegMaxThreads = 512;
+
+template <int N1C, typename TA = double, int MAXT = kBlkMaxThreads>
 struct BlockSolve {
   TA* A;                                     // operator (block layout)
   double *P;                                 // row partials
@@ -988,8 +1001,8 @@ struct BlockSolve {
   int K, CH, WB, p, N;
 };
 
-template <int N1C, typename TA>
-__device__ __forceinline__ double blk_apply(const BlockSolve<N1C, TA>& W,
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ double blk_apply(const BlockSolve<N1C, TA, MT>& W,
                                             const double* __restrict__ x) {
   constexpr int n1 = N1C, NP = N1C + 1, WM = N1C < 15 ? N1C : 15;
   const int t = threadIdx.x;
@@ -1031,11 +1044,11 @@ __device__ __forceinline__ double blk_apply(const BlockSolve<N1C, TA>& W,
 // four 1D transforms gives every output (a, b) to SP adjacent lanes (one quad), which
 // split its sum over the contracted index and combine the parts with DPP lane moves, so
 // that one batch of LDS loads per lane covers a phase.
-template <int N1C, typename TA>
-__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA>& W, const double* __restrict__ R,
-                                double* __restrict__ out) {
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
+                                         const double* __restrict__ R, double* __restrict__ out) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
-  constexpr int SP = 4 * nn <= 1024 ? 4 : 2;
+  constexpr int SP = blk_pinv_split(nn, MT);
   constexpr int NT = (n1 + SP - 1) / SP;          // terms per lane
   const int t = threadIdx.x;
   const int o = t / SP, part = t - o * SP;
@@ -1043,7 +1056,7 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA>& W, const dou
   const int a = act ? o / n1 : 0, b = act ? o - (o / n1) * n1 : 0;
   const double* Ps = W.Psi;
   auto combine = [&](double v) {
-    v += dpp_mov<0xb1, 0xf, false>(v);                       // lanes ^1
+    if constexpr (SP >= 2) v += dpp_mov<0xb1, 0xf, false>(v);  // lanes ^1
     if constexpr (SP == 4) v += dpp_mov<0x4e, 0xf, false>(v);  // lanes ^2
     return v;
   };
@@ -1092,8 +1105,8 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA>& W, const dou
 // PCG (single-reduction recurrence) on (A_op + cw w w^T) x = b; owner thread t < nn holds
 // x (in/out, warm start on entry), b and w.  Iteration count as pcg_solve.  zero_start:
 // x = 0 on entry (the first product is skipped).
-template <int N1C, typename TA, typename App>
-__device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA>& W, App&& apply, double* red,
+template <int N1C, typename TA, int MT, typename App>
+__device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App&& apply, double* red,
                                            double& x, double bval, double cw, double wt,
                                            double rtol, int maxit, bool zero_start) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
@@ -1148,8 +1161,8 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA>& W, App&& a
   return maxit + 1;
 }
 
-template <int N1C, typename TA>
-__device__ __forceinline__ int blk_solve(const BlockSolve<N1C, TA>& W, double* red, double& x,
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ int blk_solve(const BlockSolve<N1C, TA, MT>& W, double* red, double& x,
                                          double bval, double cw, double wt, double rtol, int maxit,
                                          bool zero_start = false) {
   return blk_solve_g(W, [&W](const double* v) { return blk_apply(W, v); }, red, x, bval, cw, wt,
@@ -1291,8 +1304,8 @@ __device__ __forceinline__ int blk_solve_mixed(const BlockSolve<N1C, float>& W,
   return its > maxit ? maxit + 1 : total + its;
 }
 
-template <int N1C>
-__device__ __forceinline__ void pcg2_stage_carve(const PcgStageArgs& a, BlockSolve<N1C>& W,
+template <int N1C, int MT = kBlkMaxThreads>
+__device__ __forceinline__ void pcg2_stage_carve(const PcgStageArgs& a, BlockSolve<N1C, double, MT>& W,
                                                  StageCommon& C) {
   extern __shared__ double shd[];
   constexpr int NP = N1C + 1, nn = N1C * N1C;
@@ -1377,6 +1390,170 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
   stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM);
 }
 
+// ---------------------------------------------------------------------------------
+// Operator in registers (FP64, column-block layout).  The entries a work unit of the
+// block product multiplies are the same in every iteration of a solve, so after the
+// operator has been expanded into LDS each unit copies its CH x W entries (and its row
+// and column offsets) into registers; an iteration then reads only x and the row partials
+// from LDS.  Compiled for fixed (N + 1, p), which fixes W = min(2p + 1, N + 1) and the
+// chunk height CH chosen by the same rule as the host tables.
+// ---------------------------------------------------------------------------------
+__host__ __device__ constexpr int blk_band_c(int k, int p, int N) {
+  return (k + p < N ? k + p : N) - (k - p > 0 ? k - p : 0) + 1;
+}
+__host__ __device__ constexpr int blk_ch_c(int n1, int p, int maxt) {
+  for (int ch = 1; ch <= 4; ++ch) {
+    int kk = 0;
+    for (int jy = 0; jy < n1; ++jy) kk += (blk_band_c(jy, p, n1 - 1) + ch - 1) / ch;
+    if (n1 * kk <= maxt) return ch;
+  }
+  return 0;
+}
+
+template <int N1C, int P>
+struct RegOp {
+  static constexpr int W = 2 * P + 1 < N1C ? 2 * P + 1 : N1C;
+  static constexpr int CH = blk_ch_c(N1C, P, kRegMaxThreads);
+  static_assert(CH > 0, "no chunk height fits the thread limit");
+  double a[CH][W];
+  int xoff;          // jy * NP + lo(ix): first x value of the unit
+  int wx, ni;        // columns and rows of the unit (0 rows: no unit)
+  int pd[CH];        // row-partial slot of each row
+};
+
+// Set up the unit geometry of this thread (once per problem: it depends only on the
+// tables) and copy the unit's entries from the LDS block layout.
+template <int N1C, int P>
+__device__ __forceinline__ void reg_fetch(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                          RegOp<N1C, P>& R) {
+  constexpr int n1 = N1C, NP = N1C + 1, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < CH; ++i)
+#pragma unroll
+    for (int q = 0; q < WM; ++q) R.a[i][q] = 0.0;
+  R.xoff = 0;
+  R.wx = 0;
+  R.ni = 0;
+  if (t < n1 * W.K) {
+    const int k = t / n1, ix = t - k * n1;
+    const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
+    const int lox = st_lo(ix, P), wx = st_w(ix, P, N1C - 1);
+    const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
+    const int i0 = c * CH;
+    const int ni = min(CH, wy - i0);
+    R.xoff = jy * NP + lox;
+    R.wx = wx;
+    R.ni = ni;
+    const double* Ab = W.A + W.boff[jy * n1 + ix] + i0 * wx;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int iy = loy + i0 + i;
+      R.pd[i] = (iy * n1 + ix) * W.WB + (jy - st_lo(iy, P));
+#pragma unroll
+      for (int q = 0; q < WM; ++q)
+        if (i < ni && q < wx) R.a[i][q] = Ab[i * wx + q];
+    }
+  }
+}
+
+// y_t = (A x)_t for owner threads, as blk_apply, with the entries from registers.
+template <int N1C, int P>
+__device__ __forceinline__ double reg_apply(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                            const RegOp<N1C, P>& R,
+                                            const double* __restrict__ x) {
+  constexpr int n1 = N1C, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
+  const int t = threadIdx.x;
+  if (R.ni > 0) {
+    double xs[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) xs[q] = q < R.wx ? x[R.xoff + q] : 0.0;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < WM; ++q) acc += R.a[i][q] * xs[q];
+      if (i < R.ni) W.P[R.pd[i]] = acc;
+    }
+  }
+  __syncthreads();
+  double y = 0.0;
+  if (t < n1 * n1) {
+    const int wiy = st_w(t / n1, P, N1C - 1);
+    const double* pr = W.P + t * W.WB;
+    for (int q = 0; q < wiy; ++q) y += pr[q];
+  }
+  return y;
+}
+
+template <int STAGE, int N1C, int P>
+__device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const long e,
+                                                 BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                                 StageCommon& C) {
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  double* const Aop = W.A;
+  const double* const Shalf = a.el.S + e * g.nst;
+  const int* const bdst = a.blk_dst;
+  const int nst = g.nst;
+  stage_prologue<STAGE>(a, e, C, [Aop, Shalf, bdst, nst]() { blk_load(nst, Aop, Shalf, bdst); });
+  if (own) W.U[pidx] = C.U[t];
+  RegOp<N1C, P> R;
+  reg_fetch(W, R);               // the operator is complete after the prologue's barriers
+  __syncthreads();
+  // the LDS operator is free again: bring in M_J now, its loads overlap the S_hat solve
+  if (a.mapped) blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
+  auto applyS = [&W, &R](const double* v) { return reg_apply(W, R, v); };
+  // r = -S_K U + F_v
+  {
+    const double su = applyS(W.U);
+    if (own) C.rv[t] -= su;
+  }
+  // ---- S_hat y = F_u ------------------------------------------------------------------
+  double dS = 1.0;
+  if (own) {
+    const int kx = t % n1, ky = t / n1;
+    dS = t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky];
+    if (a.el.dlog && t > 0) dS *= exp((double)a.el.dlog[e * nn + t]);
+    W.DI[pidx] = 1.0 / dS;
+  }
+  double y = C.xs0;
+  int itS = blk_solve_g(W, applyS, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit,
+                        false);
+  if (itS > a.maxit && a.el.dlog) {
+    if (own) {
+      const int kx = t % n1, ky = t / n1;
+      W.DI[pidx] = 1.0 / (t == 0 ? C.d00 : C.kbr * C.lamr[kx] + C.kbs * C.lamr[ky]);
+    }
+    y = C.xs0;
+    itS = blk_solve_g(W, applyS, C.red, y, own ? C.Fu[t] : 0.0, C.cw, C.wt, a.rtol, a.maxit,
+                      false);
+  }
+  __syncthreads();
+  // ---- M_J z = r --------------------------------------------------------------------
+  int itM;
+  double z;
+  if (own) W.DI[pidx] = 1.0 / C.area;
+  if (a.mapped) {
+    reg_fetch(W, R);             // M_J's block layout is complete after the barriers above
+    z = C.xm0;
+    itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false);
+  } else {
+    // Cartesian: the preconditioner is the exact inverse of M_J
+    double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
+    if (own) W.R[pidx] = C.rv[t];
+    block_sum<1>(bb1, C.red, nn);
+    blk_pinv(W, W.R, W.U);
+    z = own ? W.U[pidx] : 0.0;
+    itM = bb1[0] > 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM);
+}
+
 template <int N1C>
 __device__ __forceinline__ void pcg2m_stage_carve(const PcgStageArgs& a, BlockSolve<N1C, float>& W,
                                                   StageCommon& C) {
@@ -1404,8 +1581,9 @@ __device__ __forceinline__ void pcg2m_stage_carve(const PcgStageArgs& a, BlockSo
   stage_carve_small(g, sp, ip, preg, C);
 }
 
-template <int N1C, typename TA>
-__device__ __forceinline__ void blk_load_tables(const PcgStageArgs& a, const BlockSolve<N1C, TA>& W,
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ void blk_load_tables(const PcgStageArgs& a,
+                                                const BlockSolve<N1C, TA, MT>& W,
                                                 const StageCommon& C) {
   constexpr int NP = N1C + 1, nn = N1C * N1C;
   const int t = threadIdx.x;
@@ -1498,8 +1676,6 @@ __device__ __forceinline__ void pcg2m_stage_elem(const PcgStageArgs& a, const lo
   stage_epilogue<STAGE>(a, e, C, own ? y : 0.0, own ? z : 0.0, itS, itM, swS, swM);
 }
 
-// At most 768 threads (12 waves, 3 per SIMD), so that a lane may hold 170 VGPRs.
-constexpr int kBlkMaxThreads = 768;
 
 // Grouped, persistent form over the elements of several problems (each with its own
 // geometry and LDS layout, all fitting the launch's LDS size and block size).  Problem i
@@ -1507,10 +1683,13 @@ constexpr int kBlkMaxThreads = 768;
 // N1C > 0: every member uses the column-block layout with N + 1 = N1C; N1C = 0: every
 // member uses the row layout.
 template <int STAGE, int KEY>
-__global__ __launch_bounds__(KEY > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_group(
+__global__ __launch_bounds__((KEY & 64) ? kRegMaxThreads : KEY > 0 ? kBlkMaxThreads : 1024)
+void k_pcg_stage_group(
     const PcgStageArgs* __restrict__ args, const long* __restrict__ el_start, int nprob) {
   constexpr int N1C = KEY & 31;            // N + 1 of the column-block families
-  constexpr bool MIX = KEY >= 32;          // FP32 operator + FP64 refinement
+  constexpr bool MIX = (KEY & 32) != 0;    // FP32 operator + FP64 refinement
+  constexpr bool REG = (KEY & 64) != 0;    // FP64 operator in registers, degree KEY >> 7
+  constexpr int PK = KEY >> 7;
   const long total = el_start[nprob];
   int pi = 0, cur = -1;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
@@ -1533,6 +1712,14 @@ __global__ __launch_bounds__(KEY > 0 ? kBlkMaxThreads : 1024) void k_pcg_stage_g
         cur = pi;
       }
       pcg2m_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
+    } else if constexpr (REG) {
+      BlockSolve<N1C, double, kRegMaxThreads> W;
+      pcg2_stage_carve<N1C, kRegMaxThreads>(a, W, C);
+      if (pi != cur) {
+        blk_load_tables<N1C, double>(a, W, C);
+        cur = pi;
+      }
+      pcg2r_stage_elem<STAGE, N1C, PK>(a, b - el_start[pi], W, C);
     } else {
       BlockSolve<N1C> W;
       pcg2_stage_carve<N1C>(a, W, C);
@@ -1675,6 +1862,8 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
                      int* nnz, int* threads, int mixed) {
   const int n1 = g.n1, N = g.N, p = g.p, nn = g.nn;
   if (n1 != 9 && n1 != 13 && n1 != 17) return 0;
+  // the register-operator kernels run on fewer threads with taller chunks
+  const int maxt = pcg_family_key(n1, p, 1, mixed) & 64 ? kRegMaxThreads : kBlkMaxThreads;
   boff.assign(nn, 0);
   int off = 0, wb = 0;
   for (int jy = 0; jy < n1; ++jy)
@@ -1687,7 +1876,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
   for (ch = 1; ch <= 4; ++ch) {
     kk = 0;
     for (int jy = 0; jy < n1; ++jy) kk += (st_w(jy, p, N) + ch - 1) / ch;
-    if (n1 * kk <= kBlkMaxThreads) break;
+    if (n1 * kk <= maxt) break;
   }
   if (ch > 4 || kk > 255) return 0;
   jc.clear();
@@ -1713,9 +1902,9 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
   *CH = ch;
   *WB = wb;
   *nnz = off;
-  const int sp = 4 * nn <= 1024 ? 4 : 2;        // lanes per output in blk_pinv
+  const int sp = blk_pinv_split(nn, maxt);      // lanes per output in blk_pinv
   *threads = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
-  if (*threads > kBlkMaxThreads) return 0;
+  if (*threads > maxt) return 0;
   return 1;
 }
 
@@ -1741,6 +1930,21 @@ int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds) {
   return threads >= ((a.g.nn + 63) / 64) * 64;
 }
 
+// Kernel families of the grouped stage kernel: 0 (row layout), N + 1 (column blocks,
+// FP64 operator in LDS), N + 1 + 32 (mixed), N + 1 + 64 + 128 p (FP64 operator in registers).
+#define GDW_REG_KEY(n1, p) ((n1) | 64 | ((p) << 7))
+#define GDW_PCG_KEYS(X)                                                                   \
+  X(0) X(9) X(13) X(17) X(41) X(45) X(49)                                                 \
+  X(GDW_REG_KEY(9, 3)) X(GDW_REG_KEY(9, 5)) X(GDW_REG_KEY(9, 7)) X(GDW_REG_KEY(13, 3))   \
+  X(GDW_REG_KEY(13, 5))
+
+static bool pcg_key_known(int key) {
+#define GDW_K(k) if (key == (k)) return true;
+  GDW_PCG_KEYS(GDW_K)
+#undef GDW_K
+  return false;
+}
+
 template <int STAGE, int N1C>
 static hipError_t launch_group_k(const PcgStageArgs* args, const long* el_start, int nprob,
                                  unsigned grid, int threads, size_t lds, hipStream_t st) {
@@ -1750,17 +1954,15 @@ static hipError_t launch_group_k(const PcgStageArgs* args, const long* el_start,
 }
 
 template <int STAGE>
-static hipError_t launch_group_n1(int n1, const PcgStageArgs* args, const long* el_start,
+static hipError_t launch_group_n1(int key, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds,
                                   hipStream_t st) {
-  switch (n1) {
-    case 9: return launch_group_k<STAGE, 9>(args, el_start, nprob, grid, threads, lds, st);
-    case 13: return launch_group_k<STAGE, 13>(args, el_start, nprob, grid, threads, lds, st);
-    case 17: return launch_group_k<STAGE, 17>(args, el_start, nprob, grid, threads, lds, st);
-    case 9 + 32: return launch_group_k<STAGE, 41>(args, el_start, nprob, grid, threads, lds, st);
-    case 13 + 32: return launch_group_k<STAGE, 45>(args, el_start, nprob, grid, threads, lds, st);
-    case 17 + 32: return launch_group_k<STAGE, 49>(args, el_start, nprob, grid, threads, lds, st);
-    default: return launch_group_k<STAGE, 0>(args, el_start, nprob, grid, threads, lds, st);
+  switch (key) {
+#define GDW_K(k) \
+    case k: return launch_group_k<STAGE, k>(args, el_start, nprob, grid, threads, lds, st);
+    GDW_PCG_KEYS(GDW_K)
+#undef GDW_K
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1777,17 +1979,16 @@ static hipError_t group_attrs() {
 }
 
 hipError_t pcg_group_prepare() {
-  hipError_t e;
-  if ((e = group_attrs<0>()) != hipSuccess) return e;
-  if ((e = group_attrs<9>()) != hipSuccess) return e;
-  if ((e = group_attrs<13>()) != hipSuccess) return e;
-  if ((e = group_attrs<17>()) != hipSuccess) return e;
-  if ((e = group_attrs<41>()) != hipSuccess) return e;
-  if ((e = group_attrs<45>()) != hipSuccess) return e;
-  return group_attrs<49>();
+  hipError_t e = hipSuccess;
+#define GDW_K(k) if (e == hipSuccess) e = group_attrs<k>();
+  GDW_PCG_KEYS(GDW_K)
+#undef GDW_K
+  return e;
 }
 
-int pcg_group_max_threads(int key) { return key > 0 ? kBlkMaxThreads : 1024; }
+int pcg_group_max_threads(int key) {
+  return (key & 64) ? kRegMaxThreads : key > 0 ? kBlkMaxThreads : 1024;
+}
 
 hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, const long* el_start,
                                   int nprob, unsigned grid, int threads, size_t lds, hipStream_t st) {
@@ -1805,13 +2006,11 @@ hipError_t launch_pcg_stage_group(int stage, int n1, const PcgStageArgs* args, c
 template <int STAGE>
 static const void* group_kernel_n1(int key) {
   switch (key) {
-    case 9: return (const void*)k_pcg_stage_group<STAGE, 9>;
-    case 13: return (const void*)k_pcg_stage_group<STAGE, 13>;
-    case 17: return (const void*)k_pcg_stage_group<STAGE, 17>;
-    case 41: return (const void*)k_pcg_stage_group<STAGE, 41>;
-    case 45: return (const void*)k_pcg_stage_group<STAGE, 45>;
-    case 49: return (const void*)k_pcg_stage_group<STAGE, 49>;
-    default: return (const void*)k_pcg_stage_group<STAGE, 0>;
+#define GDW_K(k) \
+    case k: return (const void*)k_pcg_stage_group<STAGE, k>;
+    GDW_PCG_KEYS(GDW_K)
+#undef GDW_K
+    default: return nullptr;
   }
 }
 
@@ -1821,7 +2020,14 @@ unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel) {
   return persistent_grid(k, threads, lds, nel);
 }
 
-int pcg_group_key(const PcgStageArgs& a) { return a.v2 ? a.g.n1 + (a.mixed ? 32 : 0) : 0; }
+int pcg_family_key(int n1, int p, int v2, int mixed) {
+  if (!v2) return 0;
+  if (mixed) return n1 + 32;
+  const int rk = GDW_REG_KEY(n1, p);
+  return pcg_key_known(rk) ? rk : n1;
+}
+
+int pcg_group_key(const PcgStageArgs& a) { return pcg_family_key(a.g.n1, a.g.p, a.v2, a.mixed); }
 
 int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds) {
   if (a.v2) {
