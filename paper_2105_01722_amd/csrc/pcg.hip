@@ -1045,8 +1045,9 @@ __device__ __forceinline__ double blk_apply(const BlockSolve<N1C, TA, MT>& W,
 // split its sum over the contracted index and combine the parts with DPP lane moves, so
 // that one batch of LDS loads per lane covers a phase.
 template <int N1C, typename TA, int MT>
-__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
-                                         const double* __restrict__ R, double* __restrict__ out) {
+__device__ __forceinline__ void blk_pinv_lanes(const BlockSolve<N1C, TA, MT>& W,
+                                               const double* __restrict__ R,
+                                               double* __restrict__ out) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
   constexpr int SP = blk_pinv_split(nn, MT);
   constexpr int NT = (n1 + SP - 1) / SP;          // terms per lane
@@ -1100,6 +1101,76 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
   s = combine(s);
   if (act && part == 0) out[a * NP + b] = s;
   __syncthreads();
+}
+
+typedef double pcg_d4 __attribute__((ext_vector_type(4)));
+
+// The same four transforms on the FP64 matrix cores, for N + 1 <= 16: each is a 16 x 16 x 16
+// product (zero padded) done by one wave as four v_mfma_f64_16x16x4 steps.  Lane l = 16 g + c
+// holds A[c][4 s + g] and B[4 s + g][c] of step s and gets D[4 r + g][c] in register r.  So a
+// product's D registers are the A operand of the next product read as a transpose
+// (D[4 s + g][c] taken as A[c][4 s + g]), and the chain alternates
+//   T1^T = R^T Psi,   T2 = T1 Psi,   Z = DI o T2,   T3^T = Z^T Psi^T,   out = T3 Psi^T
+// with only R read from and only out written to LDS.  The other waves wait at the closing
+// barrier.
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ void blk_pinv_mfma(const BlockSolve<N1C, TA, MT>& W,
+                                              const double* __restrict__ R,
+                                              double* __restrict__ out) {
+  static_assert(N1C <= 16, "one 16 x 16 tile");
+  constexpr int n1 = N1C, NP = N1C + 1;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int c = t & 15, g = t >> 4;
+    const double* Ps = W.Psi;
+    const bool cin = c < n1;
+    double psk[4], pks[4];          // Psi[4s+g][c] and Psi[c][4s+g]
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + g;
+      const bool in = cin && k < n1;
+      psk[s] = in ? Ps[k * NP + c] : 0.0;
+      pks[s] = in ? Ps[c * NP + k] : 0.0;
+    }
+    pcg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + g;
+      const double rv = (cin && k < n1) ? R[k * NP + c] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rv, psk[s], acc, 0, 0, 0);
+    }
+    pcg_d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[s], psk[s], acc2, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 4 * r + g;
+      acc2[r] *= (cin && a < n1) ? W.DI[a * NP + c] : 0.0;
+    }
+    pcg_d4 acc3 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc2[s], pks[s], acc3, 0, 0, 0);
+    pcg_d4 acc4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc4 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc3[s], pks[s], acc4, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 4 * r + g;
+      if (cin && a < n1) out[a * NP + c] = acc4[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Preconditioner application: matrix cores where the grid fits one tile.
+template <int N1C, typename TA, int MT>
+__device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
+                                         const double* __restrict__ R, double* __restrict__ out) {
+  if constexpr (N1C <= 16) blk_pinv_mfma(W, R, out);
+  else blk_pinv_lanes(W, R, out);
 }
 
 // PCG (single-reduction recurrence) on (A_op + cw w w^T) x = b; owner thread t < nn holds
