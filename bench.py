@@ -417,7 +417,7 @@ def main():
             "max_it_S": its["max_it_S"], "max_it_M": its["max_it_M"],
             "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": 78.6,
                          "unit": "TFLOP/s", "frac": flops / 78.6e12, "traffic": None,
-                         "kernel": "k_pcg_stage_group<*,13> (4 stage variants)"},
+                         "kernel": "k_pcg_stage_group<*,717> (4 stage variants; N+1 = 13, p = 5, operator in registers)"},
             "mixed": {"ms_per_step": msm / ksteps, "value": pdof * ksteps / (msm * 1e-3),
                       "speedup_vs_fp64": ms / msm, "mean_it_S": itm["mean_it_S"],
                       "mean_it_M": itm["mean_it_M"], "mean_refine_sweeps": itm["mean_refine"],

@@ -1124,13 +1124,14 @@ __device__ __forceinline__ void blk_pinv_mfma(const BlockSolve<N1C, TA, MT>& W,
     const int c = t & 15, g = t >> 4;
     const double* Ps = W.Psi;
     const bool cin = c < n1;
-    double psk[4], pks[4];          // Psi[4s+g][c] and Psi[c][4s+g]
+    double psk[4], pks[4], di[4];   // Psi[4s+g][c], Psi[c][4s+g], DI[4s+g][c]
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 4 * s + g;
       const bool in = cin && k < n1;
       psk[s] = in ? Ps[k * NP + c] : 0.0;
       pks[s] = in ? Ps[c * NP + k] : 0.0;
+      di[s] = in ? W.DI[k * NP + c] : 0.0;
     }
     pcg_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1144,10 +1145,7 @@ __device__ __forceinline__ void blk_pinv_mfma(const BlockSolve<N1C, TA, MT>& W,
     for (int s = 0; s < 4; ++s)
       acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[s], psk[s], acc2, 0, 0, 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = 4 * r + g;
-      acc2[r] *= (cin && a < n1) ? W.DI[a * NP + c] : 0.0;
-    }
+    for (int r = 0; r < 4; ++r) acc2[r] *= di[r];
     pcg_d4 acc3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
