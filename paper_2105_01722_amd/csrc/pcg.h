@@ -74,13 +74,15 @@ struct PcgStageArgs {
   const int* blk_off;   // [nn] start of block (ix, jy) at index jy*(N+1) + ix
   const int* blk_dst;   // [nst][2] block-layout positions of upper entry h and its transpose
   const int* blk_jc;    // [blk_K] work units jy | (c << 8)
+  const int* blk_gidx;  // register kernels: [CH * W][blk_threads] upper-half index of each
+                        // unit entry (-1: padding)
   int blk_K, blk_CH, blk_WB, blk_threads;
 };
 
 // Column-block layout tables for one geometry; returns 0 when the layout does not apply
 // (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
-                     std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
+                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx, int* K, int* CH, int* WB,
                      int* nnz, int* threads, int mixed);
 // FP32 hi / lo split of the upper-half operators into the column-block layout.
 hipError_t launch_split_hilo(const double* half, const int* dst, int nst, int nnz, long nel,

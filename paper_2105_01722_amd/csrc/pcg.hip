@@ -759,7 +759,8 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   //   cB[l] = sum_q wq sigma_u (K Nh)_normal B[q][l],  cD[l] = sum_q wq sigma_u (K Nh)_tangent D[q][l],
   //   cV[l] = sum_q wq c^2 s_J sigma_v B[q][l]
   // over the face cells k whose window holds l; 8 lanes per (face, node), lane kk takes
-  // cell ck0[l] + kk (at most p + 1 <= 8 cells), the lanes' parts are added by DPP.
+  // cells ck0[l] + kk, ck0[l] + kk + 8, ..., and the lanes' parts are added by DPP.  A node
+  // lies in up to p + 1 + (p - 1) / 2 windows where the closure clamps them (11 at p = 7).
   for (int base = 0; base < 4 * n1 * 8; base += blockDim.x) {
     const int fl = (base + t) >> 3, kk = (base + t) & 7;
     double cB = 0, cD = 0, cV = 0;
@@ -767,8 +768,7 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
     if (fl < 4 * n1) {
       f = fl / n1;
       l = fl - f * n1;
-      const int k = ck0[l] + kk;
-      if (k <= ck1[l]) {
+      for (int k = ck0[l] + kk; k <= ck1[l]; k += 8) {
         const int j = l - cs[k];
 #pragma unroll 2
         for (int qa = 0; qa < m; ++qa) {
@@ -1124,14 +1124,13 @@ __device__ __forceinline__ void blk_pinv_mfma(const BlockSolve<N1C, TA, MT>& W,
     const int c = t & 15, g = t >> 4;
     const double* Ps = W.Psi;
     const bool cin = c < n1;
-    double psk[4], pks[4], di[4];   // Psi[4s+g][c], Psi[c][4s+g], DI[4s+g][c]
+    double psk[4], pks[4];          // Psi[4s+g][c] and Psi[c][4s+g]
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 4 * s + g;
       const bool in = cin && k < n1;
       psk[s] = in ? Ps[k * NP + c] : 0.0;
       pks[s] = in ? Ps[c * NP + k] : 0.0;
-      di[s] = in ? W.DI[k * NP + c] : 0.0;
     }
     pcg_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1145,7 +1144,10 @@ __device__ __forceinline__ void blk_pinv_mfma(const BlockSolve<N1C, TA, MT>& W,
     for (int s = 0; s < 4; ++s)
       acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[s], psk[s], acc2, 0, 0, 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc2[r] *= di[r];
+    for (int r = 0; r < 4; ++r) {
+      const int a = 4 * r + g;
+      acc2[r] *= (cin && a < n1) ? W.DI[a * NP + c] : 0.0;
+    }
     pcg_d4 acc3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -1460,23 +1462,30 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
 }
 
 // ---------------------------------------------------------------------------------
-// Operator in registers (FP64, column-block layout).  The entries a work unit of the
-// block product multiplies are the same in every iteration of a solve, so after the
-// operator has been expanded into LDS each unit copies its CH x W entries (and its row
-// and column offsets) into registers; an iteration then reads only x and the row partials
-// from LDS.  Compiled for fixed (N + 1, p), which fixes W = min(2p + 1, N + 1) and the
-// chunk height CH chosen by the same rule as the host tables.
+// Operator in registers (FP64, column-block work units).  The entries a work unit of the
+// block product multiplies are the same in every iteration of a solve, so each unit keeps
+// its CH x W entries in registers and an iteration reads only x and the row partials from
+// LDS.  The entries come either from the operator expanded into LDS (coalesced loads of
+// the element's upper half, then a copy per unit) or, where the expanded operator does
+// not fit LDS, straight from the upper half in HBM through a per-problem index table.
+// Compiled for fixed (N + 1, p), which fixes W = min(2p + 1, N + 1) and the chunk height
+// CH chosen by the same rule as the host tables.
 // ---------------------------------------------------------------------------------
 __host__ __device__ constexpr int blk_band_c(int k, int p, int N) {
   return (k + p < N ? k + p : N) - (k - p > 0 ? k - p : 0) + 1;
 }
 __host__ __device__ constexpr int blk_ch_c(int n1, int p, int maxt) {
-  for (int ch = 1; ch <= 4; ++ch) {
+  for (int ch = 1; ch <= 8; ++ch) {
     int kk = 0;
     for (int jy = 0; jy < n1; ++jy) kk += (blk_band_c(jy, p, n1 - 1) + ch - 1) / ch;
     if (n1 * kk <= maxt) return ch;
   }
   return 0;
+}
+
+// (N + 1, p) pairs whose expanded FP64 operator exceeds LDS: gather from HBM.
+__host__ __device__ constexpr bool reg_gathers(int n1, int p) {
+  return (n1 == 13 && p == 7) || (n1 == 17 && p == 5);
 }
 
 template <int N1C, int P>
@@ -1490,8 +1499,7 @@ struct RegOp {
   int pd[CH];        // row-partial slot of each row
 };
 
-// Set up the unit geometry of this thread (once per problem: it depends only on the
-// tables) and copy the unit's entries from the LDS block layout.
+// Unit geometry of this thread and its CH x W entries, copied from the LDS block layout.
 template <int N1C, int P>
 __device__ __forceinline__ void reg_fetch(const BlockSolve<N1C, double, kRegMaxThreads>& W,
                                           RegOp<N1C, P>& R) {
@@ -1526,6 +1534,45 @@ __device__ __forceinline__ void reg_fetch(const BlockSolve<N1C, double, kRegMaxT
   }
 }
 
+// Unit geometry of this thread and its CH x W entries, gathered from the element's upper
+// half `half` (index table a.blk_gidx, slot-major so that the table reads coalesce).
+template <int N1C, int P>
+__device__ __forceinline__ void reg_gather(const PcgStageArgs& a,
+                                           const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                           RegOp<N1C, P>& R, const double* __restrict__ half) {
+  constexpr int n1 = N1C, NP = N1C + 1, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
+  const int t = threadIdx.x;
+  const int T = a.blk_threads;
+  const int* __restrict__ gi = a.blk_gidx;
+#pragma unroll
+  for (int i = 0; i < CH; ++i)
+#pragma unroll
+    for (int q = 0; q < WM; ++q) R.a[i][q] = 0.0;
+  R.xoff = 0;
+  R.wx = 0;
+  R.ni = 0;
+  if (t < n1 * W.K) {
+    const int k = t / n1, ix = t - k * n1;
+    const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
+    const int lox = st_lo(ix, P), wx = st_w(ix, P, N1C - 1);
+    const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
+    const int i0 = c * CH;
+    R.xoff = jy * NP + lox;
+    R.wx = wx;
+    R.ni = min(CH, wy - i0);
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int iy = loy + i0 + i;
+      R.pd[i] = (iy * n1 + ix) * W.WB + (jy - st_lo(iy, P));
+#pragma unroll
+      for (int q = 0; q < WM; ++q) {
+        const int h = gi[(i * WM + q) * T + t];
+        if (h >= 0) R.a[i][q] = half[h];
+      }
+    }
+  }
+}
+
 // y_t = (A x)_t for owner threads, as blk_apply, with the entries from registers.
 template <int N1C, int P>
 __device__ __forceinline__ double reg_apply(const BlockSolve<N1C, double, kRegMaxThreads>& W,
@@ -1555,6 +1602,39 @@ __device__ __forceinline__ double reg_apply(const BlockSolve<N1C, double, kRegMa
   return y;
 }
 
+template <int N1C>
+__host__ __device__ inline size_t reg_lds_doubles(const PcgGeom& g, int WB) {
+  constexpr int NP = N1C + 1;
+  return (size_t)g.nn * WB + 6 * NP * NP + common_doubles(g);
+}
+
+template <int N1C>
+__device__ __forceinline__ void pcg2r_stage_carve(const PcgStageArgs& a,
+                                                  BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                                  StageCommon& C) {
+  extern __shared__ double shd[];
+  constexpr int NP = N1C + 1, nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  W.K = a.blk_K;
+  W.CH = a.blk_CH;
+  W.WB = a.blk_WB;
+  W.p = g.p;
+  W.N = g.N;
+  double* sp = shd;
+  W.A = nullptr;
+  W.P = sp;    sp += nn * W.WB;
+  W.R = sp;    sp += NP * NP;
+  W.U = sp;    sp += NP * NP;
+  W.T = sp;    sp += NP * NP;
+  W.Z = sp;    sp += NP * NP;
+  W.DI = sp;   sp += NP * NP;
+  W.Psi = sp;  sp += NP * NP;
+  int* ip = reinterpret_cast<int*>(shd + reg_lds_doubles<N1C>(g, W.WB));
+  W.boff = ip;  ip += nn;
+  W.jc = ip;    ip += W.K;
+  stage_carve(g, sp, ip, C);
+}
+
 template <int STAGE, int N1C, int P>
 __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const long e,
                                                  BlockSolve<N1C, double, kRegMaxThreads>& W,
@@ -1564,17 +1644,25 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   const int t = threadIdx.x;
   const bool own = t < nn;
   const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
-  double* const Aop = W.A;
-  const double* const Shalf = a.el.S + e * g.nst;
-  const int* const bdst = a.blk_dst;
-  const int nst = g.nst;
-  stage_prologue<STAGE>(a, e, C, [Aop, Shalf, bdst, nst]() { blk_load(nst, Aop, Shalf, bdst); });
-  if (own) W.U[pidx] = C.U[t];
+  constexpr bool GATHER = reg_gathers(N1C, P);
   RegOp<N1C, P> R;
-  reg_fetch(W, R);               // the operator is complete after the prologue's barriers
-  __syncthreads();
-  // the LDS operator is free again: bring in M_J now, its loads overlap the S_hat solve
-  if (a.mapped) blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
+  if constexpr (GATHER) {
+    stage_prologue<STAGE>(a, e, C, []() {});
+    if (own) W.U[pidx] = C.U[t];
+    reg_gather(a, W, R, a.el.S + e * g.nst);
+    __syncthreads();
+  } else {
+    double* const Aop = W.A;
+    const double* const Shalf = a.el.S + e * g.nst;
+    const int* const bdst = a.blk_dst;
+    const int nst = g.nst;
+    stage_prologue<STAGE>(a, e, C, [Aop, Shalf, bdst, nst]() { blk_load(nst, Aop, Shalf, bdst); });
+    if (own) W.U[pidx] = C.U[t];
+    reg_fetch(W, R);             // the operator is complete after the prologue's barriers
+    __syncthreads();
+    // the LDS operator is free again: bring in M_J now
+    if (a.mapped) blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
+  }
   auto applyS = [&W, &R](const double* v) { return reg_apply(W, R, v); };
   // r = -S_K U + F_v
   {
@@ -1607,7 +1695,8 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   double z;
   if (own) W.DI[pidx] = 1.0 / C.area;
   if (a.mapped) {
-    reg_fetch(W, R);             // M_J's block layout is complete after the barriers above
+    if constexpr (GATHER) reg_gather(a, W, R, a.el.M + e * g.nst);
+    else reg_fetch(W, R);        // M_J's block layout is complete after the barriers above
     z = C.xm0;
     itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false);
   } else {
@@ -1783,7 +1872,8 @@ void k_pcg_stage_group(
       pcg2m_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
     } else if constexpr (REG) {
       BlockSolve<N1C, double, kRegMaxThreads> W;
-      pcg2_stage_carve<N1C, kRegMaxThreads>(a, W, C);
+      if constexpr (reg_gathers(N1C, PK)) pcg2r_stage_carve<N1C>(a, W, C);
+      else pcg2_stage_carve<N1C, kRegMaxThreads>(a, W, C);
       if (pi != cur) {
         blk_load_tables<N1C, double>(a, W, C);
         cur = pi;
@@ -1917,6 +2007,15 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
 // ---------------------------------------------------------------------------------
 static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K, int mixed = 0) {
   size_t nd;
+  if ((pcg_family_key(g.n1, g.p, 1, mixed) & 64) && reg_gathers(g.n1, g.p)) {
+    switch (g.n1) {
+      case 9: nd = reg_lds_doubles<9>(g, WB); break;
+      case 13: nd = reg_lds_doubles<13>(g, WB); break;
+      case 17: nd = reg_lds_doubles<17>(g, WB); break;
+      default: return (size_t)-1;
+    }
+    return nd * sizeof(double) + ((size_t)g.nn + K + common_ints(g)) * sizeof(int);
+  }
   switch (g.n1) {
     case 9: nd = mixed ? mix_lds_doubles<9>(g, nnz_full, WB) : blk_lds_doubles<9>(g, nnz_full, WB); break;
     case 13: nd = mixed ? mix_lds_doubles<13>(g, nnz_full, WB) : blk_lds_doubles<13>(g, nnz_full, WB); break;
@@ -1927,12 +2026,14 @@ static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K, int m
 }
 
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
-                     std::vector<int>& dst, std::vector<int>& jc, int* K, int* CH, int* WB,
-                     int* nnz, int* threads, int mixed) {
+                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx, int* K,
+                     int* CH, int* WB, int* nnz, int* threads, int mixed) {
   const int n1 = g.n1, N = g.N, p = g.p, nn = g.nn;
   if (n1 != 9 && n1 != 13 && n1 != 17) return 0;
   // the register-operator kernels run on fewer threads with taller chunks
-  const int maxt = pcg_family_key(n1, p, 1, mixed) & 64 ? kRegMaxThreads : kBlkMaxThreads;
+  const bool reg = (pcg_family_key(n1, p, 1, mixed) & 64) != 0;
+  const int maxt = reg ? kRegMaxThreads : kBlkMaxThreads;
+  const int chmax = reg ? 8 : 4;
   boff.assign(nn, 0);
   int off = 0, wb = 0;
   for (int jy = 0; jy < n1; ++jy)
@@ -1942,12 +2043,13 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
     }
   for (int k = 0; k < n1; ++k) wb = std::max(wb, st_w(k, p, N));
   int ch = 1, kk = 0;
-  for (ch = 1; ch <= 4; ++ch) {
+  for (ch = 1; ch <= chmax; ++ch) {
     kk = 0;
     for (int jy = 0; jy < n1; ++jy) kk += (st_w(jy, p, N) + ch - 1) / ch;
     if (n1 * kk <= maxt) break;
   }
-  if (ch > 4 || kk > 255) return 0;
+  if (ch > chmax || kk > 255) return 0;
+  if (reg && ch != blk_ch_c(n1, p, kRegMaxThreads)) return 0;   // the kernel's compiled CH
   jc.clear();
   for (int jy = 0; jy < n1; ++jy) {
     const int nc = (st_w(jy, p, N) + ch - 1) / ch;
@@ -1965,15 +2067,38 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
       dst[2 * h + 1] = boff[iy * n1 + jx] + (jy - st_lo(iy, p)) * st_w(jx, p, N) + (ix - st_lo(jx, p));
     }
   }
+  const int sp = blk_pinv_split(nn, maxt);      // lanes per output in blk_pinv
+  const int thr = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
+  if (thr > maxt) return 0;
+  gidx.clear();
+  if (reg && reg_gathers(n1, p)) {
+    // upper-half index of every (unit, row, column) slot: the inverse of dst
+    std::vector<int> inv((size_t)off, -1);
+    for (int h = 0; h < g.nst; ++h) {
+      inv[dst[2 * h]] = h;
+      inv[dst[2 * h + 1]] = h;
+    }
+    const int W = std::min(2 * p + 1, n1);
+    gidx.assign((size_t)ch * W * thr, -1);
+    for (int t = 0; t < n1 * kk; ++t) {
+      const int k = t / n1, ix = t % n1;
+      const int jy = jc[k] & 0xff, c = jc[k] >> 8;
+      const int wx = st_w(ix, p, N), wy = st_w(jy, p, N);
+      for (int i = 0; i < ch && c * ch + i < wy; ++i)
+        for (int q = 0; q < wx; ++q) {
+          const int h = inv[boff[jy * n1 + ix] + (c * ch + i) * wx + q];
+          if (h < 0) return 0;                    // every block entry is an operator entry
+          gidx[((size_t)i * W + q) * thr + t] = h;
+        }
+    }
+  }
   const size_t lds = blk_lds_bytes(g, off, wb, kk, mixed);
   if (lds > 160 * 1024) return 0;
   *K = kk;
   *CH = ch;
   *WB = wb;
   *nnz = off;
-  const int sp = blk_pinv_split(nn, maxt);      // lanes per output in blk_pinv
-  *threads = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
-  if (*threads > maxt) return 0;
+  *threads = thr;
   return 1;
 }
 
@@ -2005,7 +2130,7 @@ int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds) {
 #define GDW_PCG_KEYS(X)                                                                   \
   X(0) X(9) X(13) X(17) X(41) X(45) X(49)                                                 \
   X(GDW_REG_KEY(9, 3)) X(GDW_REG_KEY(9, 5)) X(GDW_REG_KEY(9, 7)) X(GDW_REG_KEY(13, 3))   \
-  X(GDW_REG_KEY(13, 5))
+  X(GDW_REG_KEY(13, 5)) X(GDW_REG_KEY(13, 7)) X(GDW_REG_KEY(17, 3)) X(GDW_REG_KEY(17, 5))
 
 static bool pcg_key_known(int key) {
 #define GDW_K(k) if (key == (k)) return true;
