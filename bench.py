@@ -343,9 +343,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "repeats": 5}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path "
+        print("bench.py measures one GPU only; the library has no multi-GPU path "
               "(the element grid would shard by blocks with one face-trace exchange per "
-              "RK stage, see DESIGN.md)", file=sys.stderr)
+              "RK stage)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

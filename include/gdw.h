@@ -42,7 +42,7 @@ typedef enum {
   GDW_EHIP = -3,          /* a HIP runtime call failed                           */
   GDW_ENOCONV = -4,       /* an element solve did not converge (PCG path)        */
   GDW_ENONFINITE = -5,    /* NaN or Inf found in the state after a run            */
-  GDW_EUNSUPPORTED = -6   /* a valid request this build does not implement        */
+  GDW_EUNSUPPORTED = -6   /* a valid request the library does not implement      */
 } gdw_status;
 
 /* Numerical flux (Sec. 2.2.1): central alpha = 1/2, beta = tau = 0; upwind

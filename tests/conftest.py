@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) when no GPU is visible, so that a plain
-    # `pytest` on a CPU-only machine stays green; `-m gpu` on the GPU machine runs them.
+    # `pytest` on a CPU-only machine stays green; `-m gpu` on a machine with a GPU runs them.
     try:
         import torch
         has_gpu = torch.cuda.is_available()

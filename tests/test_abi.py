@@ -139,3 +139,12 @@ def test_batch_arguments_rejected_on_host():
     assert gdw.lib.gdw_batch_step_times(None, None, 0) == gdw.GDW_EINVAL
     assert gdw.lib.gdw_batch_plan(None) == b""
     gdw.lib.gdw_batch_destroy(None)
+
+
+def test_bench_refuses_several_gpus_before_touching_a_device():
+    """bench.py measures one GPU: --gpus N with N > 1 exits with status 2 and a message,
+    before any device work (so this runs without a GPU)."""
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
