@@ -7,6 +7,8 @@ closed-form identities.
 """
 from fractions import Fraction
 
+import os
+
 import numpy as np
 import pytest
 
@@ -73,11 +75,12 @@ def test_p3_ghost_closure_matches_worked_example():
     phi~0 = phi0 + 4 phi_{-1}, phi~1 = phi1 - 6 phi_{-1}, phi~2 = phi2 + 4 phi_{-1},
     phi~3 = phi3 - phi_{-1}; the oracle's cell-0 basis must equal these."""
     N, p = 8, 3
+    coef = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                   "gd_p3_extrapolation_closure.txt"))[:, 1]
     t = np.linspace(0.0, 1.0, 23)[1:-1]
     phi, _ = gd1d.basis_on_cell(0, N, p, t)
     g = np.array([[_Phi(p, x - i) for i in range(-1, 4)] for x in t])  # phi_{-1..3}
-    expect = np.stack([g[:, 1] + 4 * g[:, 0], g[:, 2] - 6 * g[:, 0],
-                       g[:, 3] + 4 * g[:, 0], g[:, 4] - g[:, 0]], axis=1)
+    expect = np.stack([g[:, i + 1] + coef[i] * g[:, 0] for i in range(4)], axis=1)
     np.testing.assert_allclose(phi[:, :4], expect, atol=1e-14)
     np.testing.assert_array_equal(phi[:, 4:], 0.0)
     # right boundary is the mirror image (Sec. 2.1.1: "handled analogously")
