@@ -5,9 +5,8 @@ formula: the generating function is built here from eq. GD_basis_lagrange, the
 matrices are checked against exact rational integration, textbook FEM values and
 closed-form identities.
 """
-from fractions import Fraction
-
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
