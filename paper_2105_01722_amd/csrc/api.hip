@@ -36,6 +36,7 @@ static void free_all(gdw_ctx* c) {
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
+  F(c->el.Sreg); F(c->el.Mreg);
   F(c->el.w); F(c->el.sc); F(c->el.face);
   F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
@@ -351,6 +352,12 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
       GDW_HIP(hipMalloc(&c->el.Mlo, nb));
     }
   }
+  if (c->blk_v2 && c->blk_gidx) {
+    // slot-ordered operator copies of the register kernels that cannot stage through LDS
+    const size_t nb = (size_t)nel * pcg_reg_slots(n1, p) * c->blk_threads * sizeof(double);
+    GDW_HIP(hipMalloc(&c->el.Sreg, nb));
+    if (d->mapped) GDW_HIP(hipMalloc(&c->el.Mreg, nb));
+  }
   GDW_HIP(hipMalloc(&c->d_pargs, 4 * sizeof(PcgStageArgs)));
   GDW_HIP(hipMalloc(&c->d_pel, 2 * sizeof(long)));
   {
@@ -425,6 +432,14 @@ extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* 
   GDW_HIP(hipMemcpyAsync(c->c2n, Cd, (size_t)c->nel * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
   GDW_HIP(launch_assemble(c->g, Xd, Yd, Cd, c->el, c->nel, st));
   GDW_HIP(launch_face_geom(c->g, Xd, Yd, Cd, c->el, c->nel, st));
+  if (c->el.Sreg) {
+    const int slots = pcg_reg_slots(c->g.n1, c->g.p);
+    GDW_HIP(launch_reg_permute(c->el.S, c->blk_gidx, c->g.nst, slots, c->blk_threads, c->nel,
+                               c->el.Sreg, st));
+    if (c->el.Mreg)
+      GDW_HIP(launch_reg_permute(c->el.M, c->blk_gidx, c->g.nst, slots, c->blk_threads, c->nel,
+                                 c->el.Mreg, st));
+  }
   if (c->el.Shi) {
     GDW_HIP(launch_split_hilo(c->el.S, c->blk_dst, c->g.nst, c->blk_nnz, c->nel, c->el.Shi,
                               c->el.Slo, st));

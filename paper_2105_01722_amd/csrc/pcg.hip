@@ -1467,7 +1467,8 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
 // its CH x W entries in registers and an iteration reads only x and the row partials from
 // LDS.  The entries come either from the operator expanded into LDS (coalesced loads of
 // the element's upper half, then a copy per unit) or, where the expanded operator does
-// not fit LDS, straight from the upper half in HBM through a per-problem index table.
+// not fit LDS, from a copy of the operator that set-up permutes into work-unit slot order
+// (slot-major, so that every load of a wave is one contiguous run).
 // Compiled for fixed (N + 1, p), which fixes W = min(2p + 1, N + 1) and the chunk height
 // CH chosen by the same rule as the host tables.
 // ---------------------------------------------------------------------------------
@@ -1534,16 +1535,15 @@ __device__ __forceinline__ void reg_fetch(const BlockSolve<N1C, double, kRegMaxT
   }
 }
 
-// Unit geometry of this thread and its CH x W entries, gathered from the element's upper
-// half `half` (index table a.blk_gidx, slot-major so that the table reads coalesce).
+// Unit geometry of this thread and its CH x W entries, read from the element's slot-ordered
+// operator `reg` ([slots][blk_threads], slot-major: the loads of a wave are contiguous).
 template <int N1C, int P>
 __device__ __forceinline__ void reg_gather(const PcgStageArgs& a,
                                            const BlockSolve<N1C, double, kRegMaxThreads>& W,
-                                           RegOp<N1C, P>& R, const double* __restrict__ half) {
+                                           RegOp<N1C, P>& R, const double* __restrict__ reg) {
   constexpr int n1 = N1C, NP = N1C + 1, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
   const int t = threadIdx.x;
   const int T = a.blk_threads;
-  const int* __restrict__ gi = a.blk_gidx;
 #pragma unroll
   for (int i = 0; i < CH; ++i)
 #pragma unroll
@@ -1557,18 +1557,17 @@ __device__ __forceinline__ void reg_gather(const PcgStageArgs& a,
     const int lox = st_lo(ix, P), wx = st_w(ix, P, N1C - 1);
     const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
     const int i0 = c * CH;
+    const int ni = min(CH, wy - i0);
     R.xoff = jy * NP + lox;
     R.wx = wx;
-    R.ni = min(CH, wy - i0);
+    R.ni = ni;
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       const int iy = loy + i0 + i;
       R.pd[i] = (iy * n1 + ix) * W.WB + (jy - st_lo(iy, P));
 #pragma unroll
-      for (int q = 0; q < WM; ++q) {
-        const int h = gi[(i * WM + q) * T + t];
-        if (h >= 0) R.a[i][q] = half[h];
-      }
+      for (int q = 0; q < WM; ++q)
+        if (i < ni && q < wx) R.a[i][q] = reg[(size_t)(i * WM + q) * T + t];
     }
   }
 }
@@ -1649,7 +1648,7 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   if constexpr (GATHER) {
     stage_prologue<STAGE>(a, e, C, []() {});
     if (own) W.U[pidx] = C.U[t];
-    reg_gather(a, W, R, a.el.S + e * g.nst);
+    reg_gather(a, W, R, a.el.Sreg + (size_t)e * RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads);
     __syncthreads();
   } else {
     double* const Aop = W.A;
@@ -1695,7 +1694,8 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   double z;
   if (own) W.DI[pidx] = 1.0 / C.area;
   if (a.mapped) {
-    if constexpr (GATHER) reg_gather(a, W, R, a.el.M + e * g.nst);
+    if constexpr (GATHER)
+      reg_gather(a, W, R, a.el.Mreg + (size_t)e * RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads);
     else reg_fetch(W, R);        // M_J's block layout is complete after the barriers above
     z = C.xm0;
     itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false);
@@ -1975,6 +1975,31 @@ hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, 
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_face_geom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, X, Y, C2,
                      el, nel);
+  return hipGetLastError();
+}
+
+__global__ void k_reg_permute(const double* __restrict__ half, const int* __restrict__ gidx,
+                              int nst, long per, long total, double* __restrict__ out) {
+  for (long id = blockIdx.x * (long)blockDim.x + threadIdx.x; id < total;
+       id += (long)gridDim.x * blockDim.x) {
+    const long e = id / per, r = id - e * per;
+    const int h = gidx[r];
+    out[id] = h >= 0 ? half[e * nst + h] : 0.0;
+  }
+}
+
+int pcg_reg_slots(int n1, int p) {
+  if (!reg_gathers(n1, p) || !(pcg_family_key(n1, p, 1, 0) & 64)) return 0;
+  return blk_ch_c(n1, p, kRegMaxThreads) * std::min(2 * p + 1, n1);
+}
+
+hipError_t launch_reg_permute(const double* half, const int* gidx, int nst, int slots,
+                              int threads, long nel, double* out, hipStream_t st) {
+  const long per = (long)slots * threads, total = per * nel;
+  if (total == 0) return hipSuccess;
+  const long nb = std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_reg_permute, dim3((unsigned)nb), dim3(256), 0, st, half, gidx, nst, per,
+                     total, out);
   return hipGetLastError();
 }
 
