@@ -353,7 +353,7 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
     }
   }
   if (c->blk_v2 && c->blk_gidx) {
-    // slot-ordered operator copies of the register kernels that cannot stage through LDS
+    // slot-ordered operator copies read by the register kernels
     const size_t nb = (size_t)nel * pcg_reg_slots(n1, p) * c->blk_threads * sizeof(double);
     GDW_HIP(hipMalloc(&c->el.Sreg, nb));
     if (d->mapped) GDW_HIP(hipMalloc(&c->el.Mreg, nb));

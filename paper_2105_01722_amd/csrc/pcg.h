@@ -41,8 +41,8 @@ struct PcgElem {
   double* sc;           // [nel][8]: kappa/area, kbar_rr, kbar_ss, kappa*area, area, int c^2 J
   double* face;         // [nel][4][nq][3]: (K Nh)_r, (K Nh)_s, c^2 s_J at face points
   float* dlog;          // [nel][nn] log-scale of the S preconditioner diagonal (NULL: plain)
-  double* Sreg;         // register kernels whose expanded operator exceeds LDS: S_K in work-unit
-  double* Mreg;         // slot order, [nel][slots][blk_threads] (0 in padding slots); M_J alike
+  double* Sreg;         // register kernels: S_K in work-unit slot order,
+  double* Mreg;         // [nel][slots][blk_threads] (0 in padding slots); M_J alike
 };
 
 struct PcgStageArgs {
@@ -87,8 +87,8 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
                      std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx, int* K, int* CH, int* WB,
                      int* nnz, int* threads, int mixed);
 // FP32 hi / lo split of the upper-half operators into the column-block layout.
-// Work-unit slots per thread (CH x W) of the register kernels that load their entries from
-// a slot-ordered copy of the operator (N + 1 = 13, p = 7 and N + 1 = 17, p = 5); 0 otherwise.
+// Work-unit slots per thread (CH x W) of the register kernels, which load their entries from
+// a slot-ordered copy of the operator; 0 for the other kernel families.
 int pcg_reg_slots(int n1, int p);
 // out[e][s][t] = half[e][gidx[s * threads + t]] (0 where gidx < 0), for every element.
 hipError_t launch_reg_permute(const double* half, const int* gidx, int nst, int slots,

@@ -1465,10 +1465,9 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
 // Operator in registers (FP64, column-block work units).  The entries a work unit of the
 // block product multiplies are the same in every iteration of a solve, so each unit keeps
 // its CH x W entries in registers and an iteration reads only x and the row partials from
-// LDS.  The entries come either from the operator expanded into LDS (coalesced loads of
-// the element's upper half, then a copy per unit) or, where the expanded operator does
-// not fit LDS, from a copy of the operator that set-up permutes into work-unit slot order
-// (slot-major, so that every load of a wave is one contiguous run).
+// LDS.  The entries come from a copy of the operator that set-up permutes into work-unit
+// slot order (slot-major, so that every load of a wave is one contiguous run); the
+// operator never passes through LDS, which holds only the vectors and row partials.
 // Compiled for fixed (N + 1, p), which fixes W = min(2p + 1, N + 1) and the chunk height
 // CH chosen by the same rule as the host tables.
 // ---------------------------------------------------------------------------------
@@ -1484,11 +1483,6 @@ __host__ __device__ constexpr int blk_ch_c(int n1, int p, int maxt) {
   return 0;
 }
 
-// (N + 1, p) pairs whose expanded FP64 operator exceeds LDS: gather from HBM.
-__host__ __device__ constexpr bool reg_gathers(int n1, int p) {
-  return (n1 == 13 && p == 7) || (n1 == 17 && p == 5);
-}
-
 template <int N1C, int P>
 struct RegOp {
   static constexpr int W = 2 * P + 1 < N1C ? 2 * P + 1 : N1C;
@@ -1499,41 +1493,6 @@ struct RegOp {
   int wx, ni;        // columns and rows of the unit (0 rows: no unit)
   int pd[CH];        // row-partial slot of each row
 };
-
-// Unit geometry of this thread and its CH x W entries, copied from the LDS block layout.
-template <int N1C, int P>
-__device__ __forceinline__ void reg_fetch(const BlockSolve<N1C, double, kRegMaxThreads>& W,
-                                          RegOp<N1C, P>& R) {
-  constexpr int n1 = N1C, NP = N1C + 1, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < CH; ++i)
-#pragma unroll
-    for (int q = 0; q < WM; ++q) R.a[i][q] = 0.0;
-  R.xoff = 0;
-  R.wx = 0;
-  R.ni = 0;
-  if (t < n1 * W.K) {
-    const int k = t / n1, ix = t - k * n1;
-    const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
-    const int lox = st_lo(ix, P), wx = st_w(ix, P, N1C - 1);
-    const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
-    const int i0 = c * CH;
-    const int ni = min(CH, wy - i0);
-    R.xoff = jy * NP + lox;
-    R.wx = wx;
-    R.ni = ni;
-    const double* Ab = W.A + W.boff[jy * n1 + ix] + i0 * wx;
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int iy = loy + i0 + i;
-      R.pd[i] = (iy * n1 + ix) * W.WB + (jy - st_lo(iy, P));
-#pragma unroll
-      for (int q = 0; q < WM; ++q)
-        if (i < ni && q < wx) R.a[i][q] = Ab[i * wx + q];
-    }
-  }
-}
 
 // Unit geometry of this thread and its CH x W entries, read from the element's slot-ordered
 // operator `reg` ([slots][blk_threads], slot-major: the loads of a wave are contiguous).
@@ -1643,25 +1602,12 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   const int t = threadIdx.x;
   const bool own = t < nn;
   const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
-  constexpr bool GATHER = reg_gathers(N1C, P);
+  const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads;
   RegOp<N1C, P> R;
-  if constexpr (GATHER) {
-    stage_prologue<STAGE>(a, e, C, []() {});
-    if (own) W.U[pidx] = C.U[t];
-    reg_gather(a, W, R, a.el.Sreg + (size_t)e * RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads);
-    __syncthreads();
-  } else {
-    double* const Aop = W.A;
-    const double* const Shalf = a.el.S + e * g.nst;
-    const int* const bdst = a.blk_dst;
-    const int nst = g.nst;
-    stage_prologue<STAGE>(a, e, C, [Aop, Shalf, bdst, nst]() { blk_load(nst, Aop, Shalf, bdst); });
-    if (own) W.U[pidx] = C.U[t];
-    reg_fetch(W, R);             // the operator is complete after the prologue's barriers
-    __syncthreads();
-    // the LDS operator is free again: bring in M_J now
-    if (a.mapped) blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
-  }
+  stage_prologue<STAGE>(a, e, C, []() {});
+  if (own) W.U[pidx] = C.U[t];
+  reg_gather(a, W, R, a.el.Sreg + e * per);
+  __syncthreads();
   auto applyS = [&W, &R](const double* v) { return reg_apply(W, R, v); };
   // r = -S_K U + F_v
   {
@@ -1694,9 +1640,7 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   double z;
   if (own) W.DI[pidx] = 1.0 / C.area;
   if (a.mapped) {
-    if constexpr (GATHER)
-      reg_gather(a, W, R, a.el.Mreg + (size_t)e * RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads);
-    else reg_fetch(W, R);        // M_J's block layout is complete after the barriers above
+    reg_gather(a, W, R, a.el.Mreg + e * per);
     z = C.xm0;
     itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false);
   } else {
@@ -1872,8 +1816,7 @@ void k_pcg_stage_group(
       pcg2m_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
     } else if constexpr (REG) {
       BlockSolve<N1C, double, kRegMaxThreads> W;
-      if constexpr (reg_gathers(N1C, PK)) pcg2r_stage_carve<N1C>(a, W, C);
-      else pcg2_stage_carve<N1C, kRegMaxThreads>(a, W, C);
+      pcg2r_stage_carve<N1C>(a, W, C);
       if (pi != cur) {
         blk_load_tables<N1C, double>(a, W, C);
         cur = pi;
@@ -1989,7 +1932,7 @@ __global__ void k_reg_permute(const double* __restrict__ half, const int* __rest
 }
 
 int pcg_reg_slots(int n1, int p) {
-  if (!reg_gathers(n1, p) || !(pcg_family_key(n1, p, 1, 0) & 64)) return 0;
+  if (!(pcg_family_key(n1, p, 1, 0) & 64)) return 0;
   return blk_ch_c(n1, p, kRegMaxThreads) * std::min(2 * p + 1, n1);
 }
 
@@ -2032,7 +1975,7 @@ hipError_t launch_pcg_traces(const PcgGeom& g, const PcgElem& el, const double* 
 // ---------------------------------------------------------------------------------
 static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K, int mixed = 0) {
   size_t nd;
-  if ((pcg_family_key(g.n1, g.p, 1, mixed) & 64) && reg_gathers(g.n1, g.p)) {
+  if (pcg_family_key(g.n1, g.p, 1, mixed) & 64) {
     switch (g.n1) {
       case 9: nd = reg_lds_doubles<9>(g, WB); break;
       case 13: nd = reg_lds_doubles<13>(g, WB); break;
@@ -2096,7 +2039,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
   const int thr = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
   if (thr > maxt) return 0;
   gidx.clear();
-  if (reg && reg_gathers(n1, p)) {
+  if (reg) {
     // upper-half index of every (unit, row, column) slot: the inverse of dst
     std::vector<int> inv((size_t)off, -1);
     for (int h = 0; h < g.nst; ++h) {
