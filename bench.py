@@ -11,8 +11,10 @@ RK4 step (4 fused stage kernels) over all 18,939,904 DOF per field.
 Printed: ONE JSON line.  `value` = DOF-updates/s in FP64 (nx*ny*(N+1)^2 * steps /
 time; inputs resident in HBM).  Also reported: the FP32-storage mode, the error of
 both against the exact solution, the roofline of the stage kernel (algorithmic HBM
-bytes per launch / measured average launch time) and the FP64 CPU oracle timed on a
-bounded sample on the host.
+bytes per launch / measured average launch time), the variable-coefficient mapped PCG
+workload in FP64 and in mixed precision (`pcg`), the learned preconditioner (`learned`),
+the 64-problem batch (`batch`) and the FP64 CPU oracle timed on a bounded sample on the
+host (`cpu_baseline`).
 """
 import argparse
 import json
