@@ -38,6 +38,10 @@ PROBLEMS = [
     dict(nx=2, ny=3, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
          pcg_rtol=1e-13),
     dict(nx=3, ny=2, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True, pcg_rtol=1e-13),
+    dict(nx=2, ny=2, N=16, p=5, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
+         pcg_rtol=1e-13),
+    dict(nx=2, ny=3, N=12, p=7, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
+         pcg_rtol=1e-13),
 ]
 
 
@@ -88,6 +92,7 @@ def test_batch_equals_solo_runs_and_rebuilds_on_new_dt():
     plan = b.plan()
     _say(plan.split("candidates:")[0])
     assert "fdm n1=9" in plan and "pcg blocks n1=13" in plan
+    assert "n1=17 (registers, p=5)" in plan and "n1=13 (registers, p=7)" in plan
     b.run(dts, 3)
     times = b.step_times()
     assert len(times) == 3 and all(t > 0 for t in times)
