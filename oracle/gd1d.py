@@ -7,8 +7,8 @@ nodal form eq. GD_basis_nodalformula), Sec. 2.1.1 (extrapolation closure and the
 p = 3 worked example), Sec. 3.1 (1D mass and stiffness, bandwidth p) and
 Sec. 3.2 (surface vectors phi(L), phi(R), phi'(L), phi'(R)).
 
-Reading used here (the paper states the closure only for p = 3 and says that
-larger p extrapolate "at the order of the interior scheme"): ghost values are
+Reading used here (the paper states the closure only for p = 3; for larger p it
+extrapolates to the accuracy of the interior formulas): ghost values are
 the degree-p polynomial through nodes 0..p (N-p..N on the right).  On a cell
 whose interior stencil reaches a ghost node every stencil value then lies on
 that polynomial, so the cell interpolant *is* that polynomial.  Hence on cell k

@@ -82,7 +82,7 @@ def test_p3_ghost_closure_matches_worked_example():
     expect = np.stack([g[:, i + 1] + coef[i] * g[:, 0] for i in range(4)], axis=1)
     np.testing.assert_allclose(phi[:, :4], expect, atol=1e-14)
     np.testing.assert_array_equal(phi[:, 4:], 0.0)
-    # right boundary is the mirror image (Sec. 2.1.1: "handled analogously")
+    # the right boundary is the mirror image (Sec. 2.1.1 treats it the same way)
     phiR, _ = gd1d.basis_on_cell(N - 1, N, p, N - t)
     np.testing.assert_allclose(phiR[:, ::-1][:, :4], expect, atol=1e-14)
 
