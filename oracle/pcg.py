@@ -10,13 +10,17 @@ averages:
 
   P_S = Psi_2^{-T} diag(D) Psi_2^{-1},  D_(ky,kx) = kbar_rr lam_kx + kbar_ss lam_ky,
         D_(0,0) = kappa |Omega_k|,
-  P_M = Psi_2^{-T} diag(|Omega_k|) Psi_2^{-1},
+  P_M = S^-1 Psi_2^{-T} diag(|Omega_k|) Psi_2^{-1} S^-1,  S = diag(s),
+        s_i = sqrt(|Omega_k| Mref_(iy,iy) Mref_(ix,ix) / (M_J)_ii),
 
 with Psi, lam the simultaneous diagonalisation of the 1D GD stiffness and mass
 matrices on the reference interval [0, 1] (Psi^T M_ref Psi = I), kbar_rr = int K_rr,
 kbar_ss = int K_ss over the reference square, kappa the element-mean c^2 and
-|Omega_k| = int J.  So P^{-1} r = Psi_2 diag(1/D) Psi_2^T r.  On a Cartesian element with
-constant c^2, P_S = S_hat and P_M = M_J exactly (PCG converges in one iteration).
+|Omega_k| = int J.  So P_S^{-1} r = Psi_2 diag(1/D) Psi_2^T r and
+P_M^{-1} r = s o (Psi_2 Psi_2^T (s o r)) / |Omega_k|.  The nodal scale s gives P_M the
+diagonal of M_J (Psi_2^{-T} Psi_2^{-1} = Mref (x) Mref, the reference mass), which follows
+the Jacobian's variation inside the element.  On a Cartesian element with constant c^2,
+P_S = S_hat and P_M = M_J exactly (s = 1; PCG converges in one iteration).
 
 Stopping rule: ||b - A x||_2 <= rtol ||b||_2 (true residual, recomputed each iteration
 from the recurrence), at most maxit iterations; x0 = the previous solution of the
@@ -58,14 +62,22 @@ class TensorPreconditioner:
             D = Df.reshape(ne, n1, n1)
         self.DS = D
         self.DM = ops.area.copy()
+        Mh, _ = gd1d.matrices_unit(prob.N, prob.p)
+        m = np.diag(Mh) / prob.N                     # diagonal of the reference mass on [0, 1]
+        dPM = ops.area[:, None] * np.outer(m, m).ravel()[None, :]     # index iy*(N+1) + ix
+        dMJ = np.stack([np.diag(ops.M[e]) for e in range(ne)])
+        self.sM = np.sqrt(dPM / dMJ)
 
     def apply(self, e, r, which):
         """P^{-1} r for element e; r is a flat (N+1)^2 vector (index iy*(N+1) + ix)."""
         n1, Psi = self.n1, self.Psi
+        if which == "M":
+            r = self.sM[e] * r
         R = r.reshape(n1, n1)
         Rh = Psi.T @ R @ Psi                        # [ky, kx]
         Rh = Rh / (self.DS[e] if which == "S" else self.DM[e])
-        return (Psi @ Rh @ Psi.T).ravel()
+        z = (Psi @ Rh @ Psi.T).ravel()
+        return self.sM[e] * z if which == "M" else z
 
 
 def pcg(A, b, x0, apply_pinv, rtol, maxit):

@@ -36,7 +36,7 @@ static void free_all(gdw_ctx* c) {
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
-  F(c->el.Sreg); F(c->el.Mreg);
+  F(c->el.Sreg); F(c->el.Mreg); F(c->el.msc);
   F(c->el.w); F(c->el.sc); F(c->el.face);
   F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
@@ -326,7 +326,10 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   const long nel = c->nel;
   const size_t nodal = (size_t)nel * nn * sizeof(double);
   GDW_HIP(hipMalloc(&c->el.S, (size_t)nel * g.nst * sizeof(double)));
-  if (d->mapped) GDW_HIP(hipMalloc(&c->el.M, (size_t)nel * g.nst * sizeof(double)));
+  if (d->mapped) {
+    GDW_HIP(hipMalloc(&c->el.M, (size_t)nel * g.nst * sizeof(double)));
+    GDW_HIP(hipMalloc(&c->el.msc, (size_t)nel * nn * sizeof(double)));
+  }
   GDW_HIP(hipMalloc(&c->el.w, nodal));
   GDW_HIP(hipMalloc(&c->el.sc, (size_t)nel * 8 * sizeof(double)));
   GDW_HIP(hipMalloc(&c->el.face, (size_t)nel * 4 * g.nq * 3 * sizeof(double)));
@@ -432,6 +435,7 @@ extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* 
   GDW_HIP(hipMemcpyAsync(c->c2n, Cd, (size_t)c->nel * nn * sizeof(double), hipMemcpyDeviceToDevice, st));
   GDW_HIP(launch_assemble(c->g, Xd, Yd, Cd, c->el, c->nel, st));
   GDW_HIP(launch_face_geom(c->g, Xd, Yd, Cd, c->el, c->nel, st));
+  if (c->el.msc) GDW_HIP(launch_mscale(c->g, c->el, c->nel, st));
   if (c->el.Sreg) {
     const int slots = pcg_reg_slots(c->g.n1, c->g.p);
     GDW_HIP(launch_reg_permute(c->el.S, c->blk_gidx, c->g.nst, slots, c->blk_threads, c->nel,

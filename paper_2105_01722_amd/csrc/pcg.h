@@ -43,6 +43,7 @@ struct PcgElem {
   float* dlog;          // [nel][nn] log-scale of the S preconditioner diagonal (NULL: plain)
   double* Sreg;         // register kernels: S_K in work-unit slot order,
   double* Mreg;         // [nel][slots][blk_threads] (0 in padding slots); M_J alike
+  double* msc;          // [nel][nn] nodal scale of the M_J preconditioner (mapped meshes)
 };
 
 struct PcgStageArgs {
@@ -90,6 +91,8 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
 // Work-unit slots per thread (CH x W) of the register kernels, which load their entries from
 // a slot-ordered copy of the operator; 0 for the other kernel families.
 int pcg_reg_slots(int n1, int p);
+// Nodal scale of the M_J preconditioner of every element into el.msc (needs el.M, el.sc).
+hipError_t launch_mscale(const PcgGeom& g, const PcgElem& el, long nel, hipStream_t st);
 // out[e][s][t] = half[e][gidx[s * threads + t]] (0 where gidx < 0), for every element.
 hipError_t launch_reg_permute(const double* half, const int* gidx, int nst, int slots,
                               int threads, long nel, double* out, hipStream_t st);

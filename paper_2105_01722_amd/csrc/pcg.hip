@@ -453,8 +453,9 @@ __device__ inline void op_load(const PcgGeom& g, const PcgShared& W, const doubl
 // cw != 0 (S_hat).  Two workgroup reductions per iteration: d.q, then
 // (r.r, r.z, w.z) after the preconditioner (z is formed before the convergence test).
 // Returns the iteration count (maxit + 1 if it did not converge).
+// sc: this owner's nodal scale of the preconditioner (P^-1 r -> sc P^-1 (sc r); 1 for S_hat).
 __device__ int pcg_solve(const PcgGeom& g, const PcgShared& W, double cw, double wt, double dinv,
-                         double rtol, int maxit) {
+                         double rtol, int maxit, double sc = 1.0) {
   const int t = threadIdx.x, nn = g.nn, n1 = g.n1;
   const bool own = t < nn;
   double s2[2] = {own ? wt * W.x[t] : 0.0, own ? W.b[t] * W.b[t] : 0.0};
@@ -467,10 +468,14 @@ __device__ int pcg_solve(const PcgGeom& g, const PcgShared& W, double cw, double
   }
   {
     const double ax = op_apply(g, W, W.x) + cw * wt * wx;
-    if (own) W.r[t] = W.b[t] - ax;
+    if (own) {
+      W.r[t] = W.b[t] - ax;
+      W.q[t] = W.r[t] * sc;
+    }
   }
   __syncthreads();
-  pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
+  pinv_apply<double>(W.q, W.tmp, W.z, W.Psi, dinv, n1, nn);
+  if (own) W.z[t] *= sc;
   double s3[3] = {own ? W.r[t] * W.r[t] : 0.0, own ? W.r[t] * W.z[t] : 0.0,
                   own ? wt * W.z[t] : 0.0};
   block_sum<3>(s3, W.red, nn);
@@ -487,9 +492,11 @@ __device__ int pcg_solve(const PcgGeom& g, const PcgShared& W, double cw, double
     if (own) {
       W.x[t] += alpha * W.d[t];
       W.r[t] -= alpha * qv;
+      W.q[t] = W.r[t] * sc;
     }
     __syncthreads();
-    pinv_apply<double>(W.r, W.tmp, W.z, W.Psi, dinv, n1, nn);
+    pinv_apply<double>(W.q, W.tmp, W.z, W.Psi, dinv, n1, nn);
+    if (own) W.z[t] *= sc;
     double s3b[3] = {own ? W.r[t] * W.r[t] : 0.0, own ? W.r[t] * W.z[t] : 0.0,
                      own ? wt * W.z[t] : 0.0};
     block_sum<3>(s3b, W.red, nn);
@@ -590,6 +597,7 @@ __device__ void face_traces_lds(const PcgGeom& g, const FaceTabs& T, const doubl
 // ---------------------------------------------------------------------------------
 struct StageCommon {
   double *U, *V, *Fu, *rv, *lamr, *lines, *red, *sig;
+  double ms = 1.0;   // this owner's nodal scale of the M_J preconditioner
   bool gtab;                                 // cb, cd, face data read from global memory
   FaceTabs T;
   double ub, vb, yu, yv, xs0, xm0, wt;      // owner thread t < nn
@@ -727,6 +735,7 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
     C.xs0 = a.xS[e * nn + t];
     C.xm0 = a.xM[e * nn + t];
     C.wt = a.el.w[e * nn + t];
+    C.ms = a.el.msc ? a.el.msc[e * nn + t] : 1.0;
   }
   const double* sc = a.el.sc + e * 8;
   C.cw = sc[0];
@@ -952,7 +961,7 @@ __device__ __forceinline__ void pcg_stage_elem(const PcgStageArgs& a, const long
       W.b[t] = C.rv[t];
     }
     __syncthreads();
-    itM = pcg_solve(g, W, 0.0, 0.0, own ? 1.0 / C.area : 0.0, a.rtol, a.maxit);
+    itM = pcg_solve(g, W, 0.0, 0.0, own ? 1.0 / C.area : 0.0, a.rtol, a.maxit, C.ms);
   } else {
     // Cartesian: M_J = |Omega| M_ref (x) M_ref = Psi_2^{-T} diag(|Omega|) Psi_2^{-1}, so the
     // preconditioner is the exact inverse (one PCG iteration).
@@ -1175,11 +1184,14 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
 
 // PCG (single-reduction recurrence) on (A_op + cw w w^T) x = b; owner thread t < nn holds
 // x (in/out, warm start on entry), b and w.  Iteration count as pcg_solve.  zero_start:
-// x = 0 on entry (the first product is skipped).
+// x = 0 on entry (the first product is skipped).  scaled (uniform over the block): the
+// preconditioner is P^-1 r -> sc P^-1 (sc r) with sc this owner's nodal scale; the scaled
+// vector is written back to W.U before the product reads it.
 template <int N1C, typename TA, int MT, typename App>
 __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App&& apply, double* red,
                                            double& x, double bval, double cw, double wt,
-                                           double rtol, int maxit, bool zero_start) {
+                                           double rtol, int maxit, bool zero_start,
+                                           bool scaled = false, double sc = 1.0) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
   const int t = threadIdx.x;
   const bool own = t < nn;
@@ -1198,10 +1210,15 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
     return 0;
   }
   double r = own ? bval - ax - cw * s2[0] * wt : 0.0;
-  if (own) W.R[pidx] = r;
+  if (own) W.R[pidx] = scaled ? r * sc : r;
   __syncthreads();
   blk_pinv(W, W.R, W.U);
   double u = own ? W.U[pidx] : 0.0;
+  if (scaled) {
+    u *= sc;
+    if (own) W.U[pidx] = u;
+    __syncthreads();
+  }
   double q = apply(W.U);
   double s4[4] = {r * u, q * u, wt * u, r * r};
   block_sum<4>(s4, red, nn);
@@ -1213,10 +1230,15 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
   for (int it = 1; it <= maxit; ++it) {
     x += alpha * pv;
     r -= alpha * sv;
-    if (own) W.R[pidx] = r;
+    if (own) W.R[pidx] = scaled ? r * sc : r;
     __syncthreads();
     blk_pinv(W, W.R, W.U);
     u = own ? W.U[pidx] : 0.0;
+    if (scaled) {
+      u *= sc;
+      if (own) W.U[pidx] = u;
+      __syncthreads();
+    }
     q = apply(W.U);
     double sr[4] = {r * u, q * u, wt * u, r * r};
     block_sum<4>(sr, red, nn);
@@ -1235,9 +1257,10 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
 template <int N1C, typename TA, int MT>
 __device__ __forceinline__ int blk_solve(const BlockSolve<N1C, TA, MT>& W, double* red, double& x,
                                          double bval, double cw, double wt, double rtol, int maxit,
-                                         bool zero_start = false) {
+                                         bool zero_start = false, bool scaled = false,
+                                         double sc = 1.0) {
   return blk_solve_g(W, [&W](const double* v) { return blk_apply(W, v); }, red, x, bval, cw, wt,
-                     rtol, maxit, zero_start);
+                     rtol, maxit, zero_start, scaled, sc);
 }
 
 // Copy one element operator from its HBM upper half into the block layout.
@@ -1331,7 +1354,8 @@ template <int N1C>
 __device__ __forceinline__ int blk_solve_mixed(const BlockSolve<N1C, float>& W,
                                                const float* __restrict__ lo, double* red,
                                                double& x, double bval, double cw, double wt,
-                                               double rtol, int maxit, int* sweeps) {
+                                               double rtol, int maxit, int* sweeps,
+                                               bool scaled = false, double msc = 1.0) {
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
   const int t = threadIdx.x;
   const bool own = t < nn;
@@ -1363,7 +1387,8 @@ __device__ __forceinline__ int blk_solve_mixed(const BlockSolve<N1C, float>& W,
     // inner tolerance: what is left to reach rtol, but not below the FP32 operator's floor
     const double tin = fmax(kInnerTol, 0.5 * sqrt(tol2 / s2[0]));
     double c = 0.0;
-    const int its = blk_solve<N1C, float>(W, red, c, r * sc, cw, wt, tin, maxit, true);
+    const int its = blk_solve<N1C, float>(W, red, c, r * sc, cw, wt, tin, maxit, true, scaled,
+                                           msc);
     total += its > maxit ? maxit : its;
     if (its > maxit || total > maxit) break;
     x += c / sc;
@@ -1371,7 +1396,7 @@ __device__ __forceinline__ int blk_solve_mixed(const BlockSolve<N1C, float>& W,
   *sweeps = sw + 1;
   // fallback: PCG with the accurate product from the current iterate
   const int its = blk_solve_g(W, [&W, lo](const double* v) { return blk_apply64(W, lo, v); }, red,
-                              x, bval, cw, wt, rtol, maxit, false);
+                              x, bval, cw, wt, rtol, maxit, false, scaled, msc);
   return its > maxit ? maxit + 1 : total + its;
 }
 
@@ -1447,7 +1472,8 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
   if (a.mapped) {
     blk_load(g.nst, W.A, a.el.M + e * g.nst, a.blk_dst);
     z = C.xm0;
-    itM = blk_solve(W, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit);
+    itM = blk_solve(W, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false,
+                    a.el.msc != nullptr, C.ms);
   } else {
     // Cartesian: the preconditioner is the exact inverse of M_J
     double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
@@ -1642,7 +1668,8 @@ __device__ __forceinline__ void pcg2r_stage_elem(const PcgStageArgs& a, const lo
   if (a.mapped) {
     reg_gather(a, W, R, a.el.Mreg + e * per);
     z = C.xm0;
-    itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false);
+    itM = blk_solve_g(W, applyS, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol, a.maxit, false,
+                      a.el.msc != nullptr, C.ms);
   } else {
     // Cartesian: the preconditioner is the exact inverse of M_J
     double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
@@ -1764,7 +1791,7 @@ __device__ __forceinline__ void pcg2m_stage_elem(const PcgStageArgs& a, const lo
     blk_load32(nnz, W.A, a.el.Mhi + e * nnz);
     z = C.xm0;
     itM = blk_solve_mixed(W, a.el.Mlo + e * nnz, C.red, z, own ? C.rv[t] : 0.0, 0.0, 0.0, a.rtol,
-                          a.maxit, &swM);
+                          a.maxit, &swM, a.el.msc != nullptr, C.ms);
   } else {
     // Cartesian: the preconditioner is the exact inverse of M_J (FP64 transforms)
     double bb1[1] = {own ? C.rv[t] * C.rv[t] : 0.0};
@@ -1918,6 +1945,26 @@ hipError_t launch_face_geom(const PcgGeom& g, const double* X, const double* Y, 
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_face_geom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, X, Y, C2,
                      el, nel);
+  return hipGetLastError();
+}
+
+// Nodal scale of the M_J preconditioner: s_i = sqrt(diag(P_M)_i / (M_J)_ii) with
+// diag(P_M)_(iy,ix) = |Omega_k| Mref_(iy,iy) Mref_(ix,ix), so that s P_M^-1 s has the
+// inverse diagonal scaling of M_J itself.
+__global__ void k_mscale(PcgGeom g, PcgElem el, long nel) {
+  const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (id >= nel * g.nn) return;
+  const long e = id / g.nn;
+  const int i = (int)(id - e * g.nn), ix = i % g.n1, iy = i / g.n1;
+  const double d = el.M[e * g.nst + g.rowoff[i] + st_pos(ix, iy, ix, iy, g.p, g.N)];
+  const double pm = el.sc[e * 8 + 4] * g.Mref[iy * g.n1 + iy] * g.Mref[ix * g.n1 + ix];
+  el.msc[id] = sqrt(pm / d);
+}
+
+hipError_t launch_mscale(const PcgGeom& g, const PcgElem& el, long nel, hipStream_t st) {
+  const long n = nel * g.nn;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mscale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, el, nel);
   return hipGetLastError();
 }
 
