@@ -152,3 +152,34 @@ def test_fp32_mode_within_1e6(flux):
     Ug, Vg, _, _ = _gpu(prob, U0, V0, dt, steps, precision="fp32")
     Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, steps)
     assert _rel(Ug, Uo) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_nonfinite_state_reported(precision):
+    """A NaN in the initial data propagates through the arithmetic (every kernel still runs
+    to completion) and the end-of-run check reports it: gdw_get_stats and gdw_energy return
+    ENONFINITE, and the context stays usable (a finite state set afterwards runs clean)."""
+    _say("case: nonfinite state", precision)
+    from paper_2105_01722_amd import gdw
+    prob = dg2d.CartProblem(nx=3, ny=2, N=8, p=3, flux="upwind")
+    rng = np.random.default_rng(5)
+    U0 = rng.standard_normal((2, 3, 9, 9))
+    V0 = rng.standard_normal((2, 3, 9, 9))
+    bad = U0.copy()
+    bad[1, 2, 4, 4] = np.nan
+    s = gdw.Solver(prob.nx, prob.ny, prob.N, prob.p, c2=prob.c2, flux=prob.flux, xi=prob.xi,
+                   precision=precision, Lx=prob.Lx, Ly=prob.Ly, x0=prob.x0, y0=prob.y0)
+    try:
+        s.set_state(bad, V0)
+        s.run(0.1 * prob.hx, 2)
+        st = s.stats(check=False)
+        assert st["status"] == gdw.GDW_ENONFINITE
+        with pytest.raises(gdw.GdwError) as ei:
+            s.energy()
+        assert ei.value.status == gdw.GDW_ENONFINITE
+        s.set_state(U0, V0)
+        s.run(0.1 * prob.hx, 2)
+        assert s.stats(check=False)["status"] == gdw.GDW_OK
+        assert np.isfinite(s.energy())
+    finally:
+        s.close()

@@ -53,6 +53,33 @@ def test_preconditioner_exact_on_cartesian_constant():
         np.testing.assert_allclose(_pmat(P, e, "M", n1), ops.M[e], atol=1e-12 * np.abs(ops.M[e]).max())
 
 
+def test_mass_preconditioner_carries_the_mass_diagonal():
+    """On mapped elements with a varying Jacobian the scaled mass preconditioner
+    P_M = S^-1 Psi_2^-T diag(|Omega_k|) Psi_2^-1 S^-1 has exactly the diagonal of M_J (the
+    property that defines the nodal scale s), stays symmetric positive definite, and is
+    closer to M_J than the unscaled form (smaller spread of the eigenvalues of P_M^-1 M_J).
+    A wrong index in s (ix and iy swapped, or the element's own area left out) breaks the
+    diagonal identity on these elements, whose mapping is not symmetric in x and y."""
+    X, Y = inputs.node_coords(2, 2, 8)
+    Xm = X + 0.06 * np.sin(2 * np.pi * X) * np.cos(np.pi * Y)   # not symmetric in x and y
+    Ym = Y + 0.02 * np.sin(2 * np.pi * Y)
+    ops = general.GenOps(general.GenProblem(nx=2, ny=2, N=8, p=3, flux="upwind"), Xm, Ym,
+                         inputs.c2_field(3, X, Y))
+    P = pcg.TensorPreconditioner(ops)
+    n1 = ops.n1
+    s_saved = P.sM.copy()
+    for e in range(4):
+        PM = _pmat(P, e, "M", n1)
+        np.testing.assert_allclose(np.diag(PM), np.diag(ops.M[e]), rtol=1e-12)
+        np.testing.assert_allclose(PM, PM.T, atol=1e-13 * np.abs(PM).max())
+        ev = np.linalg.eigvals(np.linalg.solve(PM, ops.M[e])).real
+        P.sM[e] = 1.0
+        ev0 = np.linalg.eigvals(np.linalg.solve(_pmat(P, e, "M", n1), ops.M[e])).real
+        P.sM[e] = s_saved[e]
+        assert ev.min() > 0 and ev.max() / ev.min() < ev0.max() / ev0.min()
+    assert np.abs(s_saved - 1.0).max() > 1e-3     # the scale is not trivially one here
+
+
 def test_one_iteration_when_exact():
     ops = _ops(n=2, N=6, p=3, mapped=False, variable=False)
     f = pcg.PcgRhs(ops, rtol=1e-13)
