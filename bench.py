@@ -12,7 +12,8 @@ Printed: ONE JSON line.  `value` = DOF-updates/s in FP64 (nx*ny*(N+1)^2 * steps 
 time; inputs resident in HBM).  Also reported: the FP32-storage mode, the error of
 both against the exact solution, the roofline of the stage kernel (algorithmic HBM
 bytes per launch / measured average launch time), the variable-coefficient mapped PCG
-workload in FP64 and in mixed precision (`pcg`), the learned preconditioner (`learned`),
+workload in FP64 and in mixed precision (`pcg`), the same grid as the headline with
+Dirichlet walls (`walls`), the learned preconditioner (`learned`),
 the 64-problem batch (`batch`) and the FP64 CPU oracle timed on a bounded sample on the
 host (`cpu_baseline`).
 """
@@ -33,7 +34,7 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
 # by a plain device copy's reading of the same counters (x2.0 read, x1.0 write); the
 # summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.  Set to None
 # whenever that kernel changes until the counters are taken again.
-FDM_STAGE_TRAFFIC = (319437.89 * 2.0 + 468754.90) * 1024.0
+FDM_STAGE_TRAFFIC = (319255.72 * 2.0 + 468908.02) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -71,6 +72,41 @@ def _time_gpu(w, precision, steps, warmup):
     Uh = U.cpu().numpy()
     err = float(np.linalg.norm(Uh - exact) / np.linalg.norm(exact))
     return ms, err, st
+
+
+def _time_walls(steps, warmup, n=256, N=16, p=5, cfl=0.15, k=4, l=3):
+    """The headline grid with Dirichlet walls on all four sides: u0 = sin(k pi x)
+    sin(l pi y), v0 = 0, whose exact solution is cos(pi sqrt(k^2 + l^2) t) u0."""
+    import torch
+    from paper_2105_01722_amd import gdw, inputs
+    X, Y = inputs.node_coords(n, n, N)
+    U0n = np.sin(k * np.pi * X) * np.sin(l * np.pi * Y)
+    dt = cfl / (n * N)
+    s = gdw.Solver(n, n, N, p, c2=1.0, flux="upwind", xi=1.0, bc=("dirichlet",) * 4)
+    U0 = torch.from_numpy(U0n).cuda()
+    s.set_state(U0, torch.zeros_like(U0))
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.run(dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    U, _ = s.get_state()
+    s.stats()
+    s.close()
+    T = dt * (steps + warmup)
+    exact = np.cos(np.pi * np.hypot(k, l) * T) * U0n
+    err = float(np.linalg.norm(U.cpu().numpy() - exact) / np.linalg.norm(exact))
+    ndof = n * n * (N + 1) ** 2
+    return {"workload": "256x256 elements, N=16, p=5, upwind, Dirichlet walls on all sides, "
+                        "u0 = sin(%d pi x) sin(%d pi y), v0 = 0, RK4 dt = 0.15 h" % (k, l),
+            "ms_per_step": ms / steps, "value": ndof * steps / (ms * 1e-3),
+            "unit": "DOF-updates/s", "dtype": "f64", "rel_err_vs_exact": err}
 
 
 def _pcg_workload(n=128, N=12, p=5, grf_seed=3, mode_seed=2):
@@ -320,6 +356,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
+    ap.add_argument("--no-walls", action="store_true", help="skip the Dirichlet-wall run")
     ap.add_argument("--no-pcg", action="store_true", help="skip the variable-coefficient PCG workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems section")
@@ -398,6 +435,11 @@ def main():
         out["fp32"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                        "rel_err_vs_exact": err32,
                        "roofline_frac": 24 * 4 * ndof * args.steps / (ms32 * 1e-3) / HBM_PEAK}
+    if not args.no_walls:
+        out["walls"] = _time_walls(args.steps, args.warmup)
+        out["walls"]["ms_vs_periodic"] = out["walls"]["ms_per_step"] / (ms64 / args.steps)
+        print("bench: walls %.3f ms/step" % out["walls"]["ms_per_step"], file=sys.stderr,
+              flush=True)
     if not args.no_pcg:
         pw = _pcg_workload()
         pn, pN = pw["n"], pw["N"]

@@ -64,11 +64,20 @@ typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1 } gdw_precision;
  * required for variable c^2 or mapped elements.  AUTO picks FDM when it applies. */
 typedef enum { GDW_SOLVE_AUTO = 0, GDW_SOLVE_FDM = 1, GDW_SOLVE_PCG = 2 } gdw_solver;
 
+/* Kind of one side of the rectangle.  The paper states no boundary flux (its 2D
+ * Dirichlet experiment, Sec. 6, has homogeneous data), so a wall face uses the interior
+ * flux of Sec. 2.2.1 with a mirror exterior state built from the element's own traces:
+ * DIRICHLET (u = 0): v_ext = -v, a_ext = -a (a = outward normal derivative);
+ * NEUMANN (du/dn = 0): v_ext = v, a_ext = a.  On the GD grid this equals the periodic
+ * scheme on the rectangle mirrored across the wall with odd (even) data.  A direction
+ * is periodic on both of its sides or on neither.  Walls are offered on the FDM path. */
+typedef enum { GDW_BC_PERIODIC = 0, GDW_BC_DIRICHLET = 1, GDW_BC_NEUMANN = 2 } gdw_bc;
+
 typedef struct {
   int nx, ny;          /* elements per direction (the paper's n)                     Sec. 2   */
   int N;               /* cells per element per direction, N >= p                    Sec. 2   */
   int p;               /* odd GD degree                                              Sec. 2   */
-  double x0, y0;       /* lower-left corner of the periodic rectangle                          */
+  double x0, y0;       /* lower-left corner of the rectangle                                   */
   double Lx, Ly;       /* its side lengths (> 0)                                               */
   double c2;           /* constant c^2 > 0 (used when coeff_variable = 0)                      */
   int flux;            /* gdw_flux                                                   Sec. 2.2.1 */
@@ -79,6 +88,8 @@ typedef struct {
   int mapped;          /* 1: element node coordinates given by gdw_set_coeff (PCG path)        */
   double pcg_rtol;     /* PCG stop: ||b - A x||_2 <= pcg_rtol ||b||_2 (<= 0: 1e-12)   Sec. 7.1 */
   int pcg_maxit;       /* PCG iteration limit per element solve (<= 0: 200)                   */
+  int bc[4];           /* gdw_bc of the sides x = x0 + Lx (E), x = x0 (W), y = y0 + Ly (N),
+                          y = y0 (S); all zero: periodic in x and y                            */
 } gdw_desc;
 
 typedef struct gdw_ctx gdw_ctx;   /* opaque; owns every device workspace */
@@ -94,7 +105,8 @@ const char* gdw_last_error(void);
  * S_j psi = lambda M_j psi with psi^T M_j psi = 1 (Sec. 3.2) in FP64 on the device.
  * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
  * non-positive length, c2 or xi, an unknown enum, solver FDM with a variable
- * coefficient or a mapped mesh; EUNSUPPORTED for the PCG path with p > 7 or an element
+ * coefficient or a mapped mesh, a direction periodic on one side only; EUNSUPPORTED
+ * for walls on the PCG path, for the PCG path with p > 7 or an element
  * operator that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path
  * in GDW_MIXED_FP32; ENOMEM / EHIP from the device.  Uses the current HIP device;
  * synchronous. */

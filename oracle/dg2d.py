@@ -22,6 +22,13 @@ Readings (where the paper is silent, garbled or inconsistent):
     w_i = int phi_i and kappa = c^2; the solution y of S_hat y = F_u does not depend on
     kappa because 1^T F_u = 0.
   * Initial data is nodal interpolation (the paper's nodal formulation).
+  * Physical boundaries (the paper states no boundary flux; its 2D Dirichlet experiment
+    of Sec. 6 has homogeneous data): a wall face takes the interior flux formula with
+    a mirror exterior state.  Dirichlet u = 0: the odd mirror, v_ext = -v and
+    a_ext = -a (a = outward normal derivative); Neumann du/dn = 0: the even mirror,
+    v_ext = v, a_ext = a.  With a GD basis that is symmetric under reflection this is
+    exactly the periodic scheme on the domain doubled across the wall with odd (even)
+    data, which is how it is pinned.
 
 Array layout: a field on the element grid is [ny, nx, N+1 (iy), N+1 (ix)];
 element (ex, ey) covers [x0 + ex Hx, x0 + (ex+1) Hx] x [y0 + ey Hy, ...];
@@ -58,6 +65,19 @@ class CartProblem:
     c2: float = 1.0
     flux: str = "central"
     xi: float = 1.0
+    # boundary kind of the E, W, N, S sides: "periodic", "dirichlet" or "neumann"
+    # (a direction is periodic on both of its sides or on neither)
+    bc: tuple = ("periodic", "periodic", "periodic", "periodic")
+
+    def __post_init__(self):
+        kinds = ("periodic", "dirichlet", "neumann")
+        bc = tuple(self.bc)
+        if len(bc) != 4 or any(k not in kinds for k in bc):
+            raise ValueError("bc: four of %s (E, W, N, S)" % (kinds,))
+        for a, b in ((0, 1), (2, 3)):
+            if (bc[a] == "periodic") != (bc[b] == "periodic"):
+                raise ValueError("a direction is periodic on both sides or on neither")
+        self.bc = bc
 
     @property
     def Hx(self):
@@ -126,14 +146,29 @@ def traces(U, V, ops):
     }
 
 
-def neighbour_traces(tr):
-    """Traces of the periodic neighbour across each face, on its opposite face."""
-    return {
+# the elements on each side of the grid ([ny, nx, ...] indexing)
+_SIDE = {"E": (slice(None), -1), "W": (slice(None), 0), "N": (-1, slice(None)),
+         "S": (0, slice(None))}
+
+
+def neighbour_traces(tr, bc=("periodic",) * 4):
+    """Traces of the neighbour across each face, on its opposite face: the periodic
+    neighbour, or on a wall face the mirror state of the element's own traces
+    (Dirichlet: a_ext = -a, v_ext = -v; Neumann: a_ext = a, v_ext = v)."""
+    nb = {
         "E": tuple(np.roll(t, -1, axis=1) for t in tr["W"]),
         "W": tuple(np.roll(t, +1, axis=1) for t in tr["E"]),
         "N": tuple(np.roll(t, -1, axis=0) for t in tr["S"]),
         "S": tuple(np.roll(t, +1, axis=0) for t in tr["N"]),
     }
+    for f, kind in zip("EWNS", bc):
+        if kind == "periodic":
+            continue
+        sgn = -1.0 if kind == "dirichlet" else 1.0
+        side = _SIDE[f]
+        for k in (0, 1):
+            nb[f][k][side] = sgn * tr[f][k][side]
+    return nb
 
 
 def face_sigmas(a, v, a_nb, v_nb, alpha, beta, tau):
@@ -160,7 +195,7 @@ def lifts(U, V, ops):
     alpha, beta, tau = flux_params(prob.flux, prob.xi)
     c2 = prob.c2
     tr = traces(U, V, ops)
-    nb = neighbour_traces(tr)
+    nb = neighbour_traces(tr, prob.bc)
     sig = {f: face_sigmas(tr[f][0], tr[f][1], nb[f][0], nb[f][1], alpha, beta, tau)
            for f in "EWNS"}
     Fu = np.zeros_like(U)

@@ -75,7 +75,17 @@ static gdw_status validate(const gdw_desc* d) {
   if (d->solver == GDW_SOLVE_FDM && general) {
     set_error("the FDM solve needs a constant c^2 on Cartesian elements"); return GDW_EINVAL;
   }
+  for (int k = 0; k < 4; ++k)
+    if (d->bc[k] != GDW_BC_PERIODIC && d->bc[k] != GDW_BC_DIRICHLET && d->bc[k] != GDW_BC_NEUMANN) {
+      set_error("unknown boundary kind"); return GDW_EINVAL;
+    }
+  if ((d->bc[0] == GDW_BC_PERIODIC) != (d->bc[1] == GDW_BC_PERIODIC) ||
+      (d->bc[2] == GDW_BC_PERIODIC) != (d->bc[3] == GDW_BC_PERIODIC)) {
+    set_error("a direction is periodic on both of its sides or on neither"); return GDW_EINVAL;
+  }
+  const bool walls = d->bc[0] || d->bc[1] || d->bc[2] || d->bc[3];
   const bool pcg = d->solver == GDW_SOLVE_PCG || general;
+  if (pcg && walls) { set_error("walls are offered on the FDM path only"); return GDW_EUNSUPPORTED; }
   if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
   if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
@@ -546,6 +556,8 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.invL = (const T*)c->invL;
   a.lam = (const T*)c->lam;
   a.gh = (const T*)c->gh;
+  a.bcbits = 0;
+  for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
   stage_roles(c, stage, a);
   return a;
 }

@@ -23,6 +23,7 @@ struct StageArgs {
   const T* gh;         // [8][n1]: gE hE gW hW gN hN gS hS
   long nel;
   int nx, ny, n1;
+  int bcbits;          // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
   T dt, c2, alpha, beta, tau;
 };
 

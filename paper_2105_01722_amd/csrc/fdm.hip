@@ -423,15 +423,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     const int f = r / n1, j = r - f * n1;
     const long e = e0 + el;
     const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
+    // Neighbour across face f (periodic wrap).  On a wall face (its side is not periodic
+    // and the element touches it) the exterior state is the mirror of the element's own
+    // traces: read its own face with the sign -1 (Dirichlet) or +1 (Neumann).
+    const int kf = (a.bcbits >> (2 * f)) & 3;
     long enb;
     int fnb;
-    if (f == 0) { enb = (long)ey * a.nx + (ex + 1 == a.nx ? 0 : ex + 1); fnb = 1; }
-    else if (f == 1) { enb = (long)ey * a.nx + (ex == 0 ? a.nx - 1 : ex - 1); fnb = 0; }
-    else if (f == 2) { enb = (long)(ey + 1 == a.ny ? 0 : ey + 1) * a.nx + ex; fnb = 3; }
-    else { enb = (long)(ey == 0 ? a.ny - 1 : ey - 1) * a.nx + ex; fnb = 2; }
+    bool wall;
+    if (f == 0) { wall = ex + 1 == a.nx; enb = (long)ey * a.nx + (wall ? 0 : ex + 1); fnb = 1; }
+    else if (f == 1) { wall = ex == 0; enb = (long)ey * a.nx + (wall ? a.nx - 1 : ex - 1); fnb = 0; }
+    else if (f == 2) { wall = ey + 1 == a.ny; enb = (long)(wall ? 0 : ey + 1) * a.nx + ex; fnb = 3; }
+    else { wall = ey == 0; enb = (long)(wall ? a.ny - 1 : ey - 1) * a.nx + ex; fnb = 2; }
+    wall = wall && kf != 0;
     const T* ts = a.tr_in + e * 8 * n1 + 2 * f * n1;
-    const T* tn = a.tr_in + enb * 8 * n1 + 2 * fnb * n1;
-    const T as = ts[j], vs = ts[n1 + j], an = tn[j], vn = tn[n1 + j];
+    const T* tn = wall ? ts : a.tr_in + enb * 8 * n1 + 2 * fnb * n1;
+    const T as = ts[j], vs = ts[n1 + j];
+    T an = tn[j], vn = tn[n1 + j];
+    if (wall && kf == 1) {
+      an = -an;
+      vn = -vn;
+    }
     const T jv = vn - vs;
     sig[(el * 8 + 2 * f) * n1 + j] = (T(1) - alpha) * jv - beta * (as + an);
     sig[(el * 8 + 2 * f + 1) * n1 + j] = (T(1) - alpha) * as - alpha * an + tau * jv;

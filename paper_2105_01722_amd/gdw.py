@@ -16,6 +16,8 @@ GDW_OK, GDW_EINVAL, GDW_ENOMEM, GDW_EHIP, GDW_ENOCONV, GDW_ENONFINITE, GDW_EUNSU
 GDW_FLUX_CENTRAL, GDW_FLUX_UPWIND = 0, 1
 GDW_FP64, GDW_MIXED_FP32 = 0, 1
 GDW_SOLVE_AUTO, GDW_SOLVE_FDM, GDW_SOLVE_PCG = 0, 1, 2
+GDW_BC_PERIODIC, GDW_BC_DIRICHLET, GDW_BC_NEUMANN = 0, 1, 2
+_BC = {"periodic": GDW_BC_PERIODIC, "dirichlet": GDW_BC_DIRICHLET, "neumann": GDW_BC_NEUMANN}
 
 _STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV",
                  -5: "ENONFINITE", -6: "EUNSUPPORTED"}
@@ -27,7 +29,8 @@ class gdw_desc(ctypes.Structure):
                 ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("c2", ctypes.c_double),
                 ("flux", ctypes.c_int), ("xi", ctypes.c_double), ("precision", ctypes.c_int),
                 ("solver", ctypes.c_int), ("coeff_variable", ctypes.c_int), ("mapped", ctypes.c_int),
-                ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int)]
+                ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int),
+                ("bc", ctypes.c_int * 4)]
 
 
 class gdw_stats(ctypes.Structure):
@@ -167,8 +170,9 @@ def gdw_destroy(ctx):
 # --- convenience wrapper -----------------------------------------------------------------
 def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", solver="auto",
               Lx=1.0, Ly=1.0, x0=0.0, y0=0.0, coeff_variable=False, mapped=False,
-              pcg_rtol=1e-12, pcg_maxit=200):
-    """A gdw_desc from keyword arguments (names as in include/gdw.h)."""
+              pcg_rtol=1e-12, pcg_maxit=200, bc=("periodic",) * 4):
+    """A gdw_desc from keyword arguments (names as in include/gdw.h); bc: the kinds of
+    the E, W, N, S sides ("periodic", "dirichlet", "neumann" or the gdw_bc values)."""
     d = gdw_desc()
     d.nx, d.ny, d.N, d.p = nx, ny, N, p
     d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
@@ -181,11 +185,16 @@ def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", so
     d.mapped = int(bool(mapped))
     d.pcg_rtol = pcg_rtol
     d.pcg_maxit = pcg_maxit
+    if len(bc) != 4:
+        raise ValueError("bc: four side kinds (E, W, N, S)")
+    for k, b in enumerate(bc):
+        d.bc[k] = _BC[b] if isinstance(b, str) else int(b)
     return d
 
 
 class Solver:
-    """One problem: nx x ny periodic elements, N cells, odd degree p (see include/gdw.h)."""
+    """One problem: nx x ny elements (periodic unless walls are given), N cells, odd degree
+    p (see include/gdw.h)."""
 
     def __init__(self, nx, ny, N, p, **kw):
         self._attach(make_desc(nx, ny, N, p, **kw), None)

@@ -40,7 +40,11 @@ def _desc(**kw):
     d.precision = gdw.GDW_FP64
     d.solver = gdw.GDW_SOLVE_AUTO
     for k, v in kw.items():
-        setattr(d, k, v)
+        if k == "bc":
+            for i, b in enumerate(v):
+                d.bc[i] = b
+        else:
+            setattr(d, k, v)
     return d
 
 
@@ -60,6 +64,11 @@ def _desc(**kw):
     (dict(solver=gdw.GDW_SOLVE_FDM, mapped=1), gdw.GDW_EINVAL),
     (dict(coeff_variable=1, N=12, p=9), gdw.GDW_EUNSUPPORTED),
     (dict(mapped=1, pcg_rtol=float("nan")), gdw.GDW_EINVAL),
+    (dict(bc=(7, 7, 0, 0)), gdw.GDW_EINVAL),
+    (dict(bc=(gdw.GDW_BC_DIRICHLET, gdw.GDW_BC_PERIODIC, 0, 0)), gdw.GDW_EINVAL),
+    (dict(bc=(0, 0, gdw.GDW_BC_PERIODIC, gdw.GDW_BC_NEUMANN)), gdw.GDW_EINVAL),
+    (dict(bc=(gdw.GDW_BC_DIRICHLET,) * 4, coeff_variable=1), gdw.GDW_EUNSUPPORTED),
+    (dict(bc=(gdw.GDW_BC_NEUMANN,) * 4, solver=gdw.GDW_SOLVE_PCG), gdw.GDW_EUNSUPPORTED),
 ])
 def test_invalid_descriptors_rejected_on_host(kw, status):
     """Validation happens before any device call, so it runs without a GPU."""
