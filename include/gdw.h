@@ -70,7 +70,8 @@ typedef enum { GDW_SOLVE_AUTO = 0, GDW_SOLVE_FDM = 1, GDW_SOLVE_PCG = 2 } gdw_so
  * DIRICHLET (u = 0): v_ext = -v, a_ext = -a (a = outward normal derivative);
  * NEUMANN (du/dn = 0): v_ext = v, a_ext = a.  On the GD grid this equals the periodic
  * scheme on the rectangle mirrored across the wall with odd (even) data.  A direction
- * is periodic on both of its sides or on neither.  Walls are offered on the FDM path. */
+ * is periodic on both of its sides or on neither.  On the PCG path (mapped elements) the
+ * mirror is taken at the face quadrature points of the wall face. */
 typedef enum { GDW_BC_PERIODIC = 0, GDW_BC_DIRICHLET = 1, GDW_BC_NEUMANN = 2 } gdw_bc;
 
 typedef struct {
@@ -106,7 +107,7 @@ const char* gdw_last_error(void);
  * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
  * non-positive length, c2 or xi, an unknown enum, solver FDM with a variable
  * coefficient or a mapped mesh, a direction periodic on one side only; EUNSUPPORTED
- * for walls on the PCG path, for the PCG path with p > 7 or an element
+ * for the PCG path with p > 7 or an element
  * operator that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path
  * in GDW_MIXED_FP32; ENOMEM / EHIP from the device.  Uses the current HIP device;
  * synchronous. */

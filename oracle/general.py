@@ -48,6 +48,20 @@ class GenProblem:
     p: int
     flux: str = "upwind"
     xi: float = 1.0
+    # boundary kind of the E, W, N, S sides of the element grid (as in dg2d.CartProblem):
+    # a wall face takes the mirror exterior state of the element's own traces at its face
+    # points (Dirichlet: a_ext = -a, v_ext = -v; Neumann: a_ext = a, v_ext = v)
+    bc: tuple = ("periodic", "periodic", "periodic", "periodic")
+
+    def __post_init__(self):
+        kinds = ("periodic", "dirichlet", "neumann")
+        bc = tuple(self.bc)
+        if len(bc) != 4 or any(k not in kinds for k in bc):
+            raise ValueError("bc: four of %s (E, W, N, S)" % (kinds,))
+        for a, b in ((0, 1), (2, 3)):
+            if (bc[a] == "periodic") != (bc[b] == "periodic"):
+                raise ValueError("a direction is periodic on both sides or on neither")
+        self.bc = bc
 
 
 FACES = ("E", "W", "N", "S")
@@ -237,6 +251,25 @@ def _neighbour(arr, f, prob):
 OPP = {"E": "W", "W": "E", "N": "S", "S": "N"}
 
 
+def _exterior(tr, f, prob):
+    """Exterior state (a_nb, v_nb) at the points of face f of every element: the periodic
+    neighbour's traces on its opposite face, or on a wall face the mirror of the element's
+    own traces."""
+    an = _neighbour(tr[OPP[f]][0], f, prob)
+    vn = _neighbour(tr[OPP[f]][1], f, prob)
+    kind = prob.bc["EWNS".index(f)]
+    if kind != "periodic":
+        sgn = -1.0 if kind == "dirichlet" else 1.0
+        side = {"E": (slice(None), -1), "W": (slice(None), 0), "N": (-1, slice(None)),
+                "S": (0, slice(None))}[f]
+        wall = np.zeros((prob.ny, prob.nx), dtype=bool)
+        wall[side] = True
+        wall = wall.ravel()
+        an[wall] = sgn * tr[f][0][wall]
+        vn[wall] = sgn * tr[f][1][wall]
+    return an, vn
+
+
 def lifts(U, V, ops):
     """F_u,i = int c^2 (n . grad phi_i)(v* - v) dS and F_v,i = int c^2 phi_i n.(grad u)* dS."""
     prob = ops.prob
@@ -248,8 +281,7 @@ def lifts(U, V, ops):
     for f in FACES:
         fd = ops.faces[f]
         a, v = tr[f]
-        an = _neighbour(tr[OPP[f]][0], f, prob)
-        vn = _neighbour(tr[OPP[f]][1], f, prob)
+        an, vn = _exterior(tr, f, prob)
         su, sv = face_sigmas(a, v, an, vn, alpha, beta, tau)
         wsu = fd["wq"][None, :] * su
         wsv = fd["wq"][None, :] * sv * fd["c2sJ"]
@@ -303,16 +335,18 @@ def energy_rate(U, V, ops):
 
 
 def face_dissipation(U, V, ops):
-    """-sum over faces of int c^2 (beta (a + a_nb)^2 + tau (v_nb - v)^2) dS (each face once)."""
+    """-sum over faces of int c^2 (beta (a + a_nb)^2 + tau (v_nb - v)^2) dS: every face of
+    every element with weight 1/2, so an interior face (seen from both sides) counts once
+    and a wall face (seen from its element only, against the mirror state) counts half --
+    the share of the doubled domain that the wall's half owns."""
     prob = ops.prob
     _, beta, tau = flux_params(prob.flux, prob.xi)
     tr = face_traces(U, V, ops)
     tot = 0.0
-    for f in ("E", "N"):
+    for f in FACES:
         fd = ops.faces[f]
         a, v = tr[f]
-        an = _neighbour(tr[OPP[f]][0], f, prob)
-        vn = _neighbour(tr[OPP[f]][1], f, prob)
+        an, vn = _exterior(tr, f, prob)
         integrand = fd["c2sJ"] * (beta * (a + an) ** 2 + tau * (vn - v) ** 2)
-        tot -= float(np.sum(fd["wq"][None, :] * integrand))
+        tot -= 0.5 * float(np.sum(fd["wq"][None, :] * integrand))
     return tot

@@ -83,9 +83,7 @@ static gdw_status validate(const gdw_desc* d) {
       (d->bc[2] == GDW_BC_PERIODIC) != (d->bc[3] == GDW_BC_PERIODIC)) {
     set_error("a direction is periodic on both of its sides or on neither"); return GDW_EINVAL;
   }
-  const bool walls = d->bc[0] || d->bc[1] || d->bc[2] || d->bc[3];
   const bool pcg = d->solver == GDW_SOLVE_PCG || general;
-  if (pcg && walls) { set_error("walls are offered on the FDM path only"); return GDW_EUNSUPPORTED; }
   if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
   if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
@@ -576,6 +574,8 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.nel = c->nel;
   a.nx = c->d.nx;
   a.ny = c->d.ny;
+  a.bcbits = 0;
+  for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
   a.mapped = c->d.mapped;
   a.dt = dt;
   a.alpha = c->alpha;

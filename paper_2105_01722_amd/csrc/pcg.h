@@ -65,6 +65,7 @@ struct PcgStageArgs {
   int* fail;            // smallest element id that hit maxit (0x7f7f7f7f if none)
   long nel;
   int nx, ny;
+  int bcbits;           // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
   int mapped;
   double dt, alpha, beta, tau, rtol, rtol_inner;
   int maxit;

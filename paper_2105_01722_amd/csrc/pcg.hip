@@ -750,15 +750,26 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   // ---- face fluxes sigma_u, sigma_v at the face points (Sec. 2.2.1) ----------------
   for (int id = t; id < 4 * nq; id += blockDim.x) {
     const int f = id / nq, q = id - (id / nq) * nq;
+    // neighbour across face f (periodic wrap); a wall face (its side is not periodic and
+    // the element touches it) reads its own trace instead, negated for Dirichlet: the
+    // mirror exterior state
     int nbx = ex, nby = ey, fnb;
-    if (f == 0) { nbx = ex + 1 == a.nx ? 0 : ex + 1; fnb = 1; }
-    else if (f == 1) { nbx = ex == 0 ? a.nx - 1 : ex - 1; fnb = 0; }
-    else if (f == 2) { nby = ey + 1 == a.ny ? 0 : ey + 1; fnb = 3; }
-    else { nby = ey == 0 ? a.ny - 1 : ey - 1; fnb = 2; }
+    bool wall;
+    if (f == 0) { wall = ex + 1 == a.nx; nbx = wall ? 0 : ex + 1; fnb = 1; }
+    else if (f == 1) { wall = ex == 0; nbx = wall ? a.nx - 1 : ex - 1; fnb = 0; }
+    else if (f == 2) { wall = ey + 1 == a.ny; nby = wall ? 0 : ey + 1; fnb = 3; }
+    else { wall = ey == 0; nby = wall ? a.ny - 1 : ey - 1; fnb = 2; }
+    const int kf = (a.bcbits >> (2 * f)) & 3;
+    wall = wall && kf != 0;
     const long enb = (long)nby * a.nx + nbx;
     const double* ts = a.tr_in + (e * 4 * nq + id) * 2;
-    const double* tn = a.tr_in + (enb * 4 * nq + fnb * nq + q) * 2;
-    const double as = ts[0], vs = ts[1], an = tn[0], vn = tn[1];
+    const double* tn = wall ? ts : a.tr_in + (enb * 4 * nq + fnb * nq + q) * 2;
+    const double as = ts[0], vs = ts[1];
+    double an = tn[0], vn = tn[1];
+    if (wall && kf == 1) {
+      an = -an;
+      vn = -vn;
+    }
     const double jv = vn - vs;
     sig[id * 2] = (1.0 - a.alpha) * jv - a.beta * (as + an);
     sig[id * 2 + 1] = (1.0 - a.alpha) * as - a.alpha * an + a.tau * jv;

@@ -1,5 +1,6 @@
 """GPU parity of wall boundaries (Dirichlet / Neumann mirror states) on the
-constant-coefficient path, through the C ABI, and the paper's 2D Dirichlet experiment.
+constant-coefficient path and on the PCG path (mapped elements, variable c^2), through
+the C ABI, and the paper's 2D Dirichlet experiment.
 
 Parity bar: FP64 nodal state relative l2 <= 1e-12 against the FP64 oracle (the same bar
 as the periodic tests), FP32 storage <= 1e-6.  Grids span several 4-element (FP64) and
@@ -21,7 +22,7 @@ import sys
 import numpy as np
 import pytest
 
-from oracle import dg2d, gd1d
+from oracle import dg2d, gd1d, general
 from paper_2105_01722_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -201,3 +202,63 @@ def test_paper_dirichlet_rates(table, p, flux):
     assert abs(got_en - r_en) <= 0.25
     if p in (3, 5):
         assert abs(got_l2 - r_l2) <= 0.6
+
+
+# ---- walls on the PCG path (mapped elements, variable c^2) ----------------------------
+def _pcg_gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, bc, flux="upwind", rtol=1e-13,
+             precision="fp64"):
+    from paper_2105_01722_amd import gdw
+    s = gdw.Solver(n, n, N, p, flux=flux, xi=1.0, solver="pcg", coeff_variable=True,
+                   mapped=True, pcg_rtol=rtol, precision=precision, bc=bc)
+    try:
+        s.set_coeff(c2, Xm, Ym)
+        s.set_state(U0, V0)
+        s.run(dt, steps)
+        U, V = s.get_state()
+        E = s.energy()
+        st = s.stats(check=False)
+    finally:
+        s.close()
+    return U.cpu().numpy(), V.cpu().numpy(), E, st
+
+
+@pytest.mark.parametrize("bcname", ["dirichlet", "mixed", "x_periodic"])
+@pytest.mark.parametrize("n,N,p,flux", [(3, 12, 5, "upwind"), (3, 8, 3, "central"),
+                                        (2, 16, 5, "upwind"), (3, 7, 5, "upwind")])
+def test_pcg_walls_match_dense_oracle(bcname, n, N, p, flux):
+    """Curved mesh (straight outer sides) with variable c^2: the GPU PCG path with walls
+    against the dense-direct general oracle with the same walls; register-operator
+    kernels (N + 1 = 13, 9, 17) and the row layout (N = 7)."""
+    _say("case: pcg walls", bcname, n, N, p, flux)
+    X, Y = inputs.node_coords(n, n, N)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    c2 = inputs.c2_field(3, X, Y)
+    U0 = inputs.fourier_field(inputs.fourier_modes(2, kmax=4), Xm, Ym)
+    V0 = 0.2 * inputs.fourier_field(inputs.fourier_modes(4, kmax=4), Xm, Ym)
+    dt, steps = 0.1 / (n * N), 3
+    Ug, Vg, Eg, st = _pcg_gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, BCS[bcname], flux=flux)
+    assert st["status"] == 0 and st["fail_elem"] == -1
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux=flux, bc=BCS[bcname]),
+                         Xm, Ym, c2)
+    Uo, Vo = general.run(U0, V0, ops, dt, steps)
+    assert _rel(Ug, Uo) <= 1e-12
+    assert _rel(Vg, Vo) <= 1e-12
+    Eo = general.energy(Uo, Vo, ops)
+    assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
+
+
+def test_pcg_walls_cartesian_equal_fdm_walls():
+    """Constant c^2 on a Cartesian grid: the PCG path with walls and the FDM path with
+    the same walls give the same state (two GPU solvers, one scheme)."""
+    _say("case: pcg walls vs fdm walls")
+    n, N, p = 3, 12, 5
+    prob = dg2d.CartProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=BCS["mixed"])
+    X, Y = dg2d.node_coords(prob)
+    U0 = inputs.fourier_field(inputs.fourier_modes(2, kmax=4), X, Y)
+    V0 = np.zeros_like(U0)
+    dt = 0.1 * prob.hx
+    Uf, Vf, _, _ = _gpu(prob, U0, V0, dt, 4)
+    Up, Vp, _, st = _pcg_gpu(n, N, p, X, Y, np.ones_like(X), U0, V0, dt, 4, BCS["mixed"])
+    assert st["status"] == 0
+    assert _rel(Up, Uf) <= 1e-12
+    assert _rel(Vp, Vf) <= 1e-12

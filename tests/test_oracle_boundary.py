@@ -1,4 +1,4 @@
-"""Pins of the wall boundaries of the constant-coefficient oracle.
+"""Pins of the wall boundaries of the oracle (constant-coefficient and mapped paths).
 
 The paper gives no boundary flux; its 2D Dirichlet experiment (Sec. 6, "Dirichlet
 Boundary Conditions in Two Dimensions") has homogeneous Dirichlet data on the unit
@@ -14,12 +14,16 @@ What fixes it independently of its own code:
   * energy: with the central flux the discrete energy of Sec. 2.2 is conserved with
     walls too (dE/dt = 0), with the upwind flux it does not grow;
   * a Dirichlet standing wave sin(k pi x) sin(l pi y) cos(omega t) keeps zero boundary
-    values and converges to the exact solution.
+    values and converges to the exact solution;
+  * mapped path: on an affine mesh it is the Cartesian wall scheme; on a curved mesh with
+    variable c^2 the energy identity holds with walls (wall faces dissipate against the
+    mirror state with half weight).
 """
 import numpy as np
 import pytest
 
-from oracle import dg2d
+from oracle import dg2d, general
+from paper_2105_01722_amd import inputs
 
 
 def _odd_even_extend(W, axis_x, axis_y):
@@ -134,3 +138,51 @@ def test_dirichlet_standing_wave_converges():
         assert np.abs(U - exact).max() < 1e-3
     rate = np.log2(errs[0] / errs[1])
     assert rate > 3.3, (errs, rate)
+
+
+# ---- walls on the mapped / variable-coefficient oracle -------------------------------
+
+
+@pytest.mark.parametrize("bc", [("dirichlet",) * 4, ("neumann", "neumann", "dirichlet", "dirichlet"),
+                                ("periodic", "periodic", "neumann", "neumann")])
+@pytest.mark.parametrize("flux", ["central", "upwind"])
+def test_general_walls_on_affine_mesh_equal_cartesian_walls(bc, flux):
+    """The quadrature-based general oracle on a rectangle grid with constant c^2 and walls
+    is the Cartesian wall scheme (the mirror is taken at the face points there)."""
+    n, N, p, c2 = 3, 6, 3, 1.7
+    X, Y = inputs.node_coords(n, n, N, Lx=1.3, Ly=0.7, x0=-0.2, y0=0.1)
+    g = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux=flux, xi=np.sqrt(c2),
+                                          bc=bc), X, Y, np.full_like(X, c2))
+    c = dg2d.CartOps(dg2d.CartProblem(nx=n, ny=n, N=N, p=p, flux=flux, c2=c2, xi=np.sqrt(c2),
+                                      Lx=1.3, Ly=0.7, x0=-0.2, y0=0.1, bc=bc))
+    rng = np.random.default_rng(2)
+    U, V = rng.standard_normal(X.shape), rng.standard_normal(X.shape)
+    for x, y in zip(general.rhs(U, V, g), dg2d.rhs(U, V, c)):
+        assert np.abs(x - y).max() <= 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("bc", [("dirichlet",) * 4, ("neumann",) * 4,
+                                ("dirichlet", "dirichlet", "neumann", "neumann")])
+def test_general_walls_energy_identity_curved_variable(bc):
+    """Curved mesh (the walls stay straight: the mapping's displacement vanishes on the
+    sides of the unit square) and variable c^2: central conserves the energy exactly;
+    upwind dissipates exactly the face integral, every face of every element taken with
+    weight 1/2 (interior faces once, wall faces half, against the mirror state)."""
+    n, N, p = 3, 6, 3
+    X, Y = inputs.node_coords(n, n, N)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    c2 = inputs.c2_field(3, X, Y)
+    rng = np.random.default_rng(3)
+    U, V = rng.standard_normal(X.shape), rng.standard_normal(X.shape)
+    ne = n * n
+    for flux in ("central", "upwind"):
+        g = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux=flux, bc=bc), Xm, Ym, c2)
+        dU, dV = general.rhs(U, V, g)
+        rate = (np.einsum("ei,eij,ej->", V.reshape(ne, -1), g.M, dV.reshape(ne, -1))
+                + np.einsum("ei,eij,ej->", U.reshape(ne, -1), g.S, dU.reshape(ne, -1)))
+        scale = np.abs(np.einsum("ei,eij,ej->e", V.reshape(ne, -1), g.M, dV.reshape(ne, -1))).sum()
+        if flux == "central":
+            assert abs(rate) < 1e-11 * scale
+        else:
+            d = general.face_dissipation(U, V, g)
+            assert d < 0 and abs(rate - d) < 1e-11 * abs(d)
