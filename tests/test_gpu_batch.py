@@ -42,6 +42,12 @@ PROBLEMS = [
          pcg_rtol=1e-13),
     dict(nx=2, ny=3, N=12, p=7, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
          pcg_rtol=1e-13),
+    # members with walls, grouped with periodic members of the same class
+    dict(nx=3, ny=2, N=8, p=3, flux="upwind", precision="fp64", bc=("dirichlet",) * 4),
+    dict(nx=4, ny=3, N=8, p=5, flux="upwind", precision="fp32",
+         bc=("neumann", "neumann", "dirichlet", "dirichlet")),
+    dict(nx=2, ny=3, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
+         pcg_rtol=1e-13, bc=("dirichlet", "dirichlet", "periodic", "periodic")),
 ]
 
 

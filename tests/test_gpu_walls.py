@@ -262,3 +262,23 @@ def test_pcg_walls_cartesian_equal_fdm_walls():
     assert st["status"] == 0
     assert _rel(Up, Uf) <= 1e-12
     assert _rel(Vp, Vf) <= 1e-12
+
+
+def test_pcg_walls_mixed_precision():
+    """Mixed-precision PCG (FP32 inner iterations, FP64 refinement) with walls, against
+    the dense oracle at the mixed path's bar (1e-10, as in test_gpu_pcg.py)."""
+    _say("case: pcg walls mixed")
+    n, N, p = 3, 12, 5
+    X, Y = inputs.node_coords(n, n, N)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    c2 = inputs.c2_field(3, X, Y)
+    U0 = inputs.fourier_field(inputs.fourier_modes(2, kmax=4), Xm, Ym)
+    V0 = 0.2 * inputs.fourier_field(inputs.fourier_modes(4, kmax=4), Xm, Ym)
+    dt, steps = 0.1 / (n * N), 3
+    bc = BCS["mixed"]
+    Ug, Vg, _, st = _pcg_gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, bc, precision="mixed")
+    assert st["status"] == 0 and st["mean_refine"] >= 1.0
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=bc),
+                         Xm, Ym, c2)
+    Uo, Vo = general.run(U0, V0, ops, dt, steps)
+    assert _rel(Ug, Uo) <= 1e-10 and _rel(Vg, Vo) <= 1e-10
