@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).  Plain FP64, nodal state,
 dense direct element solves.
 
 Paper passages followed:
-  * Sec. 2 eqs. eq:wave_1 / eq:wave_2: u_t = v, v_t = div(c^2 grad u) (f = 0 here).
+  * Sec. 2 eqs. eq:wave_1 / eq:wave_2: u_t = v, v_t = div(c^2 grad u) + f.
   * Sec. 2.1.2: 2D basis = tensor product of the modified 1D basis.
   * Sec. 2.2 eqs. DG1, DG2 and DG1_extra: the element-wise variational statement.
   * Sec. 2.2.1: numerical fluxes v*, (grad u)* with (alpha, beta, tau); central
@@ -29,6 +29,10 @@ Readings (where the paper is silent, garbled or inconsistent):
     v_ext = v, a_ext = a.  With a GD basis that is symmetric under reflection this is
     exactly the periodic scheme on the domain doubled across the wall with odd (even)
     data, which is how it is pinned.
+  * Source term: f(x, y, t) = sum_k sin(omega_k t + phase_k) g_k(x, y), each g_k
+    represented by its GD interpolant (like the initial data), so the load vector of DG2
+    is M g_k and the term adds sum_k sin(omega_k t + phase_k) g_k to dV/dt.  RK4 evaluates
+    it at the stage times t, t + dt/2, t + dt/2, t + dt.
 
 Array layout: a field on the element grid is [ny, nx, N+1 (iy), N+1 (ix)];
 element (ex, ey) covers [x0 + ex Hx, x0 + (ex+1) Hx] x [y0 + ey Hy, ...];
@@ -68,6 +72,8 @@ class CartProblem:
     # boundary kind of the E, W, N, S sides: "periodic", "dirichlet" or "neumann"
     # (a direction is periodic on both of its sides or on neither)
     bc: tuple = ("periodic", "periodic", "periodic", "periodic")
+    # source terms: tuple of (g_nodal [ny, nx, N+1, N+1], omega, phase)
+    forcing: tuple = ()
 
     def __post_init__(self):
         kinds = ("periodic", "dirichlet", "neumann")
@@ -222,15 +228,23 @@ def apply_S2(U, ops):
             + np.einsum("jl,ik,ablk->abji", ops.Sy, ops.Mx, U))
 
 
-def rhs(U, V, ops):
-    """Semi-discrete time derivatives (dU/dt, dV/dt) of DG1 + DG1_extra and DG2.
+def rhs(U, V, ops, t=0.0):
+    """Semi-discrete time derivatives (dU/dt, dV/dt) of DG1 + DG1_extra and DG2 at time t.
 
-    S_hat (dU/dt - V) = F_u    and    M dV/dt = -c^2 S U + F_v.
+    S_hat (dU/dt - V) = F_u    and    M dV/dt = -c^2 S U + F_v + sum_k s_k(t) M g_k.
     """
     Fu, Fv = lifts(U, V, ops)
     y = ops.solve_Shat(Fu)
     z = ops.solve_M(-ops.prob.c2 * apply_S2(U, ops) + Fv)
-    return V + y, z
+    return V + y, z + forcing_term(ops.prob, t)
+
+
+def forcing_term(prob, t):
+    """sum_k sin(omega_k t + phase_k) g_k (nodal; zero without source terms)."""
+    out = 0.0
+    for g, omega, phase in prob.forcing:
+        out = out + np.sin(omega * t + phase) * np.asarray(g, dtype=np.float64)
+    return out
 
 
 def rk4_step(U, V, dt, f):
@@ -243,9 +257,24 @@ def rk4_step(U, V, dt, f):
             V + dt / 6.0 * (k1v + 2 * k2v + 2 * k3v + k4v))
 
 
-def run(U, V, ops, dt, steps):
-    for _ in range(steps):
-        U, V = rk4_step(U, V, dt, lambda a, b: rhs(a, b, ops))
+def rk4_step_t(U, V, t, dt, f):
+    """One classical RK4 step for Z' = f(t, Z) from time t."""
+    k1u, k1v = f(t, U, V)
+    k2u, k2v = f(t + 0.5 * dt, U + 0.5 * dt * k1u, V + 0.5 * dt * k1v)
+    k3u, k3v = f(t + 0.5 * dt, U + 0.5 * dt * k2u, V + 0.5 * dt * k2v)
+    k4u, k4v = f(t + dt, U + dt * k3u, V + dt * k3v)
+    return (U + dt / 6.0 * (k1u + 2 * k2u + 2 * k3u + k4u),
+            V + dt / 6.0 * (k1v + 2 * k2v + 2 * k3v + k4v))
+
+
+def run(U, V, ops, dt, steps, t0=0.0):
+    """steps RK4 steps from time t0 (the time only enters through source terms)."""
+    if not ops.prob.forcing:
+        for _ in range(steps):
+            U, V = rk4_step(U, V, dt, lambda a, b: rhs(a, b, ops))
+        return U, V
+    for s in range(steps):
+        U, V = rk4_step_t(U, V, t0 + s * dt, dt, lambda t, a, b: rhs(a, b, ops, t))
     return U, V
 
 

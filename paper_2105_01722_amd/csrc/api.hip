@@ -32,7 +32,7 @@ using namespace gdw;
 static void free_all(gdw_ctx* c) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   for (auto& r : c->Y) for (auto& p : r) F(p);
-  F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh);
+  F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh); F(c->frc);
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
@@ -493,6 +493,37 @@ extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V
     GDW_HIP(c->elem_bytes == 8 ? set_state_t<double>(c, U, V, st) : set_state_t<float>(c, U, V, st));
   }
   c->have_state = 1;
+  c->t = 0.0;
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_nodal,
+                                      const double* omega, const double* phase, void* stream) {
+  if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
+  if (nterms < 0 || nterms > 4) { set_error("nterms must be in 0..4"); return GDW_EINVAL; }
+  if (nterms > 0 && (!g_nodal || !omega || !phase)) { set_error("NULL argument"); return GDW_EINVAL; }
+  for (int k = 0; k < nterms; ++k)
+    if (!std::isfinite(omega[k]) || !std::isfinite(phase[k])) {
+      set_error("omega and phase must be finite"); return GDW_EINVAL;
+    }
+  if (c->solver == GDW_SOLVE_PCG) {
+    set_error("the source term is offered on the FDM path only"); return GDW_EUNSUPPORTED;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const long per = c->nel * (long)c->n1 * c->n1;
+  if (nterms > 0 && !c->frc)
+    GDW_HIP(hipMalloc(&c->frc, (size_t)4 * per * c->elem_bytes));
+  for (int k = 0; k < nterms; ++k) {
+    const double* g = g_nodal + (size_t)k * per;
+    if (c->elem_bytes == 8)
+      GDW_HIP(launch_to_modal<double>(g, (double*)c->frc + k * per, c->Px, c->Py, c->n1, c->nel, st));
+    else
+      GDW_HIP(launch_to_modal<float>(g, (float*)c->frc + k * per, c->Px, c->Py, c->n1, c->nel, st));
+    c->f_omega[k] = omega[k];
+    c->f_phase[k] = phase[k];
+  }
+  GDW_HIP(hipStreamSynchronize(st));
+  c->nf = nterms;
   return GDW_OK;
 }
 
@@ -556,6 +587,10 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.gh = (const T*)c->gh;
   a.bcbits = 0;
   for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
+  a.nf = c->nf;
+  a.frc = (const T*)c->frc;
+  a.frc_stride = c->nel * (long)c->n1 * c->n1;
+  for (int k = 0; k < 4; ++k) a.fs[k] = (T)0;
   stage_roles(c, stage, a);
   return a;
 }
@@ -609,10 +644,16 @@ template <typename T>
 static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   StageArgs<T> a[4];
   for (int k = 0; k < 4; ++k) a[k] = fdm_stage_args<T>(c, k + 1, dt);
+  static const double cst[4] = {0.0, 0.5, 0.5, 1.0};   // RK4 stage times / dt
   hipError_t e;
-  for (int s = 0; s < steps; ++s)
-    for (int k = 0; k < 4; ++k)
+  for (int s = 0; s < steps; ++s) {
+    for (int k = 0; k < 4; ++k) {
+      for (int j = 0; j < c->nf; ++j)   // source weights at this stage's time (host)
+        a[k].fs[j] = (T)std::sin(c->f_omega[j] * (c->t + cst[k] * dt) + c->f_phase[j]);
       if ((e = launch_stage<T>(k + 1, a[k], st)) != hipSuccess) return e;
+    }
+    c->t += dt;
+  }
   return hipSuccess;
 }
 

@@ -439,6 +439,10 @@ static gdw_status check_ready(gdw_batch* b, const double* dt) {
       set_error("problem " + std::to_string(i) + " has no state: call gdw_set_state first");
       return GDW_EINVAL;
     }
+    if (b->ctx[i]->nf > 0) {
+      set_error("problem " + std::to_string(i) + ": the source term is not offered in a batch");
+      return GDW_EUNSUPPORTED;
+    }
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) {
       set_error("problem " + std::to_string(i) + ": dt must be finite and > 0");
       return GDW_EINVAL;

@@ -46,6 +46,13 @@ struct gdw_ctx {
   int trc = 0;                 // trace buffer holding the traces of y
   long long steps_taken = 0;
   int have_state = 0;
+  // source term (FDM path): nf modal fields g_k [nf][nel][n1^2] in the time-loop type,
+  // f = sum_k sin(f_omega[k] t + f_phase[k]) g_k; t = time since the last set_state
+  int nf = 0;
+  void* frc = nullptr;
+  double f_omega[4] = {0, 0, 0, 0};
+  double f_phase[4] = {0, 0, 0, 0};
+  double t = 0.0;
   int solver = GDW_SOLVE_FDM;  // resolved solver
   // ---- PCG path ----
   gdw::PcgGeom g{};

@@ -25,6 +25,12 @@ struct StageArgs {
   int nx, ny, n1;
   int bcbits;          // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
   T dt, c2, alpha, beta, tau;
+  // source term: nf terms (0..4), modal g_k at frc + k * frc_stride, weights
+  // fs[k] = sin(omega_k t_stage + phase_k) of this stage
+  const T* frc;
+  long frc_stride;
+  int nf;
+  T fs[4];
 };
 
 hipError_t launch_eig(const double* M, const double* S, int n, double* work, double* Psi,

@@ -376,7 +376,9 @@ __device__ __forceinline__ void st_state(T* p, T v) {
   else *p = v;
 }
 
-template <typename T, int STAGE, int N1C, int EPB>
+// FRC: the source term is present (a.nf > 0); without it the kernel is compiled as
+// if it did not exist.
+template <typename T, int STAGE, int N1C, int EPB, bool FRC = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   const int n1 = N1C > 0 ? N1C : a.n1;
   const int nn = n1 * n1;
@@ -461,8 +463,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     const T Lv = hEk * s[1 * n1 + ky] + hWk * s[3 * n1 + ky] + hNk * s[5 * n1 + kx] +
                  hSk * s[7 * n1 + kx];
     const T ku = vb + il * Lu;
-    const T kv = c2 * (Lv - lm * ub);
+    T kv = c2 * (Lv - lm * ub);
     const long g = (e0 + l) * nn + tid;
+    if constexpr (FRC) {
+      // + sum_k s_k(t) Psi^T M g_k: the modal coefficients of the interpolated g_k
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < a.nf) kv += a.fs[k] * a.frc[k * a.frc_stride + g];
+    }
     T nu, nv;
     if (STAGE == 1) {          // the input is y itself
       nu = ub + T(0.5) * dt * ku;
@@ -498,9 +506,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   }
 }
 
-template <typename T, int STAGE, int N1C, int EPB>
+template <typename T, int STAGE, int N1C, int EPB, bool FRC>
 __global__ __launch_bounds__(1024) void k_stage(StageArgs<T> a) {
-  stage_tile<T, STAGE, N1C, EPB>(a, blockIdx.x);
+  stage_tile<T, STAGE, N1C, EPB, FRC>(a, blockIdx.x);
 }
 
 // Grouped, persistent form: the tiles of several problems of one class (same T, N+1,
@@ -613,7 +621,10 @@ static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   const int n1 = a.n1;
   const size_t sh = (size_t)(8 * n1 + EPB * 8 * n1 + EPB * 2 * n1 * n1) * sizeof(T);
   const unsigned nblk = (unsigned)((a.nel + EPB - 1) / EPB);
-  hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB>), dim3(nblk), dim3(n1 * n1), sh, st, a);
+  if (a.nf > 0)
+    hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB, true>), dim3(nblk), dim3(n1 * n1), sh, st, a);
+  else
+    hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB, false>), dim3(nblk), dim3(n1 * n1), sh, st, a);
   return hipGetLastError();
 }
 

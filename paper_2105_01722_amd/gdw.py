@@ -65,6 +65,7 @@ def _load():
         "gdw_create": (I, [ctypes.POINTER(gdw_desc), ctypes.POINTER(P)]),
         "gdw_set_coeff": (I, [P, P, P, P, P]),
         "gdw_set_state": (I, [P, P, P, P]),
+        "gdw_set_forcing": (I, [P, I, P, ctypes.POINTER(D), ctypes.POINTER(D), P]),
         "gdw_run": (I, [P, D, I, P]),
         "gdw_get_state": (I, [P, P, P, P]),
         "gdw_energy": (I, [P, ctypes.POINTER(D), P]),
@@ -234,6 +235,23 @@ class Solver:
         gdw_set_coeff(self.ctx, *ptrs, stream=stream)
         torch.cuda.current_stream().synchronize() if stream is None else None
         self._keep_coeff = keep
+
+    def set_forcing(self, terms, stream=None):
+        """Source term f = sum_k sin(omega_k t + phase_k) g_k (include/gdw.h,
+        gdw_set_forcing): terms is a list of (g_nodal, omega, phase), at most 4; [] removes
+        it.  t counts from the last set_state."""
+        import torch
+        k = len(terms)
+        if k == 0:
+            _check(lib.gdw_set_forcing(self.ctx, 0, None, None, None, _stream(stream)),
+                   "gdw_set_forcing")
+            return
+        g = torch.stack([torch.as_tensor(t[0], dtype=torch.float64).reshape(self.shape)
+                         for t in terms]).to("cuda").contiguous()
+        om = (ctypes.c_double * k)(*[float(t[1]) for t in terms])
+        ph = (ctypes.c_double * k)(*[float(t[2]) for t in terms])
+        _check(lib.gdw_set_forcing(self.ctx, k, ctypes.c_void_p(g.data_ptr()), om, ph,
+                                   _stream(stream)), "gdw_set_forcing")
 
     def precond_data(self, stream=None):
         """(samples [n_el, 64], targets [n_el, (N+1)^2 - 1]) as float32 CUDA tensors."""
