@@ -133,18 +133,20 @@ gdw_status gdw_set_coeff(gdw_ctx* ctx, const double* c2_nodal, const double* X_n
  * PCG path before gdw_set_coeff. */
 gdw_status gdw_set_state(gdw_ctx* ctx, const double* U, const double* V, void* stream);
 
-/* Source term of the PDE (Sec. 2: u_tt = div(c^2 grad u) + f), FDM path:
+/* Source term of the PDE (Sec. 2: u_tt = div(c^2 grad u) + f):
  * f(x, y, t) = sum_k sin(omega[k] t + phase[k]) g_k(x, y), k < nterms <= 4, with t the time
  * advanced by gdw_run since the last gdw_set_state.  g_nodal holds the nterms fields
  * back to back, each at every node (device FP64, layout above); each g_k is represented
- * by its GD interpolant, like the initial data, so it adds sum_k s_k(t) g_k to dv/dt
- * (in the basis of Sec. 3.2 its modal coefficients, computed here once).  RK4 evaluates
- * the weights s_k at the stage times t, t + dt/2, t + dt/2, t + dt (on the host, per
- * launch).  omega, phase: host arrays of nterms values.  nterms = 0 removes the term.
- * The library copies g; the call synchronises `stream`.  Errors: EINVAL for a NULL ctx,
- * nterms outside 0..4, a NULL array with nterms > 0 or a non-finite omega / phase;
- * EUNSUPPORTED on the PCG path.  A batch refuses (EUNSUPPORTED) to run members that carry
- * a source term. */
+ * by its GD interpolant, like the initial data, so its load vector is M g_k (M_J g_k on
+ * mapped elements) and it adds sum_k s_k(t) g_k to dv/dt (on the FDM path as the modal
+ * coefficients of Sec. 3.2, computed here once).  RK4 evaluates the weights s_k at the
+ * stage times t, t + dt/2, t + dt/2, t + dt (FDM path: on the host per launch; PCG path:
+ * in the kernel from a device clock that a one-lane kernel advances after each step).
+ * g_k is given at the nodes' physical positions.  omega, phase: host arrays of nterms
+ * values.  nterms = 0 removes the term.  The library copies g; the call synchronises
+ * `stream`.  Errors: EINVAL for a NULL ctx, nterms outside 0..4, a NULL array with
+ * nterms > 0 or a non-finite omega / phase.  A batch refuses (EUNSUPPORTED) to run
+ * members that carry a source term. */
 gdw_status gdw_set_forcing(gdw_ctx* ctx, int nterms, const double* g_nodal, const double* omega,
                            const double* phase, void* stream);
 

@@ -52,6 +52,10 @@ class GenProblem:
     # a wall face takes the mirror exterior state of the element's own traces at its face
     # points (Dirichlet: a_ext = -a, v_ext = -v; Neumann: a_ext = a, v_ext = v)
     bc: tuple = ("periodic", "periodic", "periodic", "periodic")
+    # source terms (g_nodal [ny, nx, N+1, N+1] at the physical nodes, omega, phase):
+    # f = sum_k sin(omega_k t + phase_k) g_k with g_k represented by its GD interpolant,
+    # so the load vector of DG2 is M_J g_k and dV/dt gains sum_k s_k(t) g_k
+    forcing: tuple = ()
 
     def __post_init__(self):
         kinds = ("periodic", "dirichlet", "neumann")
@@ -300,10 +304,19 @@ def lifts(U, V, ops):
     return Fu.reshape(shp), Fv.reshape(shp)
 
 
-def rhs(U, V, ops):
-    """S_hat (dU/dt - V) = F_u,   M_J dV/dt = -S_K U + F_v   (dense direct solves)."""
+def rhs(U, V, ops, t=0.0):
+    """S_hat (dU/dt - V) = F_u,   M_J dV/dt = -S_K U + F_v + sum_k s_k(t) M_J g_k
+    (dense direct solves; the source term's solve is exact: M_J^-1 M_J g_k = g_k)."""
     Fu, Fv = lifts(U, V, ops)
-    return V + ops.solve_Shat(Fu), ops.solve_M(-ops.apply_S(U) + Fv)
+    return V + ops.solve_Shat(Fu), ops.solve_M(-ops.apply_S(U) + Fv) + forcing_term(ops.prob, t)
+
+
+def forcing_term(prob, t):
+    """sum_k sin(omega_k t + phase_k) g_k (nodal; zero without source terms)."""
+    out = 0.0
+    for g, omega, phase in prob.forcing:
+        out = out + np.sin(omega * t + phase) * np.asarray(g, dtype=np.float64)
+    return out
 
 
 def rk4_step(U, V, dt, f):
@@ -315,10 +328,22 @@ def rk4_step(U, V, dt, f):
             V + dt / 6.0 * (k1v + 2 * k2v + 2 * k3v + k4v))
 
 
-def run(U, V, ops, dt, steps, f=None):
-    f = f or (lambda a, b: rhs(a, b, ops))
-    for _ in range(steps):
-        U, V = rk4_step(U, V, dt, f)
+def run(U, V, ops, dt, steps, f=None, t0=0.0):
+    """steps RK4 steps from time t0; a source term makes the stages time-dependent
+    (stage times t, t + dt/2, t + dt/2, t + dt).  f: a custom right-hand side (U, V)."""
+    if f is not None or not ops.prob.forcing:
+        f = f or (lambda a, b: rhs(a, b, ops))
+        for _ in range(steps):
+            U, V = rk4_step(U, V, dt, f)
+        return U, V
+    for s in range(steps):
+        t = t0 + s * dt
+        k1u, k1v = rhs(U, V, ops, t)
+        k2u, k2v = rhs(U + 0.5 * dt * k1u, V + 0.5 * dt * k1v, ops, t + 0.5 * dt)
+        k3u, k3v = rhs(U + 0.5 * dt * k2u, V + 0.5 * dt * k2v, ops, t + 0.5 * dt)
+        k4u, k4v = rhs(U + dt * k3u, V + dt * k3v, ops, t + dt)
+        U = U + dt / 6.0 * (k1u + 2 * k2u + 2 * k3u + k4u)
+        V = V + dt / 6.0 * (k1v + 2 * k2v + 2 * k3v + k4v)
     return U, V
 
 

@@ -32,7 +32,7 @@ using namespace gdw;
 static void free_all(gdw_ctx* c) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   for (auto& r : c->Y) for (auto& p : r) F(p);
-  F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh); F(c->frc);
+  F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh); F(c->frc); F(c->t_dev);
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
@@ -494,6 +494,7 @@ extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V
   }
   c->have_state = 1;
   c->t = 0.0;
+  if (c->t_dev) GDW_HIP(hipMemcpyAsync(c->t_dev, &c->t, sizeof(double), hipMemcpyHostToDevice, st));
   return GDW_OK;
 }
 
@@ -506,11 +507,26 @@ extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_no
     if (!std::isfinite(omega[k]) || !std::isfinite(phase[k])) {
       set_error("omega and phase must be finite"); return GDW_EINVAL;
     }
-  if (c->solver == GDW_SOLVE_PCG) {
-    set_error("the source term is offered on the FDM path only"); return GDW_EUNSUPPORTED;
-  }
   hipStream_t st = (hipStream_t)stream;
   const long per = c->nel * (long)c->n1 * c->n1;
+  if (c->solver == GDW_SOLVE_PCG) {
+    // nodal FP64 fields; the stage epilogue adds sum_k s_k g_k to dv/dt
+    if (nterms > 0 && !c->frc) GDW_HIP(hipMalloc(&c->frc, (size_t)4 * per * sizeof(double)));
+    if (nterms > 0 && !c->t_dev) {
+      GDW_HIP(hipMalloc(&c->t_dev, 17 * sizeof(double)));   // clock, then 16 weights
+      GDW_HIP(hipMemcpyAsync(c->t_dev, &c->t, sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    for (int k = 0; k < nterms; ++k) {
+      GDW_HIP(hipMemcpyAsync((double*)c->frc + k * per, g_nodal + (size_t)k * per,
+                             (size_t)per * sizeof(double), hipMemcpyDeviceToDevice, st));
+      c->f_omega[k] = omega[k];
+      c->f_phase[k] = phase[k];
+    }
+    GDW_HIP(hipStreamSynchronize(st));
+    c->nf = nterms;
+    c->pargs_ok = 0;   // the stage argument blocks carry the source
+    return GDW_OK;
+  }
   if (nterms > 0 && !c->frc)
     GDW_HIP(hipMalloc(&c->frc, (size_t)4 * per * c->elem_bytes));
   for (int k = 0; k < nterms; ++k) {
@@ -611,6 +627,10 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.ny = c->d.ny;
   a.bcbits = 0;
   for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
+  a.nf = c->nf;
+  a.frc = (const double*)c->frc;
+  a.frc_stride = c->nel * (long)c->n1 * c->n1;
+  a.f_w = c->t_dev ? c->t_dev + 1 : nullptr;
   a.mapped = c->d.mapped;
   a.dt = dt;
   a.alpha = c->alpha;
@@ -676,13 +696,23 @@ static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   }
   c->pargs_used = 1;
   const int key = pcg_group_key(c->h_pargs[0]);
-  for (int s = 0; s < steps; ++s)
+  SourceTerms src{};
+  src.nf = c->nf;
+  for (int k = 0; k < 4; ++k) {
+    src.omega[k] = c->f_omega[k];
+    src.phase[k] = c->f_phase[k];
+  }
+  for (int s = 0; s < steps; ++s) {
+    if (c->nf > 0 && (e = launch_source_step(c->t_dev, c->t_dev + 1, dt, src, st)) != hipSuccess)
+      return e;
     for (int k = 0; k < 4; ++k) {
       const unsigned grid = pcg_group_grid(k + 1, key, c->p_threads, c->p_lds, c->nel);
       if ((e = launch_pcg_stage_group(k + 1, key, c->d_pargs + k, c->d_pel, 1, grid, c->p_threads,
                                       c->p_lds, st)) != hipSuccess)
         return e;
     }
+    c->t += dt;
+  }
   c->stages_since_state += 4LL * steps;
   return hipSuccess;
 }

@@ -53,6 +53,7 @@ struct gdw_ctx {
   double f_omega[4] = {0, 0, 0, 0};
   double f_phase[4] = {0, 0, 0, 0};
   double t = 0.0;
+  double* t_dev = nullptr;     // PCG path: device clock t, then the step's stage weights [16]
   int solver = GDW_SOLVE_FDM;  // resolved solver
   // ---- PCG path ----
   gdw::PcgGeom g{};

@@ -81,7 +81,25 @@ struct PcgStageArgs {
   const int* blk_gidx;  // register kernels: [CH * W][blk_threads] upper-half index of each
                         // unit entry (-1: padding)
   int blk_K, blk_CH, blk_WB, blk_threads;
+  // source term: nf nodal fields g_k at frc + k * frc_stride; dv/dt gains
+  // sum_k f_w[4 (stage - 1) + k] g_k, the weights of the current step (written by
+  // launch_source_step before the step's four stages)
+  const double* frc;
+  long frc_stride;
+  int nf;
+  const double* f_w;
 };
+
+struct SourceTerms {
+  int nf;
+  double omega[4], phase[4];
+};
+
+// One lane, before each RK4 step of the PCG path: the weights
+// w[4 (s - 1) + k] = sin(omega_k (t + c_s dt) + phase_k) of the step's stages s = 1..4
+// (c = 0, 1/2, 1/2, 1) from the device clock t = *t_dev, then t += dt.
+hipError_t launch_source_step(double* t_dev, double* w, double dt, const SourceTerms& f,
+                              hipStream_t st);
 
 // Column-block layout tables for one geometry; returns 0 when the layout does not apply
 // (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.

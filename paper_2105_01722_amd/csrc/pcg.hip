@@ -845,9 +845,15 @@ __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn;
   const bool own = t < nn;
-  const double ku = C.vb + y, kv = z, dt = a.dt;
+  const double ku = C.vb + y, dt = a.dt;
+  double kv = z;
   if (own) {
     const long gi = e * nn + t;
+    if (a.nf > 0) {   // source term: M_J^-1 (M_J g_k) = g_k, added to dv/dt
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < a.nf) kv += a.f_w[4 * (STAGE - 1) + k] * a.frc[k * a.frc_stride + gi];
+    }
     double nu, nv;
     if (STAGE == 1) {
       nu = C.ub + 0.5 * dt * ku;
@@ -1970,6 +1976,22 @@ __global__ void k_mscale(PcgGeom g, PcgElem el, long nel) {
   const double d = el.M[e * g.nst + g.rowoff[i] + st_pos(ix, iy, ix, iy, g.p, g.N)];
   const double pm = el.sc[e * 8 + 4] * g.Mref[iy * g.n1 + iy] * g.Mref[ix * g.n1 + ix];
   el.msc[id] = sqrt(pm / d);
+}
+
+__global__ void k_source_step(double* t_dev, double* w, double dt, SourceTerms f) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double t = t_dev[0];
+  const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 4; ++k)
+      w[4 * s + k] = k < f.nf ? sin(f.omega[k] * (t + cs[s] * dt) + f.phase[k]) : 0.0;
+  t_dev[0] = t + dt;
+}
+
+hipError_t launch_source_step(double* t_dev, double* w, double dt, const SourceTerms& f,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_source_step, dim3(1), dim3(64), 0, st, t_dev, w, dt, f);
+  return hipGetLastError();
 }
 
 hipError_t launch_mscale(const PcgGeom& g, const PcgElem& el, long nel, hipStream_t st) {
