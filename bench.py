@@ -34,7 +34,7 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
 # by a plain device copy's reading of the same counters (x2.0 read, x1.0 write); the
 # summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.  Set to None
 # whenever that kernel changes until the counters are taken again.
-FDM_STAGE_TRAFFIC = (319255.72 * 2.0 + 468908.02) * 1024.0
+FDM_STAGE_TRAFFIC = (319211.54 * 2.0 + 468832.59) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -425,7 +425,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": FDM_STAGE_TRAFFIC,
                      "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
-                     "kernel": "k_stage<double,*,17,4> (4 stage variants)",
+                     "kernel": "k_stage<double,*,17,4,false> (4 stage variants)",
                      "avg_launch_us": ms64 * 1e3 / launches,
                      "alg_bytes_per_launch": alg_bytes_step / 4},
     }
