@@ -66,6 +66,12 @@ __device__ inline dd dd_fma_dd(dd x, double a, dd y) {
 // R = I - X^T M X and T = X^T S X evaluated in double-double,
 // lambda_i = T_ii / (1 - R_ii), E_ii = R_ii / 2 and, for i != j,
 // E_ij = (T_ij + lambda_j R_ij) / (lambda_j - lambda_i); X <- X + X E.
+// Pairs closer than 1e-3 max|lambda| are treated as a cluster, E_ij = R_ij / 2 (the
+// method's rule for close eigenvalues): the GD pencils have close pairs at the top of the
+// spectrum (relative gap 6e-4 at N = 16, p = 5, 2e-7 at N = 31, p = 7), and dividing by
+// such a gap amplifies the rounding of the FP64 update (X^T M X drifted from I by 1e-13
+// at N = 31).  Inside a cluster the rotation keeps Jacobi's accuracy, eps / gap <= 1e-13,
+// which changes X Lambda X^T by about 1e-16 relative.
 // X = Psi [n][n] (column k = eigenvector k), lam [n]; R, T [n][n] and col [4n] scratch.
 __device__ void eig_refine_sweep(const double* M, const double* S, int n, double* X, double* lam,
                                  double* R, double* T, double* col, bool update) {
@@ -101,7 +107,8 @@ __device__ void eig_refine_sweep(const double* M, const double* S, int n, double
     for (int j = 0; j < n; ++j) {
       if (i == j) continue;
       const double gap = lam[j] - lam[i];
-      T[i * n + j] = (fabs(gap) > 1e-12 * lmax) ? (T[i * n + j] + lam[j] * R[i * n + j]) / gap : 0.0;
+      T[i * n + j] = (fabs(gap) > 1e-3 * lmax) ? (T[i * n + j] + lam[j] * R[i * n + j]) / gap
+                                               : 0.5 * R[i * n + j];
     }
   for (int i = 0; i < n; ++i) T[i * n + i] = 0.5 * R[i * n + i];
   // X <- X + X E, row by row

@@ -183,3 +183,45 @@ def test_nonfinite_state_reported(precision):
         assert np.isfinite(s.energy())
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("nx,ny,N,p,precision,bc", [
+    (2, 3, 31, 7, "fp64", ("periodic",) * 4),      # N + 1 = 32: 1024 threads, 2 elements per tile
+    (3, 2, 31, 5, "fp32", ("periodic",) * 4),
+    (3, 2, 5, 5, "fp64", ("periodic",) * 4),       # N = p
+    (2, 2, 7, 7, "fp64", ("dirichlet",) * 4),
+    (1, 1, 9, 3, "fp64", ("dirichlet", "dirichlet", "neumann", "neumann")),  # one element, walls
+])
+def test_largest_and_degenerate_sizes(nx, ny, N, p, precision, bc):
+    """The largest element the library accepts (N + 1 = 32, one thread per modal index:
+    1024 threads, the workgroup limit), the smallest N for a degree (N = p), and a single
+    element whose four faces are all walls.  Smooth data.  FP64 bar: max(1e-12, 4 x the
+    oracle's Cholesky-vs-LU spread, 4 x the distance between the oracle with S and with
+    S~ = M Psi Lambda Psi^T M from an FP64 eigenbasis) -- the rounding floor of a
+    simultaneous-diagonalisation solve, which grows with cond(S_hat) and is largest at
+    N + 1 = 32, p = 7."""
+    _say("case: extreme sizes", nx, ny, N, p, precision, bc)
+    from paper_2105_01722_amd import gdw
+    prob = dg2d.CartProblem(nx=nx, ny=ny, N=N, p=p, flux="upwind", bc=bc)
+    X, Y = dg2d.node_coords(prob)
+    U0 = inputs.fourier_field(inputs.fourier_modes(6, kmax=3), X, Y)
+    V0 = 0.2 * inputs.fourier_field(inputs.fourier_modes(7, kmax=3), X, Y)
+    dt = 0.05 * prob.hx
+    s = gdw.Solver(nx, ny, N, p, flux="upwind", xi=1.0, precision=precision, bc=bc)
+    try:
+        s.set_state(U0, V0)
+        s.run(dt, 4)
+        Ug, Vg = (x.cpu().numpy() for x in s.get_state())
+        assert s.stats()["status"] == 0
+    finally:
+        s.close()
+    Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, 4)
+    if precision == "fp32":
+        assert _rel(Ug, Uo) <= 1e-6
+        return
+    from test_gpu_fullsize import _eigen_ops
+    U2, V2 = dg2d.run(U0, V0, _lu_ops(prob), dt, 4)
+    U3, V3 = dg2d.run(U0, V0, _eigen_ops(dg2d.CartOps(prob)), dt, 4)
+    _say("  rel U %.1e (lu %.1e, S~ %.1e)" % (_rel(Ug, Uo), _rel(U2, Uo), _rel(U3, Uo)))
+    assert _rel(Ug, Uo) <= max(1e-12, 4 * _rel(U2, Uo), 4 * _rel(U3, Uo))
+    assert _rel(Vg, Vo) <= max(1e-12, 4 * _rel(V2, Vo), 4 * _rel(V3, Vo))
