@@ -140,13 +140,14 @@ gdw_status gdw_set_state(gdw_ctx* ctx, const double* U, const double* V, void* s
  * by its GD interpolant, like the initial data, so its load vector is M g_k (M_J g_k on
  * mapped elements) and it adds sum_k s_k(t) g_k to dv/dt (on the FDM path as the modal
  * coefficients of Sec. 3.2, computed here once).  RK4 evaluates the weights s_k at the
- * stage times t, t + dt/2, t + dt/2, t + dt (FDM path: on the host per launch; PCG path:
- * in the kernel from a device clock that a one-lane kernel advances after each step).
+ * stage times t, t + dt/2, t + dt/2, t + dt: before each step a one-lane kernel computes
+ * the step's weights from a device clock and advances it (also inside a batch's captured
+ * step).
  * g_k is given at the nodes' physical positions.  omega, phase: host arrays of nterms
  * values.  nterms = 0 removes the term.  The library copies g; the call synchronises
  * `stream`.  Errors: EINVAL for a NULL ctx, nterms outside 0..4, a NULL array with
- * nterms > 0 or a non-finite omega / phase.  A batch refuses (EUNSUPPORTED) to run
- * members that carry a source term. */
+ * nterms > 0 or a non-finite omega / phase.  A batch rebuilds its captured step after
+ * a member's source term changes. */
 gdw_status gdw_set_forcing(gdw_ctx* ctx, int nterms, const double* g_nodal, const double* omega,
                            const double* phase, void* stream);
 

@@ -494,7 +494,7 @@ extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V
   }
   c->have_state = 1;
   c->t = 0.0;
-  if (c->t_dev) GDW_HIP(hipMemcpyAsync(c->t_dev, &c->t, sizeof(double), hipMemcpyHostToDevice, st));
+  if (c->t_dev) GDW_HIP(launch_set_clock(c->t_dev, 0.0, st));
   return GDW_OK;
 }
 
@@ -514,7 +514,7 @@ extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_no
     if (nterms > 0 && !c->frc) GDW_HIP(hipMalloc(&c->frc, (size_t)4 * per * sizeof(double)));
     if (nterms > 0 && !c->t_dev) {
       GDW_HIP(hipMalloc(&c->t_dev, 17 * sizeof(double)));   // clock, then 16 weights
-      GDW_HIP(hipMemcpyAsync(c->t_dev, &c->t, sizeof(double), hipMemcpyHostToDevice, st));
+      GDW_HIP(launch_set_clock(c->t_dev, c->t, st));
     }
     for (int k = 0; k < nterms; ++k) {
       GDW_HIP(hipMemcpyAsync((double*)c->frc + k * per, g_nodal + (size_t)k * per,
@@ -525,10 +525,15 @@ extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_no
     GDW_HIP(hipStreamSynchronize(st));
     c->nf = nterms;
     c->pargs_ok = 0;   // the stage argument blocks carry the source
+    ++c->args_epoch;
     return GDW_OK;
   }
   if (nterms > 0 && !c->frc)
     GDW_HIP(hipMalloc(&c->frc, (size_t)4 * per * c->elem_bytes));
+  if (nterms > 0 && !c->t_dev) {
+    GDW_HIP(hipMalloc(&c->t_dev, 17 * sizeof(double)));   // clock, then 16 weights
+    GDW_HIP(launch_set_clock(c->t_dev, c->t, st));
+  }
   for (int k = 0; k < nterms; ++k) {
     const double* g = g_nodal + (size_t)k * per;
     if (c->elem_bytes == 8)
@@ -540,6 +545,7 @@ extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_no
   }
   GDW_HIP(hipStreamSynchronize(st));
   c->nf = nterms;
+  ++c->args_epoch;   // a batch rebuilds its captured step
   return GDW_OK;
 }
 
@@ -586,6 +592,16 @@ static void stage_roles(const gdw_ctx* c, int stage, P& a) {
   }
 }
 
+SourceTerms source_terms(const gdw_ctx* c) {
+  SourceTerms f{};
+  f.nf = c->nf;
+  for (int k = 0; k < 4; ++k) {
+    f.omega[k] = c->f_omega[k];
+    f.phase[k] = c->f_phase[k];
+  }
+  return f;
+}
+
 template <typename T>
 StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   StageArgs<T> a{};
@@ -606,7 +622,7 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.nf = c->nf;
   a.frc = (const T*)c->frc;
   a.frc_stride = c->nel * (long)c->n1 * c->n1;
-  for (int k = 0; k < 4; ++k) a.fs[k] = (T)0;
+  a.fw = c->t_dev ? c->t_dev + 1 : nullptr;
   stage_roles(c, stage, a);
   return a;
 }
@@ -664,14 +680,13 @@ template <typename T>
 static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   StageArgs<T> a[4];
   for (int k = 0; k < 4; ++k) a[k] = fdm_stage_args<T>(c, k + 1, dt);
-  static const double cst[4] = {0.0, 0.5, 0.5, 1.0};   // RK4 stage times / dt
+  const SourceTerms src = source_terms(c);
   hipError_t e;
   for (int s = 0; s < steps; ++s) {
-    for (int k = 0; k < 4; ++k) {
-      for (int j = 0; j < c->nf; ++j)   // source weights at this stage's time (host)
-        a[k].fs[j] = (T)std::sin(c->f_omega[j] * (c->t + cst[k] * dt) + c->f_phase[j]);
+    if (c->nf > 0 && (e = launch_source_step(c->t_dev, c->t_dev + 1, dt, src, st)) != hipSuccess)
+      return e;
+    for (int k = 0; k < 4; ++k)
       if ((e = launch_stage<T>(k + 1, a[k], st)) != hipSuccess) return e;
-    }
     c->t += dt;
   }
   return hipSuccess;
@@ -696,12 +711,7 @@ static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   }
   c->pargs_used = 1;
   const int key = pcg_group_key(c->h_pargs[0]);
-  SourceTerms src{};
-  src.nf = c->nf;
-  for (int k = 0; k < 4; ++k) {
-    src.omega[k] = c->f_omega[k];
-    src.phase[k] = c->f_phase[k];
-  }
+  const SourceTerms src = source_terms(c);
   for (int s = 0; s < steps; ++s) {
     if (c->nf > 0 && (e = launch_source_step(c->t_dev, c->t_dev + 1, dt, src, st)) != hipSuccess)
       return e;

@@ -320,6 +320,11 @@ static gdw_status build_graph(gdw_batch* b, const std::vector<double>& dt) {
     }
   GDW_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
+  // source terms: each member's step weights from its device clock, before the stages
+  for (size_t i = 0; i < b->ctx.size() && e == hipSuccess; ++i) {
+    gdw_ctx* x = b->ctx[i];
+    if (x->nf > 0) e = launch_source_step(x->t_dev, x->t_dev + 1, dt[i], source_terms(x), b->cap);
+  }
   for (int k = 1; k <= 4 && e == hipSuccess; ++k) {
     for (auto& c : b->fdm) {
       if ((e = launch_fdm_class(c, k, c.epb, c.grid, b->cap)) != hipSuccess) break;
@@ -439,10 +444,6 @@ static gdw_status check_ready(gdw_batch* b, const double* dt) {
       set_error("problem " + std::to_string(i) + " has no state: call gdw_set_state first");
       return GDW_EINVAL;
     }
-    if (b->ctx[i]->nf > 0) {
-      set_error("problem " + std::to_string(i) + ": the source term is not offered in a batch");
-      return GDW_EUNSUPPORTED;
-    }
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) {
       set_error("problem " + std::to_string(i) + ": dt must be finite and > 0");
       return GDW_EINVAL;
@@ -492,8 +493,10 @@ extern "C" gdw_status gdw_batch_run(gdw_batch* b, const double* dt, int steps, v
   }
   GDW_HIP(hipEventRecord(b->ev[steps], st));
   b->last_steps = steps;
-  for (gdw_ctx* c : b->ctx) {
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    gdw_ctx* c = b->ctx[i];
     c->steps_taken += steps;
+    c->t += steps * d[i];   // host mirror of the source clock (the device clock advanced)
     if (c->solver == GDW_SOLVE_PCG) c->stages_since_state += 4LL * steps;
   }
   return GDW_OK;

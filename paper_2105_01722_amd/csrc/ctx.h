@@ -102,5 +102,7 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt);
 // Stage arguments of RK stage `stage` of a PCG context (full / Q / nnz_full left 0: the
 // launchers set them).
 PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt);
+// The source terms of a context (for launch_source_step).
+SourceTerms source_terms(const gdw_ctx* c);
 
 }  // namespace gdw

@@ -25,12 +25,13 @@ struct StageArgs {
   int nx, ny, n1;
   int bcbits;          // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
   T dt, c2, alpha, beta, tau;
-  // source term: nf terms (0..4), modal g_k at frc + k * frc_stride, weights
-  // fs[k] = sin(omega_k t_stage + phase_k) of this stage
+  // source term: nf terms (0..4), modal g_k at frc + k * frc_stride; the weights
+  // fw[4 (stage - 1) + k] = sin(omega_k t_stage + phase_k) of the current step sit in
+  // device memory (written by launch_source_step before the step's stages)
   const T* frc;
   long frc_stride;
   int nf;
-  T fs[4];
+  const double* fw;
 };
 
 hipError_t launch_eig(const double* M, const double* S, int n, double* work, double* Psi,

@@ -476,7 +476,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
       // + sum_k s_k(t) Psi^T M g_k: the modal coefficients of the interpolated g_k
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (k < a.nf) kv += a.fs[k] * a.frc[k * a.frc_stride + g];
+        if (k < a.nf) kv += (T)a.fw[4 * (STAGE - 1) + k] * a.frc[k * a.frc_stride + g];
     }
     T nu, nv;
     if (STAGE == 1) {          // the input is y itself
@@ -530,7 +530,9 @@ __global__ __launch_bounds__(1024) void k_stage_group(const StageArgs<T>* __rest
   int pi = 0;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
     while (pi + 1 < nprob && b >= tile_start[pi + 1]) ++pi;
-    stage_tile<T, STAGE, N1C, EPB>(args[pi], b - tile_start[pi]);
+    // the source-term build: without a source (nf = 0) it adds nothing, so members stay
+    // bitwise equal to their solo runs
+    stage_tile<T, STAGE, N1C, EPB, true>(args[pi], b - tile_start[pi]);
     __syncthreads();   // the next tile reuses the LDS
   }
 }

@@ -100,6 +100,8 @@ struct SourceTerms {
 // (c = 0, 1/2, 1/2, 1) from the device clock t = *t_dev, then t += dt.
 hipError_t launch_source_step(double* t_dev, double* w, double dt, const SourceTerms& f,
                               hipStream_t st);
+// Set the device clock to t and clear the 16 weights after it (one lane, stream-ordered).
+hipError_t launch_set_clock(double* t_dev, double t, hipStream_t st);
 
 // Column-block layout tables for one geometry; returns 0 when the layout does not apply
 // (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.

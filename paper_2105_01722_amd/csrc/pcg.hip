@@ -1988,6 +1988,15 @@ __global__ void k_source_step(double* t_dev, double* w, double dt, SourceTerms f
   t_dev[0] = t + dt;
 }
 
+__global__ void k_set_clock(double* t_dev, double t) {
+  if (blockIdx.x == 0 && threadIdx.x < 17) t_dev[threadIdx.x] = threadIdx.x == 0 ? t : 0.0;
+}
+
+hipError_t launch_set_clock(double* t_dev, double t, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, st, t_dev, t);
+  return hipGetLastError();
+}
+
 hipError_t launch_source_step(double* t_dev, double* w, double dt, const SourceTerms& f,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_source_step, dim3(1), dim3(64), 0, st, t_dev, w, dt, f);

@@ -3,7 +3,9 @@ C ABI, on the constant-coefficient path and on the PCG path (mapped elements, va
 
 Bars: FP64 nodal state relative l2 <= 1e-12 against the oracle (the periodic tests' bar),
 FP32 storage <= 1e-6; a manufactured solution converges on the GPU path as in the oracle;
-the source's clock continues across gdw_run calls and restarts at gdw_set_state.
+the source's clock continues across gdw_run calls and restarts at gdw_set_state; in a
+batch (one captured step replayed) every member equals its solo run (constant-coefficient
+members bitwise, PCG members within 1e-12).
 """
 import sys
 
@@ -171,16 +173,6 @@ def test_forcing_errors():
         assert ei.value.status == gdw.GDW_EINVAL
     finally:
         s.close()
-    b = gdw.Batch([dict(nx=2, ny=2, N=8, p=3, flux="upwind")])
-    try:
-        X, Y = inputs.node_coords(2, 2, 8)
-        b.problems[0].set_state(np.sin(2 * np.pi * X), np.zeros_like(X))
-        b.problems[0].set_forcing([(np.ones_like(X), 1.0, 0.0)])
-        with pytest.raises(gdw.GdwError) as ei:
-            b.run([0.01], 1)
-        assert ei.value.status == gdw.GDW_EUNSUPPORTED
-    finally:
-        b.close()
 
 
 # ---- PCG path -------------------------------------------------------------------------
@@ -254,3 +246,57 @@ def test_pcg_manufactured_solution_on_curved_mesh_converges():
     rate = np.log2(errs[0] / errs[1])
     _say("  errors", errs, "rate", rate)
     assert errs[1] < 1e-5 and rate > 5.0
+
+
+def test_batch_with_source_terms_equals_solo_runs():
+    """Forced and unforced members in the same classes; two runs (3 + 2 steps) so the
+    captured step's weights kernel must advance each member's clock."""
+    from paper_2105_01722_amd import gdw
+    _say("case: batch with source terms")
+    probs = [dict(nx=3, ny=2, N=8, p=3, flux="upwind", precision="fp64"),
+             dict(nx=2, ny=2, N=8, p=3, flux="upwind", precision="fp64"),
+             dict(nx=4, ny=3, N=12, p=5, flux="upwind", precision="fp32",
+                  bc=("dirichlet",) * 4),
+             dict(nx=2, ny=2, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True,
+                  mapped=True, pcg_rtol=1e-13),
+             dict(nx=2, ny=3, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True,
+                  mapped=True, pcg_rtol=1e-13)]
+    forced = [True, False, True, True, False]
+
+    def setup(s, i, kw):
+        X, Y = inputs.node_coords(kw["nx"], kw["ny"], kw["N"])
+        if kw.get("solver") == "pcg":
+            Xm, Ym = inputs.mapped_coords(X, Y)
+            s.set_coeff(inputs.c2_field(80 + i, X, Y), Xm, Ym)
+            X, Y = Xm, Ym
+        U0 = inputs.fourier_field(inputs.fourier_modes(90 + i, kmax=3), X, Y)
+        s.set_state(U0, np.zeros_like(U0))
+        if forced[i]:
+            g = inputs.fourier_field(inputs.fourier_modes(95 + i, kmax=3), X, Y)
+            s.set_forcing([(g, 4.0 + i, 0.1 * i), (0.5 * g, 9.0, -0.3)])
+
+    dts = [0.1 / (max(kw["nx"], kw["ny"]) * kw["N"]) for kw in probs]
+    b = gdw.Batch(probs)
+    try:
+        for i, kw in enumerate(probs):
+            setup(b.problems[i], i, kw)
+        b.run(dts, 3)
+        b.run(dts, 2)
+        got = [tuple(x.cpu().numpy() for x in b.problems[i].get_state()) for i in range(len(probs))]
+    finally:
+        b.close()
+    for i, kw in enumerate(probs):
+        s = gdw.Solver(**kw)
+        try:
+            setup(s, i, kw)
+            s.run(dts[i], 3)
+            s.run(dts[i], 2)
+            U, V = (x.cpu().numpy() for x in s.get_state())
+        finally:
+            s.close()
+        Ub, Vb = got[i]
+        if kw.get("solver") == "pcg":
+            assert _rel(Ub, U) <= 1e-12 and _rel(Vb, V) <= 1e-12
+        else:
+            np.testing.assert_array_equal(Ub, U)
+            np.testing.assert_array_equal(Vb, V)
