@@ -2,8 +2,8 @@
 the FP64 oracle, through the C ABI.
 
 Bar: FP64 nodal state relative l2 <= 1e-12 against the oracle at t_final; FP32
-storage mode <= 1e-6.  Sizes span several 4-element (FP64) / 8-element (FP32)
-workgroup tiles with a ragged last tile.
+storage mode <= 1e-6.  Sizes span several 4-element workgroup tiles with a ragged last
+tile.
 """
 import sys
 

@@ -3,9 +3,8 @@ constant-coefficient path and on the PCG path (mapped elements, variable c^2), t
 the C ABI, and the paper's 2D Dirichlet experiment.
 
 Parity bar: FP64 nodal state relative l2 <= 1e-12 against the FP64 oracle (the same bar
-as the periodic tests), FP32 storage <= 1e-6.  Grids span several 4-element (FP64) and
-8-element (FP32) workgroup tiles with a ragged last tile, and put wall faces on both ends
-of tiles and inside them.
+as the periodic tests), FP32 storage <= 1e-6.  Grids span several 4-element workgroup
+tiles with a ragged last tile, and put wall faces on both ends of tiles and inside them.
 
 The second part runs the experiment of Sec. 6 "Dirichlet Boundary Conditions in Two
 Dimensions" on the GPU path and compares the regression rates with the printed ones
