@@ -176,10 +176,10 @@ def test_forcing_errors():
 
 
 # ---- PCG path -------------------------------------------------------------------------
-def _pcg(n, N, p, Xm, Ym, c2, bc=("periodic",) * 4, rtol=1e-13):
+def _pcg(n, N, p, Xm, Ym, c2, bc=("periodic",) * 4, rtol=1e-13, precision="fp64"):
     from paper_2105_01722_amd import gdw
     s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
-                   mapped=True, pcg_rtol=rtol, bc=bc)
+                   mapped=True, pcg_rtol=rtol, bc=bc, precision=precision)
     s.set_coeff(c2, Xm, Ym)
     return s
 
@@ -300,3 +300,31 @@ def test_batch_with_source_terms_equals_solo_runs():
         else:
             np.testing.assert_array_equal(Ub, U)
             np.testing.assert_array_equal(Vb, V)
+
+
+def test_pcg_mixed_precision_with_source():
+    """Mixed-precision PCG (FP32 inner iterations, FP64 refinement) with a source term
+    and walls, against the dense oracle at the mixed path's bar (1e-10)."""
+    _say("case: pcg mixed with source")
+    n, N, p = 3, 12, 5
+    bc = ("dirichlet", "dirichlet", "neumann", "neumann")
+    X, Y = inputs.node_coords(n, n, N)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    c2 = inputs.c2_field(3, X, Y)
+    terms = [(inputs.fourier_field(inputs.fourier_modes(75, kmax=3), Xm, Ym), 6.0, 0.2)]
+    U0 = inputs.fourier_field(inputs.fourier_modes(2, kmax=3), Xm, Ym)
+    dt = 0.1 / (n * N)
+    s = _pcg(n, N, p, Xm, Ym, c2, bc, precision="mixed")
+    try:
+        s.set_forcing(terms)
+        s.set_state(U0, np.zeros_like(U0))
+        s.run(dt, 3)
+        Ug, Vg = (x.cpu().numpy() for x in s.get_state())
+        st = s.stats(check=False)
+        assert st["status"] == 0 and st["mean_refine"] >= 1.0
+    finally:
+        s.close()
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=bc,
+                                            forcing=tuple(terms)), Xm, Ym, c2)
+    Uo, Vo = general.run(U0, np.zeros_like(U0), ops, dt, 3)
+    assert _rel(Ug, Uo) <= 1e-10 and _rel(Vg, Vo) <= 1e-10
