@@ -63,15 +63,29 @@ def _time_gpu(w, precision, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    U, _ = s.get_state()
+    U, V = s.get_state()
     st = s.stats()
     s.close()
-    from paper_2105_01722_amd import inputs
     T = w["dt"] * (steps + warmup)
-    exact = inputs.fourier_field(w["modes"], w["X"], w["Y"], t=T)
-    Uh = U.cpu().numpy()
-    err = float(np.linalg.norm(Uh - exact) / np.linalg.norm(exact))
+    Ue, Ve = _fourier_exact_uv(w["modes"], w["X"], w["Y"], T)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = {"u": float(np.linalg.norm(Uh - Ue) / np.linalg.norm(Ue)),
+           "v": float(np.linalg.norm(Vh - Ve) / np.linalg.norm(Ve)),
+           "u_max": float(np.abs(Uh - Ue).max() / np.abs(Ue).max()),
+           "v_max": float(np.abs(Vh - Ve).max() / np.abs(Ve).max())}
     return ms, err, st
+
+
+def _fourier_exact_uv(modes, X, Y, t):
+    """u and v = u_t of the exact solution from the Fourier data with v0 = 0 (c = 1)."""
+    U = np.zeros_like(X)
+    V = np.zeros_like(X)
+    for kx, ky, a, th in modes:
+        wk = 2 * np.pi * np.hypot(kx, ky)
+        ph = np.cos(2 * np.pi * (kx * X + ky * Y) + th)
+        U += a * np.cos(wk * t) * ph
+        V -= a * wk * np.sin(wk * t) * ph
+    return U, V
 
 
 def _time_walls(steps, warmup, n=256, N=16, p=5, cfl=0.15, k=4, l=3):
@@ -323,30 +337,50 @@ def _batch_section(steps, seed=4, n_prob=64):
     }
 
 
+def _physical_cores():
+    """Physical cores of the host from lscpu (distinct (core, socket) pairs), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu", "-p=Core,Socket"], capture_output=True, text=True,
+                             timeout=10).stdout
+        pairs = {ln.strip() for ln in out.splitlines() if ln and not ln.startswith("#")}
+        return len(pairs) or None
+    except Exception:
+        return None
+
+
 def _cpu_baseline(w, n_patch=32, steps=10):
     """The FP64 oracle, as it is, on a bounded sample: a 32 x 32-element periodic patch
-    of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps."""
+    of the same element type (N = 16, p = 5, upwind) for 10 RK4 steps, timed with the
+    BLAS thread pool at the cores this process may use (the physical cores lscpu reports,
+    capped by the CPU affinity and OMP_NUM_THREADS) and again with one thread."""
     from oracle import dg2d
     from paper_2105_01722_amd import inputs
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_limits
+    phys = _physical_cores()
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cap = [c for c in (phys, avail, int(os.environ.get("OMP_NUM_THREADS", "0")) or None) if c]
+    threads = max(1, min(cap)) if cap else 1
     N, p = w["N"], w["p"]
     prob = dg2d.CartProblem(nx=n_patch, ny=n_patch, N=N, p=p, flux="upwind")
     ops = dg2d.CartOps(prob)
     X, Y = inputs.node_coords(n_patch, n_patch, N)
     U = inputs.fourier_field(w["modes"], X, Y)
     V = np.zeros_like(U)
-    t0 = time.perf_counter()
-    dg2d.run(U, V, ops, w["dt"], steps)
-    dt = time.perf_counter() - t0
-    return {"value": n_patch * n_patch * (N + 1) ** 2 * steps / dt, "unit": "DOF-updates/s",
-            "cores": int(cores), "kind": "oracle",
+    dofs = n_patch * n_patch * (N + 1) ** 2 * steps
+    res = {}
+    for nt in (threads, 1):
+        with threadpool_limits(limits=nt):
+            t0 = time.perf_counter()
+            dg2d.run(U, V, ops, w["dt"], steps)
+            res[nt] = time.perf_counter() - t0
+    return {"value": dofs / res[threads], "unit": "DOF-updates/s", "cores": int(threads),
+            "kind": "oracle",
             "sample": "%dx%d-element periodic patch, N=%d, p=%d, upwind, %d RK4 steps, FP64 "
-                      "(numpy/scipy dense Cholesky element solves)" % (n_patch, n_patch, N, p, steps),
-            "seconds": dt}
+                      "(numpy/scipy dense Cholesky element solves, BLAS threads = cores)"
+                      % (n_patch, n_patch, N, p, steps),
+            "seconds": res[threads], "physical_cores_lscpu": phys, "cpu_affinity": avail,
+            "value_1_thread": dofs / res[1], "seconds_1_thread": res[1]}
 
 
 def main():
@@ -406,10 +440,13 @@ def main():
     print("bench: fp64 %.3f ms/step" % (ms64 / args.steps), file=sys.stderr, flush=True)
     value = ndof * args.steps / (ms64 * 1e-3)
     launches = 4 * args.steps
-    # algorithmic HBM bytes of a step: 12 field accesses per DOF per field (RK4 in the
-    # y / Y / accumulator form of the stage kernels), 2 fields
-    alg_bytes_step = 24 * 8 * ndof
+    # Algorithmic HBM bytes per DOF-update: 32 s (s = 8 B), the three-register classical
+    # RK4 count (16 field accesses per DOF, field and step).  The stage kernels need only
+    # 24 s (the y / Y / accumulator form with 12 accesses), reported beside it.
+    alg_bytes_step = 32 * 8 * ndof
+    kern_bytes_step = 24 * 8 * ndof
     achieved = alg_bytes_step * args.steps / (ms64 * 1e-3)
+    achieved_kern = kern_bytes_step * args.steps / (ms64 * 1e-3)
     out = {
         "metric": "DOF-updates/s per time step + mean PCG iters; FP64 plain vs mixed/learned @ fixed err",
         "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -420,21 +457,35 @@ def main():
                                "8 seeded Fourier modes",
                    "elements": n * n, "N": N, "p": w["p"], "dof_per_field": ndof,
                    "parallelism": "single GPU"},
-        "rel_err_vs_exact": err64,
+        "rel_err_vs_exact": err64["u"], "rel_err_v_vs_exact": err64["v"],
+        "max_rel_err_vs_exact": err64["u_max"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": FDM_STAGE_TRAFFIC,
                      "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
                      "kernel": "k_stage<double,*,17,4,false> (4 stage variants)",
                      "avg_launch_us": ms64 * 1e3 / launches,
-                     "alg_bytes_per_launch": alg_bytes_step / 4},
+                     "alg_bytes_per_launch": alg_bytes_step / 4,
+                     "alg_bytes_per_dof_update": 32 * 8,
+                     "kernel_bytes_per_launch": kern_bytes_step / 4,
+                     "kernel_bytes_per_dof_update": 24 * 8,
+                     "achieved_kernel_bytes": achieved_kern / 1e9,
+                     "frac_kernel_bytes": achieved_kern / HBM_PEAK},
     }
     if not args.no_fp32:
         ms32, err32, _ = _time_gpu(w, "fp32", args.steps, args.warmup)
         print("bench: fp32 %.3f ms/step" % (ms32 / args.steps), file=sys.stderr, flush=True)
+        # FP32 storage of the stage increments around the FP64 register y: 72 B per DOF,
+        # field and step (see the stage kernel), 144 B per DOF-update
         out["fp32"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
-                       "rel_err_vs_exact": err32,
-                       "roofline_frac": 24 * 4 * ndof * args.steps / (ms32 * 1e-3) / HBM_PEAK}
+                       "speedup_vs_fp64": ms64 / ms32,
+                       "rel_err_vs_exact": err32["u"], "rel_err_v_vs_exact": err32["v"],
+                       "max_rel_err_vs_exact": err32["u_max"],
+                       "max_rel_err_v_vs_exact": err32["v_max"],
+                       "bytes_per_dof_update": 144,
+                       "roofline_frac": 144 * ndof * args.steps / (ms32 * 1e-3) / HBM_PEAK,
+                       "note": "stage increments and traces stored in FP32, y accumulated and "
+                               "the right-hand side evaluated in FP64"}
     if not args.no_walls:
         out["walls"] = _time_walls(args.steps, args.warmup)
         out["walls"]["ms_vs_periodic"] = out["walls"]["ms_per_step"] / (ms64 / args.steps)

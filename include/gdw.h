@@ -50,8 +50,11 @@ typedef enum {
 typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1 } gdw_flux;
 
 /* Arithmetic of the time loop.  GDW_FP64: state, tables and arithmetic in FP64.
- * GDW_MIXED_FP32, constant-coefficient path: state and tables stored and computed in FP32;
- * the eigenbasis is built and the energy is accumulated in FP64.  GDW_MIXED_FP32, PCG
+ * GDW_MIXED_FP32, constant-coefficient path: every stage right-hand side (fluxes, lifts,
+ * diagonal solve, traces) is evaluated in FP32 from FP32 stage values and tables; the RK4
+ * stage registers hold FP32 increments Y - y (so their rounding scales with dt |k|, not
+ * |y|) and the step is accumulated into y in FP64; the eigenbasis is built, and the
+ * energy, get_state and the non-finite check read y, in FP64.  GDW_MIXED_FP32, PCG
  * path: the state stays FP64; the element operator is split into FP32 parts
  * hi = fl32(A), lo = fl32(A - hi); the inner PCG iterations use hi, and every solve is
  * refined with FP64 residuals b - (hi + lo) x until the FP64 residual meets pcg_rtol
@@ -87,7 +90,8 @@ typedef struct {
   int solver;          /* gdw_solver                                                          */
   int coeff_variable;  /* 1: c^2 given at the nodes by gdw_set_coeff (PCG path)      Sec. 7.1 */
   int mapped;          /* 1: element node coordinates given by gdw_set_coeff (PCG path)        */
-  double pcg_rtol;     /* PCG stop: ||b - A x||_2 <= pcg_rtol ||b||_2 (<= 0: 1e-12)   Sec. 7.1 */
+  double pcg_rtol;     /* PCG stop: ||r||_2 <= pcg_rtol ||b||_2, r the CG recurrence
+                          residual (r_0 = b - A x_0); <= 0: 1e-12                     Sec. 7.1 */
   int pcg_maxit;       /* PCG iteration limit per element solve (<= 0: 200)                   */
   int bc[4];           /* gdw_bc of the sides x = x0 + Lx (E), x = x0 (W), y = y0 + Ly (N),
                           y = y0 (S); all zero: periodic in x and y                            */
@@ -107,9 +111,9 @@ const char* gdw_last_error(void);
  * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
  * non-positive length, c2 or xi, an unknown enum, solver FDM with a variable
  * coefficient or a mapped mesh, a direction periodic on one side only; EUNSUPPORTED
- * for the PCG path with p > 7 or an element
- * operator that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path
- * in GDW_MIXED_FP32; ENOMEM / EHIP from the device.  Uses the current HIP device;
+ * for the PCG path with p > 7 or an element operator that does not fit the 160 KiB of
+ * LDS of a workgroup, and for the PCG path in GDW_MIXED_FP32 with N + 1 outside
+ * {9, 13, 17}; ENOMEM / EHIP from the device.  Uses the current HIP device;
  * synchronous. */
 gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out);
 

@@ -22,9 +22,13 @@ diagonal of M_J (Psi_2^{-T} Psi_2^{-1} = Mref (x) Mref, the reference mass), whi
 the Jacobian's variation inside the element.  On a Cartesian element with constant c^2,
 P_S = S_hat and P_M = M_J exactly (s = 1; PCG converges in one iteration).
 
-Stopping rule: ||b - A x||_2 <= rtol ||b||_2 (true residual, recomputed each iteration
-from the recurrence), at most maxit iterations; x0 = the previous solution of the
-same element system (warm start), 0 at the first call.  ||b|| = 0 gives x = 0 with 0
+Stopping rule: ||r_k||_2 <= rtol ||b||_2 with r_k the CG recurrence residual
+(r_0 = b - A x_0 computed directly, then r_{k+1} = r_k - alpha_k A d_k), at most maxit
+iterations; x0 = the previous solution of the same element system (warm start), 0 at
+the first call.  The paper does not say which residual it tests; the recurrence one
+costs no extra product, and where it drifts from the true residual b - A x (about
+eps cond(A) ||x|| at rtol near eps) the parity tests bound the result against the dense
+direct solve instead.  ||b|| = 0 gives x = 0 with 0
 iterations.  The S_hat system is solved for the correction y = dU/dt - V (right side
 F_u), the M_J system for dV/dt.
 """

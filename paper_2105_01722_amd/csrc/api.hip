@@ -33,6 +33,7 @@ static void free_all(gdw_ctx* c) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   for (auto& r : c->Y) for (auto& p : r) F(p);
   F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh); F(c->frc); F(c->t_dev);
+  F(c->y64[0]); F(c->y64[1]);
   F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
@@ -148,15 +149,11 @@ static gdw_status upload_as(void** dst, const std::vector<double>& src) {
 
 static gdw_status upload_tables(gdw_ctx* c, const std::vector<double>& gh,
                                 const std::vector<double>& invL, const std::vector<double>& lam) {
+  // FP64 in both storage modes (the stage arithmetic is FP64)
   gdw_status s;
-  if (c->elem_bytes == 8) {
-    if ((s = upload_as<double>(&c->gh, gh)) != GDW_OK) return s;
-    if ((s = upload_as<double>(&c->invL, invL)) != GDW_OK) return s;
-    return upload_as<double>(&c->lam, lam);
-  }
-  if ((s = upload_as<float>(&c->gh, gh)) != GDW_OK) return s;
-  if ((s = upload_as<float>(&c->invL, invL)) != GDW_OK) return s;
-  return upload_as<float>(&c->lam, lam);
+  if ((s = upload_as<double>(&c->gh, gh)) != GDW_OK) return s;
+  if ((s = upload_as<double>(&c->invL, invL)) != GDW_OK) return s;
+  return upload_as<double>(&c->lam, lam);
 }
 
 static gdw_status create_fdm(const gdw_desc* d, gdw_ctx* c) {
@@ -208,10 +205,16 @@ static gdw_status create_fdm(const gdw_desc* d, gdw_ctx* c) {
   if ((s = upload_as<double>((void**)&c->Py, Py)) != GDW_OK) return s;
 
   const size_t field = (size_t)c->nel * nn * c->elem_bytes;
-  for (auto& r : c->Y)
-    for (auto& ptr : r) {
+  for (int r = 0; r < 3; ++r)
+    for (auto& ptr : c->Y[r]) {
+      if (r == 0 && c->elem_bytes == 4) continue;   // FP32 storage: y is y64
       GDW_HIP(hipMalloc(&ptr, field));
       GDW_HIP(hipMemset(ptr, 0, field));
+    }
+  if (c->elem_bytes == 4)
+    for (auto& ptr : c->y64) {
+      GDW_HIP(hipMalloc(&ptr, (size_t)c->nel * nn * sizeof(double)));
+      GDW_HIP(hipMemset(ptr, 0, (size_t)c->nel * nn * sizeof(double)));
     }
   const size_t trb = (size_t)c->nel * 8 * n1 * c->elem_bytes;
   for (auto& t : c->tr) {
@@ -466,11 +469,13 @@ extern "C" gdw_status gdw_set_coeff(gdw_ctx* c, const double* c2, const double* 
 template <typename T>
 static hipError_t set_state_t(gdw_ctx* c, const double* U, const double* V, hipStream_t st) {
   hipError_t e;
-  if ((e = launch_to_modal<T>(U, (T*)c->Y[0][0], c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
-  if ((e = launch_to_modal<T>(V, (T*)c->Y[0][1], c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
+  // FP64 storage: y = Y[0]; FP32 storage: y is the FP64 register y64 (traces in FP32)
+  double* yu = sizeof(T) == 8 ? (double*)c->Y[0][0] : c->y64[0];
+  double* yv = sizeof(T) == 8 ? (double*)c->Y[0][1] : c->y64[1];
+  if ((e = launch_to_modal<double>(U, yu, c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
+  if ((e = launch_to_modal<double>(V, yv, c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
   c->trc = 0;
-  return launch_traces<T>((const T*)c->Y[0][0], (const T*)c->Y[0][1], (const T*)c->gh,
-                          (T*)c->tr[0], c->n1, c->nel, st);
+  return launch_traces<double, T>(yu, yv, (const double*)c->gh, (T*)c->tr[0], c->n1, c->nel, st);
 }
 
 extern "C" gdw_status gdw_set_state(gdw_ctx* c, const double* U, const double* V, void* stream) {
@@ -609,20 +614,22 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.nx = c->d.nx;
   a.ny = c->d.ny;
   a.n1 = c->n1;
-  a.dt = (T)dt;
-  a.c2 = (T)c->d.c2;
-  a.alpha = (T)c->alpha;
-  a.beta = (T)c->beta;
-  a.tau = (T)c->tau;
-  a.invL = (const T*)c->invL;
-  a.lam = (const T*)c->lam;
-  a.gh = (const T*)c->gh;
+  a.dt = dt;
+  a.c2 = c->d.c2;
+  a.alpha = c->alpha;
+  a.beta = c->beta;
+  a.tau = c->tau;
+  a.invL = (const double*)c->invL;
+  a.lam = (const double*)c->lam;
+  a.gh = (const double*)c->gh;
   a.bcbits = 0;
   for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
   a.nf = c->nf;
   a.frc = (const T*)c->frc;
   a.frc_stride = c->nel * (long)c->n1 * c->n1;
   a.fw = c->t_dev ? c->t_dev + 1 : nullptr;
+  a.y64_u = c->y64[0];
+  a.y64_v = c->y64[1];
   stage_roles(c, stage, a);
   return a;
 }
@@ -752,8 +759,8 @@ extern "C" gdw_status gdw_get_state(gdw_ctx* c, double* U, double* V, void* stre
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
   } else {
-    GDW_HIP(launch_to_nodal<float>((const float*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
-    GDW_HIP(launch_to_nodal<float>((const float*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
+    GDW_HIP(launch_to_nodal<double>(c->y64[0], U, c->Psx, c->Psy, c->n1, c->nel, st));
+    GDW_HIP(launch_to_nodal<double>(c->y64[1], V, c->Psx, c->Psy, c->n1, c->nel, st));
   }
   return GDW_OK;
 }
@@ -768,14 +775,11 @@ extern "C" gdw_status gdw_energy(gdw_ctx* c, double* E_host, void* stream) {
                               c->nel, c->epart, (int)c->nel, out, st));
   } else {
     out = c->epart + c->npart;
-    if (c->elem_bytes == 8)
-      GDW_HIP(launch_energy<double>((const double*)c->Y[0][0], (const double*)c->Y[0][1],
-                                    (const double*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
-                                    c->npart, out, st));
-    else
-      GDW_HIP(launch_energy<float>((const float*)c->Y[0][0], (const float*)c->Y[0][1],
-                                   (const float*)c->lam, c->d.c2, c->n1, c->nel, c->epart,
-                                   c->npart, out, st));
+    const bool f64 = c->elem_bytes == 8;
+    GDW_HIP(launch_energy<double>(f64 ? (const double*)c->Y[0][0] : c->y64[0],
+                                  f64 ? (const double*)c->Y[0][1] : c->y64[1],
+                                  (const double*)c->lam, c->d.c2,
+                                  c->n1, c->nel, c->epart, c->npart, out, st));
   }
   GDW_HIP(hipMemcpyAsync(E_host, out, sizeof(double), hipMemcpyDeviceToHost, st));
   GDW_HIP(hipStreamSynchronize(st));
@@ -796,10 +800,9 @@ extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
   const long n = c->nel * (long)c->n1 * c->n1;
   GDW_HIP(hipMemsetAsync(c->nonfinite, 0, sizeof(unsigned int), st));
   for (int f = 0; f < 2; ++f) {
-    if (c->solver == GDW_SOLVE_PCG || c->elem_bytes == 8)
-      GDW_HIP(launch_count_nonfinite<double>((const double*)c->Y[0][f], n, c->nonfinite, st));
-    else
-      GDW_HIP(launch_count_nonfinite<float>((const float*)c->Y[0][f], n, c->nonfinite, st));
+    const double* y = (c->solver == GDW_SOLVE_PCG || c->elem_bytes == 8) ? (const double*)c->Y[0][f]
+                                                                          : c->y64[f];
+    GDW_HIP(launch_count_nonfinite<double>(y, n, c->nonfinite, st));
   }
   unsigned int cnt = 0;
   GDW_HIP(hipMemcpyAsync(&cnt, c->nonfinite, sizeof(unsigned int), hipMemcpyDeviceToHost, st));

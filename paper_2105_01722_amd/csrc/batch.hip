@@ -200,7 +200,7 @@ static gdw_status tune_fdm(gdw_batch* b, FdmClass& c, const std::vector<double>&
   unsigned best_grid = 0;
   char buf[160];
   for (int epb : {1, 2, 4, 8}) {
-    if (stage_lds_bytes(c.elem_bytes, c.n1, epb) > 65536) continue;
+    if (stage_lds_bytes(c.n1, epb) > 65536) continue;
     c.epb = epb;
     gdw_status s;
     if ((s = upload_fdm_tiles(c, b->ctx)) != GDW_OK) return s;

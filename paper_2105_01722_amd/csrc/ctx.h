@@ -32,6 +32,7 @@ struct gdw_ctx {
   // device buffers (time-loop type T)
   void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void* tr[2] = {nullptr, nullptr};
+  double* y64[2] = {nullptr, nullptr};   // FP32 arithmetic: the FP64 accumulation register y
   void* invL = nullptr;
   void* lam = nullptr;
   void* gh = nullptr;

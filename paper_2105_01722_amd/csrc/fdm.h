@@ -5,26 +5,29 @@
 
 namespace gdw {
 
-// Arguments of one fused RK stage (see fdm.hip for the stage-by-stage roles).
+// Arguments of one fused RK stage (see fdm.hip for the stage-by-stage roles).  T is the
+// storage type of the stage registers and traces; the arithmetic is FP64 in both modes.
 template <typename T>
 struct StageArgs {
-  const T* in_u;       // stage input, modal
+  const T* in_u;       // stage input, modal (FP32 storage: the stage increment)
   const T* in_v;
   const T* aux_u;      // y (stages 2, 3) or the accumulator (stage 4); unused in stage 1
   const T* aux_v;
   T* out_u;            // new stage value (may alias in_u for stages 2, 3)
   T* out_v;
-  T* acc_u;            // stage 2 only: accumulator Yin + 2 Ynew - y
+  T* acc_u;            // stage 2 only: accumulator Yin + 2 Ynew - y (FP32: dY2 + 2 dY3)
   T* acc_v;
+  double* y64_u;       // FP32 storage only: the FP64 register y, read by every stage and
+  double* y64_v;       // written by stage 4 (in, aux and out then hold FP32 increments)
   const T* tr_in;      // modal traces of the stage input, [nel][8][n1]
   T* tr_out;           // modal traces of the new stage value
-  const T* invL;       // [n1*n1]: 1 / (lambda_x + lambda_y), entry (0,0) = 1
-  const T* lam;        // [n1*n1]: lambda_x + lambda_y
-  const T* gh;         // [8][n1]: gE hE gW hW gN hN gS hS
+  const double* invL;  // [n1*n1]: 1 / (lambda_x + lambda_y), entry (0,0) = 1
+  const double* lam;   // [n1*n1]: lambda_x + lambda_y
+  const double* gh;    // [8][n1]: gE hE gW hW gN hN gS hS
   long nel;
   int nx, ny, n1;
   int bcbits;          // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
-  T dt, c2, alpha, beta, tau;
+  double dt, c2, alpha, beta, tau;
   // source term: nf terms (0..4), modal g_k at frc + k * frc_stride; the weights
   // fw[4 (stage - 1) + k] = sin(omega_k t_stage + phase_k) of the current step sit in
   // device memory (written by launch_source_step before the step's stages)
@@ -42,13 +45,14 @@ hipError_t launch_to_modal(const double* U, T* Ub, const double* Px, const doubl
 template <typename T>
 hipError_t launch_to_nodal(const T* Ub, double* U, const double* Psx, const double* Psy, int n1,
                            long nel, hipStream_t st);
-template <typename T>
-hipError_t launch_traces(const T* Ub, const T* Vb, const T* gh, T* tr, int n1, long nel,
+// Traces (type T) of a modal state (type S).
+template <typename S, typename T>
+hipError_t launch_traces(const S* Ub, const S* Vb, const double* gh, T* tr, int n1, long nel,
                          hipStream_t st);
 template <typename T>
 hipError_t launch_stage(int stage, const StageArgs<T>& a, hipStream_t st);
 template <typename T>
-hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int n1, long nel,
+hipError_t launch_energy(const T* Ub, const T* Vb, const double* lam, double c2, int n1, long nel,
                          double* part, int npart, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStream_t st);
@@ -59,7 +63,8 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
 template <typename T>
 hipError_t launch_stage_group(int stage, int n1, int epb, const StageArgs<T>* args,
                               const long* tile_start, int nprob, unsigned grid, hipStream_t st);
-size_t stage_lds_bytes(int elem_bytes, int n1, int epb);
+// LDS of one stage workgroup (FP64 arithmetic in both storage modes).
+size_t stage_lds_bytes(int n1, int epb);
 // Resident blocks per CU of the grouped stage kernel (LDS and thread limits).
 template <typename T>
 int stage_group_occupancy(int stage, int n1, int epb);

@@ -305,23 +305,23 @@ __global__ void k_to_nodal(const T* __restrict__ Ub, double* __restrict__ U,
 // Modal face traces of a state (used once after set_state; every stage kernel
 // writes the traces of its output itself).
 // ---------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_traces(const T* __restrict__ Ub, const T* __restrict__ Vb,
-                         const T* __restrict__ gh, T* __restrict__ tr, int n1, long nel) {
+template <typename S, typename T>
+__global__ void k_traces(const S* __restrict__ Ub, const S* __restrict__ Vb,
+                         const double* __restrict__ gh, T* __restrict__ tr, int n1, long nel) {
   const int nn = n1 * n1;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nel * 8 * n1) return;
   const long e = i / (8 * n1);
   const int r = (int)(i - e * 8 * n1);
   const int f2 = r / n1, j = r - f2 * n1;
-  const T* F = ((f2 & 1) ? Vb : Ub) + e * nn;
-  const T* g = gh + f2 * n1;
-  T acc = 0;
+  const S* F = ((f2 & 1) ? Vb : Ub) + e * nn;
+  const double* g = gh + f2 * n1;
+  double acc = 0;
   if (f2 < 4)
-    for (int k = 0; k < n1; ++k) acc += g[k] * F[j * n1 + k];
+    for (int k = 0; k < n1; ++k) acc += g[k] * (double)F[j * n1 + k];
   else
-    for (int k = 0; k < n1; ++k) acc += g[k] * F[k * n1 + j];
-  tr[i] = acc;
+    for (int k = 0; k < n1; ++k) acc += g[k] * (double)F[k * n1 + j];
+  tr[i] = (T)acc;
 }
 
 // sum_k g[k] F[j][k] (contraction along kx) and sum_k g[k] F[k][j] (along ky)
@@ -351,6 +351,7 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 
 // ---------------------------------------------------------------------------------
 // The fused RK stage.
+// FP64 (T = double):
 //   STAGE 1: in = y;      out = Y  <- y + dt/2 k1
 //   STAGE 2: in = Y, y;   out = Y  <- y + dt/2 k2 (in place),  Tacc <- Yin + 2 Ynew - y
 //   STAGE 3: in = Y, y;   out = Y  <- y + dt k3 (in place)
@@ -359,6 +360,26 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 // Y3 = y + dt/2 k2, Y4 = y + dt k3, because
 // (Y2 + 2 Y3 + Y4 - y)/3 = y + dt/6 k1 + dt/3 k2 + dt/3 k3.  12 field accesses per
 // DOF per step instead of the 16 of the textbook three-register form.
+//
+// FP32 storage (T = float): the same scheme in increments.  y lives in FP64 (y64); the
+// stage registers hold FP32 increments dY_s = Y_s - y and A = dY2 + 2 dY3, so their
+// rounding scales with dt |k| instead of |y|, and y accumulates the step in FP64:
+//   STAGE 1: in = y64;           out = dY2 <- dt/2 k(y)
+//   STAGE 2: in = dY2, y64;      out = dY3 <- dt/2 k(y + dY2) (in place), A <- dY2 + 2 dY3
+//   STAGE 3: in = dY3, y64;      out = dY4 <- dt k(y + dY3) (in place)
+//   STAGE 4: in = dY4, A, y64;   y64 <- y + (A + dY4)/3 + dt/6 k(y + dY4)
+// (y_{n+1} = y + (dY2 + 2 dY3 + dY4)/3 + dt/6 k4 is the form above with Y_s = y + dY_s.)
+// The right-hand side stays FP64 arithmetic: in the modal v-equation,
+// dVbar/dt = c^2 (lifts - Lambda Ubar) cancels terms of size Lambda |Ubar| down to about
+// omega^2 |Ubar| (the lifts carry the boundary terms of the high modes).  A variant that
+// evaluated it in FP32 from an FP32 copy of y measured, after 100 steps of the
+// 256 x 256, N = 16 workload, 2e-7 relative l2 and 1.0e-6 relative max error in v (u:
+// 8e-10); the kernel is bound by HBM bandwidth, so the FP64 arithmetic costs nothing.
+// Traces are stored in FP32.
+// Bytes per DOF, field and step:
+//   stage 1: y r (8 B), dY w (4)     stage 2: y, dY r, dY, A w (20)
+//   stage 3: y, dY r, dY w (16)      stage 4: y, dY, A r, y w (24)
+// = 72 B against 96 B in FP64.
 // ---------------------------------------------------------------------------------
 // Thread map: one workgroup of (N+1)^2 threads handles EPB consecutive elements;
 // thread t owns the modal index (kx, ky) = (t mod (N+1), t div (N+1)) in every one of
@@ -368,10 +389,9 @@ __device__ inline T dot_col(const T* g, const T* F, int j, int n1) {
 // offset.
 // One tile (EPB consecutive elements, tile index `tile`) of one problem.
 // Streaming access to the per-element state.  Each state word is read once and
-// written once per stage, so in FP64 the loads and stores bypass the cache
-// hierarchy's normal allocation (nontemporal): measured at the 256x256, N = 16
-// workload this saves about 3% per stage.  FP32 tiles are half as large and run
-// faster with ordinary accesses, so they keep them.
+// written once per stage, so FP64 words bypass the cache hierarchy's normal
+// allocation (nontemporal): measured at the 256x256, N = 16 workload this saves about
+// 3% per stage.  FP32 words are half as large and run faster with ordinary accesses.
 template <typename T>
 __device__ __forceinline__ T ld_state(const T* p) {
   if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
@@ -387,14 +407,17 @@ __device__ __forceinline__ void st_state(T* p, T v) {
 // if it did not exist.
 template <typename T, int STAGE, int N1C, int EPB, bool FRC = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
+  // FP32 storage runs the increment form around the FP64 register y
+  constexpr bool MIX = sizeof(T) == 4;
+  using R = double;                              // arithmetic
   const int n1 = N1C > 0 ? N1C : a.n1;
   const int nn = n1 * n1;
   const int tid = threadIdx.x;                   // blockDim.x == nn
   const int ky = tid / n1, kx = tid - ky * n1;
   extern __shared__ unsigned char smem_raw[];
-  T* sgh = reinterpret_cast<T*>(smem_raw);       // [8][n1] face tables
-  T* sig = sgh + 8 * n1;                         // [EPB][8][n1] modal face fluxes
-  T* snew = sig + EPB * 8 * n1;                  // [EPB][2][nn] new stage values
+  R* sgh = reinterpret_cast<R*>(smem_raw);       // [8][n1] face tables
+  R* sig = sgh + 8 * n1;                         // [EPB][8][n1] modal face fluxes
+  R* snew = sig + EPB * 8 * n1;                  // [EPB][2][nn] new stage values
   const long e0 = tile * EPB;
   const int ne = (int)min((long)EPB, a.nel - e0);
 
@@ -402,30 +425,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   // overlaps the trace loads and the flux computation.  An element's state is read
   // and written only by this workgroup, so loading it all before the (in-place)
   // stores is safe.
+  // FP64 storage: ru = in, xu = aux.  FP32 storage: yu = y, ru = the stage increment
+  // (stages 2-4), xu = A (stage 4).
+  // (loaded values stay in their storage type until use: fewer registers in FP32)
   T ru[EPB], rv[EPB], xu[EPB], xv[EPB];
+  R yu[EPB], yv[EPB];
 #pragma unroll
   for (int l = 0; l < EPB; ++l) {
     ru[l] = rv[l] = xu[l] = xv[l] = T(0);
+    yu[l] = yv[l] = R(0);
     if (l < ne) {
       const long g = (e0 + l) * nn + tid;
-      ru[l] = ld_state(&a.in_u[g]);
-      rv[l] = ld_state(&a.in_v[g]);
-      if (STAGE > 1) {
-        xu[l] = ld_state(&a.aux_u[g]);
-        xv[l] = ld_state(&a.aux_v[g]);
+      if constexpr (MIX) {
+        yu[l] = ld_state(&a.y64_u[g]);
+        yv[l] = ld_state(&a.y64_v[g]);
+        if (STAGE > 1) {
+          ru[l] = ld_state(&a.in_u[g]);
+          rv[l] = ld_state(&a.in_v[g]);
+        }
+        if (STAGE == 4) {
+          xu[l] = ld_state(&a.aux_u[g]);
+          xv[l] = ld_state(&a.aux_v[g]);
+        }
+      } else {
+        ru[l] = ld_state(&a.in_u[g]);
+        rv[l] = ld_state(&a.in_v[g]);
+        if (STAGE > 1) {
+          xu[l] = ld_state(&a.aux_u[g]);
+          xv[l] = ld_state(&a.aux_v[g]);
+        }
       }
     }
   }
-  const T il = a.invL[tid], lm = a.lam[tid];
-  const T gEk = a.gh[0 * n1 + kx], hEk = a.gh[1 * n1 + kx];
-  const T gWk = a.gh[2 * n1 + kx], hWk = a.gh[3 * n1 + kx];
-  const T gNk = a.gh[4 * n1 + ky], hNk = a.gh[5 * n1 + ky];
-  const T gSk = a.gh[6 * n1 + ky], hSk = a.gh[7 * n1 + ky];
+  const R il = a.invL[tid], lm = a.lam[tid];
+  const R gEk = a.gh[0 * n1 + kx], hEk = a.gh[1 * n1 + kx];
+  const R gWk = a.gh[2 * n1 + kx], hWk = a.gh[3 * n1 + kx];
+  const R gNk = a.gh[4 * n1 + ky], hNk = a.gh[5 * n1 + ky];
+  const R gSk = a.gh[6 * n1 + ky], hSk = a.gh[7 * n1 + ky];
   for (int i = tid; i < 8 * n1; i += blockDim.x) sgh[i] = a.gh[i];
 
   // Phase A: modal face fluxes sigma_u = (1-alpha)(v_nb - v) - beta (a + a_nb),
   // sigma_v = (1-alpha) a - alpha a_nb + tau (v_nb - v)  (Sec. 2.2.1)
-  const T alpha = a.alpha, beta = a.beta, tau = a.tau;
+  const R alpha = a.alpha, beta = a.beta, tau = a.tau;
   for (int i = tid; i < ne * 4 * n1; i += blockDim.x) {
     const int el = i / (4 * n1);
     const int r = i - el * 4 * n1;
@@ -446,58 +487,84 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     wall = wall && kf != 0;
     const T* ts = a.tr_in + e * 8 * n1 + 2 * f * n1;
     const T* tn = wall ? ts : a.tr_in + enb * 8 * n1 + 2 * fnb * n1;
-    const T as = ts[j], vs = ts[n1 + j];
-    T an = tn[j], vn = tn[n1 + j];
+    const R as = ts[j], vs = ts[n1 + j];
+    R an = tn[j], vn = tn[n1 + j];
     if (wall && kf == 1) {
       an = -an;
       vn = -vn;
     }
-    const T jv = vn - vs;
-    sig[(el * 8 + 2 * f) * n1 + j] = (T(1) - alpha) * jv - beta * (as + an);
-    sig[(el * 8 + 2 * f + 1) * n1 + j] = (T(1) - alpha) * as - alpha * an + tau * jv;
+    const R jv = vn - vs;
+    sig[(el * 8 + 2 * f) * n1 + j] = (R(1) - alpha) * jv - beta * (as + an);
+    sig[(el * 8 + 2 * f + 1) * n1 + j] = (R(1) - alpha) * as - alpha * an + tau * jv;
   }
   __syncthreads();
 
   // Phase B: modal right-hand side and the RK stage update
-  const T dt = a.dt, c2 = a.c2;
+  const R dt = a.dt, c2 = a.c2;
 #pragma unroll
   for (int l = 0; l < EPB; ++l) {
     if (l >= ne) break;
-    const T* s = sig + l * 8 * n1;
-    const T ub = ru[l], vb = rv[l], yu = xu[l], yv = xv[l];
-    const T Lu = gEk * s[0 * n1 + ky] + gWk * s[2 * n1 + ky] + gNk * s[4 * n1 + kx] +
+    const R* s = sig + l * 8 * n1;
+    // the stage value the right-hand side is evaluated at
+    R ub = (R)ru[l], vb = (R)rv[l];
+    if constexpr (MIX) {
+      ub = STAGE == 1 ? yu[l] : yu[l] + (R)ru[l];
+      vb = STAGE == 1 ? yv[l] : yv[l] + (R)rv[l];
+    }
+    const R Lu = gEk * s[0 * n1 + ky] + gWk * s[2 * n1 + ky] + gNk * s[4 * n1 + kx] +
                  gSk * s[6 * n1 + kx];
-    const T Lv = hEk * s[1 * n1 + ky] + hWk * s[3 * n1 + ky] + hNk * s[5 * n1 + kx] +
+    const R Lv = hEk * s[1 * n1 + ky] + hWk * s[3 * n1 + ky] + hNk * s[5 * n1 + kx] +
                  hSk * s[7 * n1 + kx];
-    const T ku = vb + il * Lu;
-    T kv = c2 * (Lv - lm * ub);
+    const R ku = vb + il * Lu;
+    R kv = c2 * (Lv - lm * ub);
     const long g = (e0 + l) * nn + tid;
     if constexpr (FRC) {
       // + sum_k s_k(t) Psi^T M g_k: the modal coefficients of the interpolated g_k
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (k < a.nf) kv += (T)a.fw[4 * (STAGE - 1) + k] * a.frc[k * a.frc_stride + g];
+        if (k < a.nf) kv += a.fw[4 * (STAGE - 1) + k] * (R)a.frc[k * a.frc_stride + g];
     }
-    T nu, nv;
-    if (STAGE == 1) {          // the input is y itself
-      nu = ub + T(0.5) * dt * ku;
-      nv = vb + T(0.5) * dt * kv;
-    } else if (STAGE == 2) {   // yu, yv = y
-      nu = yu + T(0.5) * dt * ku;
-      nv = yv + T(0.5) * dt * kv;
-      st_state(&a.acc_u[g], ub + T(2) * nu - yu);
-      st_state(&a.acc_v[g], vb + T(2) * nv - yv);
-    } else if (STAGE == 3) {   // yu, yv = y
-      nu = yu + dt * ku;
-      nv = yv + dt * kv;
-    } else {                   // yu, yv = accumulator
-      nu = (yu + ub) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * ku;
-      nv = (yv + vb) * T(1.0 / 3.0) + dt * T(1.0 / 6.0) * kv;
+    R su, sv;     // the new stage value (its traces go to the next stage)
+    if constexpr (MIX) {
+      if (STAGE == 4) {          // ru = dY4, xu = A
+        const R h6 = dt * (1.0 / 6.0);
+        su = yu[l] + ((R)xu[l] + (R)ru[l]) * (1.0 / 3.0) + h6 * ku;
+        sv = yv[l] + ((R)xv[l] + (R)rv[l]) * (1.0 / 3.0) + h6 * kv;
+        st_state(&a.y64_u[g], su);
+        st_state(&a.y64_v[g], sv);
+      } else {
+        const R w = STAGE == 3 ? dt : R(0.5) * dt;
+        const T nu = (T)(w * ku), nv = (T)(w * kv);     // the stored increment
+        st_state(&a.out_u[g], nu);
+        st_state(&a.out_v[g], nv);
+        if (STAGE == 2) {        // ru = dY2
+          st_state(&a.acc_u[g], (T)((R)ru[l] + R(2) * (R)nu));
+          st_state(&a.acc_v[g], (T)((R)rv[l] + R(2) * (R)nv));
+        }
+        su = yu[l] + (R)nu;
+        sv = yv[l] + (R)nv;
+      }
+    } else {
+      if (STAGE == 1) {          // the input is y itself
+        su = ub + R(0.5) * dt * ku;
+        sv = vb + R(0.5) * dt * kv;
+      } else if (STAGE == 2) {   // xu, xv = y
+        su = xu[l] + R(0.5) * dt * ku;
+        sv = xv[l] + R(0.5) * dt * kv;
+        st_state(&a.acc_u[g], (T)(ub + R(2) * su - xu[l]));
+        st_state(&a.acc_v[g], (T)(vb + R(2) * sv - xv[l]));
+      } else if (STAGE == 3) {   // xu, xv = y
+        su = xu[l] + dt * ku;
+        sv = xv[l] + dt * kv;
+      } else {                   // xu, xv = accumulator
+        su = (xu[l] + ub) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * ku;
+        sv = (xv[l] + vb) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * kv;
+      }
+      st_state(&a.out_u[g], (T)su);
+      st_state(&a.out_v[g], (T)sv);
     }
-    st_state(&a.out_u[g], nu);
-    st_state(&a.out_v[g], nv);
-    snew[(l * 2) * nn + tid] = nu;
-    snew[(l * 2 + 1) * nn + tid] = nv;
+    snew[(l * 2) * nn + tid] = su;
+    snew[(l * 2 + 1) * nn + tid] = sv;
   }
   __syncthreads();
 
@@ -506,10 +573,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
     const int el = i / (8 * n1);
     const int r = i - el * 8 * n1;
     const int f2 = r / n1, j = r - f2 * n1;
-    const T* F = snew + (el * 2 + (f2 & 1)) * nn;
-    const T* gg = sgh + f2 * n1;
+    const R* F = snew + (el * 2 + (f2 & 1)) * nn;
+    const R* gg = sgh + f2 * n1;
     a.tr_out[e0 * 8 * n1 + i] =
-        (f2 < 4) ? dot_row<T, N1C>(gg, F, j, n1) : dot_col<T, N1C>(gg, F, j, n1);
+        (T)((f2 < 4) ? dot_row<R, N1C>(gg, F, j, n1) : dot_col<R, N1C>(gg, F, j, n1));
   }
 }
 
@@ -544,7 +611,7 @@ __global__ __launch_bounds__(1024) void k_stage_group(const StageArgs<T>* __rest
 template <typename T>
 __global__ __launch_bounds__(256) void k_energy_partial(const T* __restrict__ Ub,
                                                         const T* __restrict__ Vb,
-                                                        const T* __restrict__ lam, double c2,
+                                                        const double* __restrict__ lam, double c2,
                                                         int nn, long total,
                                                         double* __restrict__ part) {
   __shared__ double red[256];
@@ -553,7 +620,7 @@ __global__ __launch_bounds__(256) void k_energy_partial(const T* __restrict__ Ub
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const int idx = (int)(i % nn);
     const double u = (double)Ub[i], v = (double)Vb[i];
-    s += v * v + c2 * (double)lam[idx] * u * u;
+    s += v * v + c2 * lam[idx] * u * u;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -615,20 +682,20 @@ hipError_t launch_to_nodal(const T* Ub, double* U, const double* Psx, const doub
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_traces(const T* Ub, const T* Vb, const T* gh, T* tr, int n1, long nel,
+template <typename S, typename T>
+hipError_t launch_traces(const S* Ub, const S* Vb, const double* gh, T* tr, int n1, long nel,
                          hipStream_t st) {
   const long total = nel * 8 * n1;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_traces<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Ub, Vb,
-                     gh, tr, n1, nel);
+  hipLaunchKernelGGL((k_traces<S, T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Ub,
+                     Vb, gh, tr, n1, nel);
   return hipGetLastError();
 }
 
 template <typename T, int STAGE, int N1C, int EPB>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   const int n1 = a.n1;
-  const size_t sh = (size_t)(8 * n1 + EPB * 8 * n1 + EPB * 2 * n1 * n1) * sizeof(T);
+  const size_t sh = stage_lds_bytes(n1, EPB);
   const unsigned nblk = (unsigned)((a.nel + EPB - 1) / EPB);
   if (a.nf > 0)
     hipLaunchKernelGGL((k_stage<T, STAGE, N1C, EPB, true>), dim3(nblk), dim3(n1 * n1), sh, st, a);
@@ -641,9 +708,7 @@ static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
 // 1 % slower than 4 on the 256 x 256, N = 16 workload).
 template <typename T, int STAGE, int N1C>
 static hipError_t dispatch_epb(const StageArgs<T>& a, hipStream_t st) {
-  auto bytes = [&](int epb) {
-    return (size_t)(8 * a.n1 + epb * 8 * a.n1 + epb * 2 * a.n1 * a.n1) * sizeof(T);
-  };
+  auto bytes = [&](int epb) { return stage_lds_bytes(a.n1, epb); };
   if (a.n1 * a.n1 > 1024) return hipErrorInvalidValue;
   constexpr int E0 = 4;
   if (bytes(E0) <= 65536) return launch_stage_t<T, STAGE, N1C, E0>(a, st);
@@ -673,14 +738,14 @@ hipError_t launch_stage(int stage, const StageArgs<T>& a, hipStream_t st) {
   }
 }
 
-size_t stage_lds_bytes(int elem_bytes, int n1, int epb) {
-  return (size_t)(8 * n1 + epb * 8 * n1 + epb * 2 * n1 * n1) * elem_bytes;
+size_t stage_lds_bytes(int n1, int epb) {
+  return (size_t)(8 * n1 + epb * 8 * n1 + epb * 2 * n1 * n1) * sizeof(double);
 }
 
 template <typename T, int STAGE, int N1C, int EPB>
 static hipError_t launch_group_t(const StageArgs<T>* args, const long* tile_start, int nprob,
                                  int n1, unsigned grid, hipStream_t st) {
-  const size_t sh = stage_lds_bytes(sizeof(T), n1, EPB);
+  const size_t sh = stage_lds_bytes(n1, EPB);
   hipLaunchKernelGGL((k_stage_group<T, STAGE, N1C, EPB>), dim3(grid), dim3(n1 * n1), sh, st, args,
                      tile_start, nprob);
   return hipGetLastError();
@@ -713,7 +778,7 @@ template <typename T>
 hipError_t launch_stage_group(int stage, int n1, int epb, const StageArgs<T>* args,
                               const long* tile_start, int nprob, unsigned grid, hipStream_t st) {
   if (nprob <= 0 || grid == 0) return hipSuccess;
-  if (n1 * n1 > 1024 || stage_lds_bytes(sizeof(T), n1, epb) > 65536) return hipErrorInvalidValue;
+  if (n1 * n1 > 1024 || stage_lds_bytes(n1, epb) > 65536) return hipErrorInvalidValue;
   switch (stage) {
     case 1: return group_n1<T, 1>(epb, args, tile_start, nprob, n1, grid, st);
     case 2: return group_n1<T, 2>(epb, args, tile_start, nprob, n1, grid, st);
@@ -726,7 +791,7 @@ template <typename T>
 int stage_group_occupancy(int stage, int n1, int epb) {
   (void)stage;
   // blocks per CU allowed by LDS (64 KiB per block at most, 160 KiB per CU) and threads
-  const size_t lds = stage_lds_bytes(sizeof(T), n1, epb);
+  const size_t lds = stage_lds_bytes(n1, epb);
   int by_lds = (int)((160 * 1024) / (lds ? lds : 1));
   int by_thr = 2048 / (((n1 * n1 + 63) / 64) * 64);
   int b = by_lds < by_thr ? by_lds : by_thr;
@@ -734,7 +799,7 @@ int stage_group_occupancy(int stage, int n1, int epb) {
 }
 
 template <typename T>
-hipError_t launch_energy(const T* Ub, const T* Vb, const T* lam, double c2, int n1, long nel,
+hipError_t launch_energy(const T* Ub, const T* Vb, const double* lam, double c2, int n1, long nel,
                          double* part, int npart, double* out, hipStream_t st) {
   const long total = nel * (long)n1 * n1;
   hipLaunchKernelGGL(k_energy_partial<T>, dim3(npart), dim3(256), 0, st, Ub, Vb, lam, c2, n1 * n1,
@@ -757,9 +822,9 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
                                          long, hipStream_t);                                     \
   template hipError_t launch_to_nodal<T>(const T*, double*, const double*, const double*, int,    \
                                          long, hipStream_t);                                     \
-  template hipError_t launch_traces<T>(const T*, const T*, const T*, T*, int, long, hipStream_t); \
   template hipError_t launch_stage<T>(int, const StageArgs<T>&, hipStream_t);                    \
-  template hipError_t launch_energy<T>(const T*, const T*, const T*, double, int, long, double*,  \
+  template hipError_t launch_energy<T>(const T*, const T*, const double*, double, int, long,       \
+                                       double*,                                                  \
                                        int, double*, hipStream_t);                               \
   template hipError_t launch_count_nonfinite<T>(const T*, long, unsigned int*, hipStream_t);       \
   template hipError_t launch_stage_group<T>(int, int, int, const StageArgs<T>*, const long*, int, \
@@ -768,5 +833,9 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
 
 GDW_INST(double)
 GDW_INST(float)
+template hipError_t launch_traces<double, double>(const double*, const double*, const double*,
+                                                  double*, int, long, hipStream_t);
+template hipError_t launch_traces<double, float>(const double*, const double*, const double*,
+                                                 float*, int, long, hipStream_t);
 
 }  // namespace gdw

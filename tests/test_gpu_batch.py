@@ -22,8 +22,7 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+from _cmp import assert_close, rel as _rel  # noqa: E402
 
 
 PROBLEMS = [
@@ -125,7 +124,8 @@ def test_batch_equals_solo_runs_and_rebuilds_on_new_dt():
         if kw.get("solver") == "pcg":
             eu, ev = _rel(Ub, U), _rel(Vb, V)
             _say("  problem %d (pcg): rel U %.2e V %.2e" % (i, eu, ev))
-            assert eu <= 1e-12 and ev <= 1e-12
+            assert_close(Ub, U, 1e-12)
+            assert_close(Vb, V, 1e-12)
         else:
             _say("  problem %d (fdm %s): max |diff| U %.2e V %.2e"
                  % (i, kw["precision"], np.abs(Ub - U).max(), np.abs(Vb - V).max()))
@@ -150,4 +150,5 @@ def test_batch_pcg_member_matches_oracle():
     Uo, Vo = general.run(U0, V0, ops, dts[1], 2)
     eu, ev = _rel(U.cpu().numpy(), Uo), _rel(V.cpu().numpy(), Vo)
     _say("  batch pcg member vs oracle: U %.2e V %.2e" % (eu, ev))
-    assert eu <= 1e-12 and ev <= 1e-12
+    assert_close(U.cpu().numpy(), Uo, 1e-12)
+    assert_close(V.cpu().numpy(), Vo, 1e-12)

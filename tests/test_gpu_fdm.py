@@ -33,8 +33,7 @@ def _gpu(prob, U0, V0, dt, steps, precision="fp64"):
     return U.cpu().numpy(), V.cpu().numpy(), E, st
 
 
-def _rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+from _cmp import assert_close, rel as _rel, relmax as _relmax  # noqa: E402
 
 
 def _lu_ops(prob):
@@ -65,8 +64,8 @@ def test_standing_wave_4x4_central_fp64():
     Ug, Vg, Eg, st = _gpu(prob, U0, V0, dt, steps)
     ops = dg2d.CartOps(prob)
     Uo, Vo = dg2d.run(U0, V0, ops, dt, steps)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
     Eo = dg2d.energy(Uo, Vo, ops)
     assert abs(Eg - Eo) <= 1e-13 * abs(Eo)
     E0 = dg2d.energy(U0, V0, ops)
@@ -90,8 +89,8 @@ def test_fourier_modes_fp64(n, N, p, flux):
     steps = 6
     Ug, Vg, _, _ = _gpu(prob, U0, V0, dt, steps)
     Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, steps)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
 
 
 @pytest.mark.parametrize("nx,ny,N,p,flux,c2", [(3, 2, 6, 3, "upwind", 2.0),
@@ -119,8 +118,8 @@ def test_generic_sizes_rectangles_fp64(nx, ny, N, p, flux, c2):
     U2, V2 = dg2d.run(U0, V0, _lu_ops(prob), dt, 5)
     tol_u = max(1e-12, 4 * _rel(U2, Uo))
     tol_v = max(1e-12, 4 * _rel(V2, Vo))
-    assert _rel(Ug, Uo) <= tol_u
-    assert _rel(Vg, Vo) <= tol_v
+    assert_close(Ug, Uo, tol_u)
+    assert_close(Vg, Vo, tol_v)
     Eo = dg2d.energy(Uo, Vo, ops)
     assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
 
@@ -140,18 +139,26 @@ def test_zero_steps_roundtrip_and_constants():
 
 @pytest.mark.parametrize("flux", ["upwind", "central"])
 def test_fp32_mode_within_1e6(flux):
-    """FP32 storage and arithmetic: relative l2 error against the FP64 oracle <= 1e-6."""
+    """FP32 storage of the stage increments around the FP64 register y: U and V within
+    1e-6 of the FP64 oracle, in relative l2 and in relative element-wise max (the same
+    bar for both; measured about 1e-9 here)."""
     _say("case: fp32", flux)
     n, N, p = 6, 16, 5
     prob = dg2d.CartProblem(nx=n, ny=n, N=N, p=p, flux=flux)
     X, Y = inputs.node_coords(n, n, N)
     U0 = inputs.fourier_field(inputs.fourier_modes(2, kmax=6), X, Y)
-    V0 = np.zeros_like(U0)
+    V0 = 3.0 * inputs.fourier_field(inputs.fourier_modes(3, kmax=6), X, Y)
     dt = 0.15 * prob.hx
     steps = 20
-    Ug, Vg, _, _ = _gpu(prob, U0, V0, dt, steps, precision="fp32")
-    Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, steps)
-    assert _rel(Ug, Uo) <= 1e-6
+    Ug, Vg, Eg, _ = _gpu(prob, U0, V0, dt, steps, precision="fp32")
+    ops = dg2d.CartOps(prob)
+    Uo, Vo = dg2d.run(U0, V0, ops, dt, steps)
+    _say("  rel l2 U %.2e V %.2e, max U %.2e V %.2e" % (
+        _rel(Ug, Uo), _rel(Vg, Vo), _relmax(Ug, Uo), _relmax(Vg, Vo)))
+    assert_close(Ug, Uo, 1e-6, max_bar=1e-6)
+    assert_close(Vg, Vo, 1e-6, max_bar=1e-6)
+    Eo = dg2d.energy(Uo, Vo, ops)
+    assert abs(Eg - Eo) <= 1e-6 * abs(Eo)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -217,11 +224,11 @@ def test_largest_and_degenerate_sizes(nx, ny, N, p, precision, bc):
         s.close()
     Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, 4)
     if precision == "fp32":
-        assert _rel(Ug, Uo) <= 1e-6
+        assert_close(Ug, Uo, 1e-6)
         return
     from test_gpu_fullsize import _eigen_ops
     U2, V2 = dg2d.run(U0, V0, _lu_ops(prob), dt, 4)
     U3, V3 = dg2d.run(U0, V0, _eigen_ops(dg2d.CartOps(prob)), dt, 4)
     _say("  rel U %.1e (lu %.1e, S~ %.1e)" % (_rel(Ug, Uo), _rel(U2, Uo), _rel(U3, Uo)))
-    assert _rel(Ug, Uo) <= max(1e-12, 4 * _rel(U2, Uo), 4 * _rel(U3, Uo))
-    assert _rel(Vg, Vo) <= max(1e-12, 4 * _rel(V2, Vo), 4 * _rel(V3, Vo))
+    assert_close(Ug, Uo, max(1e-12, 4 * _rel(U2, Uo), 4 * _rel(U3, Uo)))
+    assert_close(Vg, Vo, max(1e-12, 4 * _rel(V2, Vo), 4 * _rel(V3, Vo)))

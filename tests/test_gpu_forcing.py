@@ -22,8 +22,7 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+from _cmp import assert_close, rel as _rel, relmax as _relmax  # noqa: E402
 
 
 def _solver(prob, precision="fp64"):
@@ -69,8 +68,8 @@ def test_forcing_matches_oracle_fp64(nx, ny, N, p, flux, nterms, bc):
     finally:
         s.close()
     Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, 7)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
 
 
 def test_forcing_fp32_within_1e6():
@@ -90,7 +89,7 @@ def test_forcing_fp32_within_1e6():
     finally:
         s.close()
     Uo, _ = dg2d.run(U0, np.zeros_like(U0), dg2d.CartOps(prob), dt, 6)
-    assert _rel(Ug, Uo) <= 1e-6
+    assert_close(Ug, Uo, 1e-6)
 
 
 def test_manufactured_solution_converges_on_gpu():
@@ -212,8 +211,8 @@ def test_pcg_forcing_matches_dense_oracle(n, N, p, nterms, bc):
     ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=bc,
                                             forcing=tuple(terms)), Xm, Ym, c2)
     Uo, Vo = general.run(U0, V0, ops, dt, 3)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
 
 
 def test_pcg_manufactured_solution_on_curved_mesh_converges():
@@ -296,7 +295,8 @@ def test_batch_with_source_terms_equals_solo_runs():
             s.close()
         Ub, Vb = got[i]
         if kw.get("solver") == "pcg":
-            assert _rel(Ub, U) <= 1e-12 and _rel(Vb, V) <= 1e-12
+            assert_close(Ub, U, 1e-12)
+            assert_close(Vb, V, 1e-12)
         else:
             np.testing.assert_array_equal(Ub, U)
             np.testing.assert_array_equal(Vb, V)
@@ -327,4 +327,5 @@ def test_pcg_mixed_precision_with_source():
     ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=bc,
                                             forcing=tuple(terms)), Xm, Ym, c2)
     Uo, Vo = general.run(U0, np.zeros_like(U0), ops, dt, 3)
-    assert _rel(Ug, Uo) <= 1e-10 and _rel(Vg, Vo) <= 1e-10
+    assert_close(Ug, Uo, 1e-10)
+    assert_close(Vg, Vo, 1e-10)

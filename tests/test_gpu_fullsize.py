@@ -39,8 +39,7 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+from _cmp import assert_close, rel as _rel, relmax as _relmax  # noqa: E402
 
 
 def _patch(A, cy, cx, R):
@@ -94,7 +93,7 @@ def _eigen_ops(ops):
 
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", 1e-6)])
 def test_fdm_256x256_N16_p5_sampled(precision, bar):
-    steps = 2
+    steps = 4
     _say("case: full-size FDM 256x256 N16 p5 upwind", precision, "steps", steps)
     U0, V0, Ug, Vg, dt, (n, N, p) = _fdm_full(precision, steps)
     R = 4 * steps
@@ -108,12 +107,17 @@ def test_fdm_256x256_N16_p5_sampled(precision, bar):
         _, Vt = dg2d.run(_patch(U0, cy, cx, R), _patch(V0, cy, cx, R), opt, dt, steps)
         ref_u.append(Uo[R, R]); ref_v.append(Vo[R, R]); eig_v.append(Vt[R, R])
         got_u.append(Ug[cy, cx]); got_v.append(Vg[cy, cx])
-    eu = _rel(np.array(got_u), np.array(ref_u))
-    ev = _rel(np.array(got_v), np.array(ref_v))
-    d = _rel(np.array(eig_v), np.array(ref_v))
-    _say("  sampled rel l2: U %.3e  V %.3e  (V floor of an FP64 eigenbasis: %.3e)" % (eu, ev, d))
-    assert eu <= bar
-    assert ev <= (max(bar, 4 * d) if precision == "fp64" else bar)
+    gu, gv, ru, rv = (np.array(x) for x in (got_u, got_v, ref_u, ref_v))
+    d = _rel(np.array(eig_v), rv)
+    dm = _relmax(np.array(eig_v), rv)
+    _say("  sampled rel l2: U %.3e  V %.3e, max U %.3e  V %.3e  (V floor of an FP64 "
+         "eigenbasis: l2 %.3e, max %.3e)" % (_rel(gu, ru), _rel(gv, rv), _relmax(gu, ru),
+                                             _relmax(gv, rv), d, dm))
+    assert_close(gu, ru, bar, what="U")
+    if precision == "fp64":
+        assert_close(gv, rv, max(bar, 4 * d), max_bar=max(10 * bar, 4 * dm), what="V")
+    else:
+        assert_close(gv, rv, bar, what="V")
 
 
 def _gen_full(n, N, p, mapped, grf_seed, dt_cfl, rtol, steps, precision="fp64"):
@@ -143,7 +147,7 @@ def _gen_full(n, N, p, mapped, grf_seed, dt_cfl, rtol, steps, precision="fp64"):
     (128, True, 3, 1e-12, "mixed", 1e-10),   # mixed precision (operator hi + lo ~ 2^-48)
 ])
 def test_pcg_full_size_sampled(n, mapped, grf_seed, rtol, precision, bar):
-    N, p, steps = 12, 5, 1
+    N, p, steps = 12, 5, 2
     _say("case: full-size PCG %dx%d N12 p5 mapped=%s rtol=%g %s" % (n, n, mapped, rtol, precision))
     Xm, Ym, c2, U0, V0, Ug, Vg, dt, st = _gen_full(n, N, p, mapped, grf_seed, 0.1, rtol, steps,
                                                    precision)
@@ -158,10 +162,11 @@ def test_pcg_full_size_sampled(n, mapped, grf_seed, rtol, precision, bar):
         Uo, Vo = general.run(_patch(U0, cy, cx, R), _patch(V0, cy, cx, R), ops, dt, steps)
         ref_u.append(Uo[R, R]); ref_v.append(Vo[R, R])
         got_u.append(Ug[cy, cx]); got_v.append(Vg[cy, cx])
-    eu = _rel(np.array(got_u), np.array(ref_u))
-    ev = _rel(np.array(got_v), np.array(ref_v))
-    _say("  sampled rel l2 vs dense oracle: U %.3e  V %.3e" % (eu, ev))
-    assert eu <= bar and ev <= bar
+    gu, gv, ru, rv = (np.array(x) for x in (got_u, got_v, ref_u, ref_v))
+    _say("  sampled vs dense oracle: rel l2 U %.3e  V %.3e, max U %.3e  V %.3e"
+         % (_rel(gu, ru), _rel(gv, rv), _relmax(gu, ru), _relmax(gv, rv)))
+    assert_close(gu, ru, bar, what="U")
+    assert_close(gv, rv, bar, what="V")
 
 
 def test_fdm_walls_256x256_N16_p5_sampled():
@@ -177,7 +182,7 @@ def test_fdm_walls_256x256_N16_p5_sampled():
     max(1e-12, 4 x the larger of the two oracle distances), for U and for V."""
     import torch
     from paper_2105_01722_amd import gdw
-    steps = 2
+    steps = 4
     _say("case: full-size FDM with walls 256x256 N16 p5", "steps", steps)
     n, N, p = 256, 16, 5
     bc = ("dirichlet",) * 4
@@ -214,9 +219,64 @@ def test_fdm_walls_256x256_N16_p5_sampled():
         lu_u.append(Ul[ly, lx]); lu_v.append(Vl[ly, lx])
         got_u.append(Ug[cy, cx]); got_v.append(Vg[cy, cx])
     ru, rv = np.array(ref_u), np.array(ref_v)
-    eu, ev = _rel(np.array(got_u), ru), _rel(np.array(got_v), rv)
+    gu, gv = np.array(got_u), np.array(got_v)
     du = max(_rel(np.array(eig_u), ru), _rel(np.array(lu_u), ru))
     dv = max(_rel(np.array(eig_v), rv), _rel(np.array(lu_v), rv))
-    _say("  sampled rel l2: U %.3e  V %.3e  (oracle floors: U %.3e  V %.3e)" % (eu, ev, du, dv))
-    assert eu <= max(1e-12, 4 * du)
-    assert ev <= max(1e-12, 4 * dv)
+    dmu = max(_relmax(np.array(eig_u), ru), _relmax(np.array(lu_u), ru))
+    dmv = max(_relmax(np.array(eig_v), rv), _relmax(np.array(lu_v), rv))
+    _say("  sampled rel l2: U %.3e  V %.3e, max U %.3e  V %.3e  (oracle floors: l2 U %.3e "
+         "V %.3e, max U %.3e V %.3e)" % (_rel(gu, ru), _rel(gv, rv), _relmax(gu, ru),
+                                         _relmax(gv, rv), du, dv, dmu, dmv))
+    assert_close(gu, ru, max(1e-12, 4 * du), max_bar=max(1e-11, 4 * dmu), what="U")
+    assert_close(gv, rv, max(1e-12, 4 * dv), max_bar=max(1e-11, 4 * dmv), what="V")
+
+
+def _fourier_exact_uv(modes, X, Y, t):
+    """u and v = u_t of the exact standing-wave superposition (c = 1, v0 = 0):
+    u = sum a cos(w t) cos(2 pi k.x + theta), w = 2 pi |k|."""
+    U = np.zeros_like(X)
+    V = np.zeros_like(X)
+    for kx, ky, a, th in modes:
+        w = 2 * np.pi * np.hypot(kx, ky)
+        ph = np.cos(2 * np.pi * (kx * X + ky * Y) + th)
+        U += a * np.cos(w * t) * ph
+        V -= a * w * np.sin(w * t) * ph
+    return U, V
+
+
+@pytest.mark.parametrize("precision,bar_u,bar_v,max_v", [("fp64", 1e-12, 1e-10, 3e-10),
+                                                         ("fp32", 1e-6, 1e-6, 1e-6)])
+def test_fdm_headline_100_steps_vs_exact(precision, bar_u, bar_v, max_v):
+    """The benchmark's headline workload at its full size and length: 256 x 256 elements,
+    N = 16, p = 5, upwind, dt = 0.15 h, 100 RK4 steps from the 8-mode Fourier data with
+    v0 = 0, every element of U and V against the exact solution, in relative l2 and in
+    relative element-wise max (same bar for both).
+
+    U: FP64 <= 1e-12 (the discretisation error here is about 4e-14), FP32 storage
+    <= 1e-6.  V: from v0 = 0, V = u_t grows like t omega^2 u and at t = 3.7e-3 is small
+    against the scale eps lambda_max |u| at which any FP64 evaluation of the
+    simultaneously diagonalised operator rounds (the FP64 oracle itself moves V by 9e-12
+    against an 80-bit evaluation after 2 steps of this grid; measured here 5e-11 in l2
+    and 1e-10 in max), so the FP64 bars on V are 1e-10 (l2) and 3e-10 (max); FP32
+    storage <= 1e-6 in both norms."""
+    import torch
+    from paper_2105_01722_amd import gdw
+    n, N, p, steps = 256, 16, 5, 100
+    _say("case: headline 256x256 N16 p5 upwind, %d steps, %s" % (steps, precision))
+    X, Y = inputs.node_coords(n, n, N)
+    modes = inputs.fourier_modes(2)
+    U0 = inputs.fourier_field(modes, X, Y)
+    dt = 0.15 / (n * N)
+    s = gdw.Solver(n, n, N, p, c2=1.0, flux="upwind", xi=1.0, precision=precision)
+    try:
+        s.set_state(torch.from_numpy(U0).cuda(), torch.zeros(U0.shape, dtype=torch.float64).cuda())
+        s.run(dt, steps)
+        Ug, Vg = (x.cpu().numpy() for x in s.get_state())
+        assert s.stats()["status"] == 0
+    finally:
+        s.close()
+    Ue, Ve = _fourier_exact_uv(modes, X, Y, steps * dt)
+    _say("  vs exact: rel l2 U %.3e  V %.3e, max U %.3e  V %.3e"
+         % (_rel(Ug, Ue), _rel(Vg, Ve), _relmax(Ug, Ue), _relmax(Vg, Ve)))
+    assert_close(Ug, Ue, bar_u, max_bar=bar_u, what="U")
+    assert_close(Vg, Ve, bar_v, max_bar=max_v, what="V")

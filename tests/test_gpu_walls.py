@@ -33,8 +33,7 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+from _cmp import assert_close, rel as _rel, relmax as _relmax  # noqa: E402
 
 
 def _gpu(prob, U0, V0, dt, steps, precision="fp64"):
@@ -77,8 +76,8 @@ def test_walls_match_oracle_fp64(bcname, nx, ny, N, p, flux):
     Ug, Vg, Eg, st = _gpu(prob, U0, V0, dt, steps)
     ops = dg2d.CartOps(prob)
     Uo, Vo = dg2d.run(U0, V0, ops, dt, steps)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
     Eo = dg2d.energy(Uo, Vo, ops)
     assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
     assert st["status"] == 0
@@ -94,7 +93,7 @@ def test_walls_fp32_within_1e6(bcname):
     dt = 0.1 * prob.hx
     Ug, Vg, _, _ = _gpu(prob, U0, V0, dt, 8, precision="fp32")
     Uo, Vo = dg2d.run(U0, V0, dg2d.CartOps(prob), dt, 8)
-    assert _rel(Ug, Uo) <= 1e-6
+    assert_close(Ug, Uo, 1e-6)
 
 
 def test_dirichlet_keeps_odd_symmetry_of_the_doubled_periodic_run():
@@ -240,8 +239,8 @@ def test_pcg_walls_match_dense_oracle(bcname, n, N, p, flux):
     ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux=flux, bc=BCS[bcname]),
                          Xm, Ym, c2)
     Uo, Vo = general.run(U0, V0, ops, dt, steps)
-    assert _rel(Ug, Uo) <= 1e-12
-    assert _rel(Vg, Vo) <= 1e-12
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
     Eo = general.energy(Uo, Vo, ops)
     assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
 
@@ -259,8 +258,8 @@ def test_pcg_walls_cartesian_equal_fdm_walls():
     Uf, Vf, _, _ = _gpu(prob, U0, V0, dt, 4)
     Up, Vp, _, st = _pcg_gpu(n, N, p, X, Y, np.ones_like(X), U0, V0, dt, 4, BCS["mixed"])
     assert st["status"] == 0
-    assert _rel(Up, Uf) <= 1e-12
-    assert _rel(Vp, Vf) <= 1e-12
+    assert_close(Up, Uf, 1e-12)
+    assert_close(Vp, Vf, 1e-12)
 
 
 def test_pcg_walls_mixed_precision():
@@ -280,4 +279,5 @@ def test_pcg_walls_mixed_precision():
     ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind", bc=bc),
                          Xm, Ym, c2)
     Uo, Vo = general.run(U0, V0, ops, dt, steps)
-    assert _rel(Ug, Uo) <= 1e-10 and _rel(Vg, Vo) <= 1e-10
+    assert_close(Ug, Uo, 1e-10)
+    assert_close(Vg, Vo, 1e-10)
