@@ -235,6 +235,19 @@ gdw_status gdw_mlp_forward(gdw_mlp* mlp, const float* x, int n, float* out, void
 gdw_status gdw_mlp_grad(gdw_mlp* mlp, const float* x, const float* y, int n, float* grad,
                         double* loss_host, void* stream);
 
+/* The gradient of gdw_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): same arguments and
+ * results, except that the loss goes to device memory (*loss, one FP64 value) and the call
+ * does not synchronise.  It calls no allocator: the minibatch's activations and partial
+ * sums live in a fixed 8 MiB device array of the library (one per device, held until the
+ * process ends), so n (the number of rows) is limited by 4 n (6 hidden + 2 n_out) + 512 <= 8 MiB
+ * (n <= 1899 for 64 -> 128 -> 128 -> 168); larger n returns EINVAL.  grad: device FP32,
+ * num_params entries; x, y as for gdw_mlp_grad.  Every call on one device shares that
+ * array and overwrites it: calls that overlap on one device (other streams or threads)
+ * race, so serialise them. */
+gdw_status gdw_mlp_grad_noalloc(gdw_mlp* mlp, const float* x, const float* y, int n, float* grad,
+                                double* loss, void* stream);
+
 /* Adam training (lr, b1 = 0.9, b2 = 0.999, eps = 1e-8) over `epochs` passes of contiguous
  * minibatches of `batch` rows (the last one shorter) of (x, y), device FP32 arrays.
  * loss_host[epoch] receives the mean minibatch loss of each epoch (synchronises). */

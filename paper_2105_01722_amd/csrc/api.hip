@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -1021,6 +1022,70 @@ extern "C" gdw_status gdw_mlp_train(gdw_mlp* m, const float* x, const float* y, 
   if (e != hipSuccess) { set_error(std::string("gdw_mlp_train: ") + hipGetErrorString(e)); return GDW_EHIP; }
   if (loss_host)
     for (int ep = 0; ep < epochs; ++ep) loss_host[ep] = h[ep] / (double)nbatch;
+  return GDW_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Allocation-free network gradient.  The activations, the loss partial sums and the
+// output gradient of one minibatch live in `scratch`, a file-scope device array of
+// kScratchBytes on every device the library runs on (held until the process ends).
+// Host code never passes `scratch` itself (its name is a host-side stand-in, not a
+// device address): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and is kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------------
+static constexpr size_t kScratchBytes = (size_t)8 << 20;     // 8 MiB per device
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static gdw_status scratch_address(void** out) {
+  int dev = -1;
+  GDW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device index out of range"); return GDW_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GDW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_mlp_grad_noalloc(gdw_mlp* m, const float* x, const float* y, int n,
+                                           float* grad, double* loss, void* stream) {
+  if (!m || !x || !y || !grad || !loss || n < 1) { set_error("invalid argument"); return GDW_EINVAL; }
+  const int H = m->net.hidden, K = m->net.n_out;
+  const size_t part = 64 * sizeof(double);
+  const size_t need = part + (size_t)n * (6 * (size_t)H + 2 * (size_t)K) * sizeof(float);
+  if (need > kScratchBytes) {
+    set_error("gdw_mlp_grad_noalloc: " + std::to_string(n) + " rows need " + std::to_string(need) +
+              " bytes of scratch; the limit is " + std::to_string(kScratchBytes));
+    return GDW_EINVAL;
+  }
+  void* base = nullptr;
+  gdw_status s = scratch_address(&base);
+  if (s != GDW_OK) return s;
+  MlpWork w{};
+  w.bmax = n;
+  w.part = (double*)base;
+  float* f = (float*)((unsigned char*)base + part);
+  const size_t nh = (size_t)n * H, nk = (size_t)n * K;
+  w.z1 = f; f += nh;
+  w.h1 = f; f += nh;
+  w.z2 = f; f += nh;
+  w.h2 = f; f += nh;
+  w.dh = f; f += nh;
+  w.dz = f; f += nh;
+  w.out = f; f += nk;
+  w.dout = f;
+  MlpNet net = m->net;      // same parameters; the gradient goes straight to `grad`
+  net.g = grad;
+  hipStream_t st = (hipStream_t)stream;
+  GDW_HIP(launch_zero_f64(loss, 1, st));
+  GDW_HIP(mlp_forward(net, x, n, w, st));
+  GDW_HIP(mlp_backward(net, x, y, n, w, loss, st));
   return GDW_OK;
 }
 

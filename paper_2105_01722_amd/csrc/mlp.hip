@@ -141,6 +141,11 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
   th16[i] = (_Float16)t;
 }
 
+__global__ void k_zero_f64(double* __restrict__ p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 __global__ void k_to_half(const float* __restrict__ a, long n, _Float16* __restrict__ b) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (_Float16)a[i];
@@ -190,6 +195,12 @@ hipError_t mlp_adam(MlpNet& net, float lr, hipStream_t st) {
   const float c1 = 1.f - powf(b1, (float)net.step), c2 = 1.f - powf(b2, (float)net.step);
   hipLaunchKernelGGL(k_adam, dim3(nb(net.np)), dim3(256), 0, st, net.th, net.g, net.m, net.v, net.np,
                      lr, b1, b2, eps, c1, c2, net.w16);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f64, dim3(nb(n)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

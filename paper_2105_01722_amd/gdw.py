@@ -77,6 +77,7 @@ def _load():
         "gdw_mlp_set_params": (I, [P, P]),
         "gdw_mlp_forward": (I, [P, P, I, P, P]),
         "gdw_mlp_grad": (I, [P, P, P, I, P, ctypes.POINTER(D), P]),
+        "gdw_mlp_grad_noalloc": (I, [P, P, P, I, P, P, P]),
         "gdw_mlp_train": (I, [P, P, P, I, I, I, ctypes.c_float, P, P]),
         "gdw_mlp_destroy": (V, [P]),
         "gdw_precond_data": (I, [P, P, P, P]),
@@ -348,6 +349,26 @@ class Mlp:
                                 x.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss),
                                 _stream(stream)), "gdw_mlp_grad")
         return g, loss.value
+
+    def grad_noalloc(self, x, y, grad, loss, stream=None):
+        """gdw_mlp_grad_noalloc: gradient into `grad` (float32 CUDA tensor of num_params
+        entries) and the loss into `loss` (float64 CUDA tensor of one entry), asynchronous,
+        with no device allocation inside the library."""
+        import torch
+        for t, name, dt, k in ((x, "x", torch.float32, None), (y, "y", torch.float32, None),
+                               (grad, "grad", torch.float32, self.np),
+                               (loss, "loss", torch.float64, 1)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt \
+                    or not t.is_contiguous() or (k is not None and t.numel() != k):
+                raise ValueError("%s must be a contiguous %s CUDA tensor%s" % (
+                    name, dt, "" if k is None else " of %d entries" % k))
+        if x.dim() != 2 or x.shape[1] != self.n_in or y.shape != (x.shape[0], self.n_out):
+            raise ValueError("x must be [n, %d] and y [n, %d]" % (self.n_in, self.n_out))
+        _check(lib.gdw_mlp_grad_noalloc(self.h, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), x.shape[0],
+                                        ctypes.c_void_p(grad.data_ptr()),
+                                        ctypes.c_void_p(loss.data_ptr()), _stream(stream)),
+               "gdw_mlp_grad_noalloc")
 
     def train(self, x, y, epochs, batch=256, lr=1e-3, stream=None):
         import numpy as np
