@@ -48,12 +48,32 @@ from . import gd1d
 
 
 def flux_params(flux, xi=1.0):
-    """(alpha, beta, tau) of Sec. 2.2.1 for 'central' or 'upwind' (xi: splitting speed)."""
+    """(alpha, beta, tau) of Sec. 2.2.1 for 'central', 'upwind' (xi: splitting speed) or
+    'alternating' (alpha = 1, beta = tau = 0; the alpha of each face is face_alpha's)."""
     if flux == "central":
         return 0.5, 0.0, 0.0
     if flux == "upwind":
         return 0.5, 0.5 * xi, 0.5 / xi
-    raise ValueError("flux must be 'central' or 'upwind'")
+    if flux == "alternating":
+        return 1.0, 0.0, 0.0
+    raise ValueError("flux must be 'central', 'upwind' or 'alternating'")
+
+
+def face_alpha(flux, f, wall=False):
+    """alpha on face f ("E", "W", "N", "S") of an element.
+
+    Central and upwind: 1/2 on every face.  Alternating (Sec. 2.2.1 prints alpha = 1 with
+    superscript 1 the inside of the element): taken literally every element would use its
+    own v as v* on both sides of a face, a two-valued flux.  The reading used here fixes
+    one orientation for each face: v* is the value of the element on the low-coordinate
+    side (smaller x, or smaller y) and (grad u)* the gradient of the element on the high
+    side.  Seen from an element that is alpha = 1 on its E and N faces and alpha = 0 on
+    its W and S faces.  A wall face has no second element; there alpha = 1/2 (with
+    beta = tau = 0 the mirror state then gives v* = 0 on a Dirichlet wall and
+    n . (grad u)* = 0 on a Neumann wall, and the face exchanges no energy)."""
+    if flux != "alternating" or wall:
+        return 0.5
+    return 1.0 if f in ("E", "N") else 0.0
 
 
 @dataclass
@@ -157,6 +177,14 @@ _SIDE = {"E": (slice(None), -1), "W": (slice(None), 0), "N": (-1, slice(None)),
          "S": (0, slice(None))}
 
 
+def face_alphas(prob, f):
+    """face_alpha of face f for every element, [ny, nx] (wall faces differ)."""
+    al = np.full((prob.ny, prob.nx), face_alpha(prob.flux, f))
+    if prob.bc["EWNS".index(f)] != "periodic":
+        al[_SIDE[f]] = face_alpha(prob.flux, f, wall=True)
+    return al
+
+
 def neighbour_traces(tr, bc=("periodic",) * 4):
     """Traces of the neighbour across each face, on its opposite face: the periodic
     neighbour, or on a wall face the mirror state of the element's own traces
@@ -198,11 +226,12 @@ def lifts(U, V, ops):
     `traces`, so the face integrals are products with the 1D face mass matrix.
     """
     prob = ops.prob
-    alpha, beta, tau = flux_params(prob.flux, prob.xi)
+    _, beta, tau = flux_params(prob.flux, prob.xi)
     c2 = prob.c2
     tr = traces(U, V, ops)
     nb = neighbour_traces(tr, prob.bc)
-    sig = {f: face_sigmas(tr[f][0], tr[f][1], nb[f][0], nb[f][1], alpha, beta, tau)
+    sig = {f: face_sigmas(tr[f][0], tr[f][1], nb[f][0], nb[f][1],
+                          face_alphas(prob, f)[:, :, None], beta, tau)
            for f in "EWNS"}
     Fu = np.zeros_like(U)
     Fv = np.zeros_like(V)

@@ -37,7 +37,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import gd1d
-from .dg2d import flux_params, face_sigmas
+from .dg2d import face_alpha, flux_params, face_sigmas
 
 
 @dataclass
@@ -274,10 +274,20 @@ def _exterior(tr, f, prob):
     return an, vn
 
 
+def _face_alphas(prob, f):
+    """alpha of face f (dg2d.face_alpha) for every element, flat [e] (wall faces differ)."""
+    al = np.full((prob.ny, prob.nx), face_alpha(prob.flux, f))
+    if prob.bc["EWNS".index(f)] != "periodic":
+        side = {"E": (slice(None), -1), "W": (slice(None), 0), "N": (-1, slice(None)),
+                "S": (0, slice(None))}[f]
+        al[side] = face_alpha(prob.flux, f, wall=True)
+    return al.ravel()
+
+
 def lifts(U, V, ops):
     """F_u,i = int c^2 (n . grad phi_i)(v* - v) dS and F_v,i = int c^2 phi_i n.(grad u)* dS."""
     prob = ops.prob
-    alpha, beta, tau = flux_params(prob.flux, prob.xi)
+    _, beta, tau = flux_params(prob.flux, prob.xi)
     ne, n1 = prob.nx * prob.ny, ops.n1
     tr = face_traces(U, V, ops)
     Fu = np.zeros((ne, n1, n1))
@@ -286,7 +296,7 @@ def lifts(U, V, ops):
         fd = ops.faces[f]
         a, v = tr[f]
         an, vn = _exterior(tr, f, prob)
-        su, sv = face_sigmas(a, v, an, vn, alpha, beta, tau)
+        su, sv = face_sigmas(a, v, an, vn, _face_alphas(prob, f)[:, None], beta, tau)
         wsu = fd["wq"][None, :] * su
         wsv = fd["wq"][None, :] * sv * fd["c2sJ"]
         B, D, dn, node = fd["B"], fd["D"], fd["dn"], fd["node"]
