@@ -46,8 +46,14 @@ typedef enum {
 } gdw_status;
 
 /* Numerical flux (Sec. 2.2.1): central alpha = 1/2, beta = tau = 0; upwind
- * alpha = 1/2, beta = xi/2, tau = 1/(2 xi).  The alternating flux is not offered. */
-typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1 } gdw_flux;
+ * alpha = 1/2, beta = xi/2, tau = 1/(2 xi); alternating alpha = 1, beta = tau = 0 with
+ * one orientation per face (the printed alpha = 1 with superscript 1 the inside would be
+ * two-valued): v* is the value of the element on the low-coordinate side (smaller x or
+ * y) and (grad u)* the gradient of the element on the high side, so an element takes
+ * alpha = 1 on its E and N faces and alpha = 0 on its W and S faces.  Wall faces take
+ * alpha = 1/2 for every flux (with beta = tau = 0 the mirror state then gives v* = 0 on a
+ * Dirichlet wall and n . (grad u)* = 0 on a Neumann wall). */
+typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1, GDW_FLUX_ALTERNATING = 2 } gdw_flux;
 
 /* Arithmetic of the time loop.  GDW_FP64: state, tables and arithmetic in FP64.
  * GDW_MIXED_FP32, constant-coefficient path: every stage right-hand side (fluxes, lifts,

@@ -65,7 +65,9 @@ static gdw_status validate(const gdw_desc* d) {
     set_error("Lx, Ly must be finite and > 0"); return GDW_EINVAL;
   }
   if (!(d->c2 > 0) || !std::isfinite(d->c2)) { set_error("c2 must be finite and > 0"); return GDW_EINVAL; }
-  if (d->flux != GDW_FLUX_CENTRAL && d->flux != GDW_FLUX_UPWIND) { set_error("unknown flux"); return GDW_EINVAL; }
+  if (d->flux != GDW_FLUX_CENTRAL && d->flux != GDW_FLUX_UPWIND && d->flux != GDW_FLUX_ALTERNATING) {
+    set_error("unknown flux"); return GDW_EINVAL;
+  }
   if (d->flux == GDW_FLUX_UPWIND && (!(d->xi > 0) || !std::isfinite(d->xi))) {
     set_error("xi must be finite and > 0 for the upwind flux"); return GDW_EINVAL;
   }
@@ -409,7 +411,12 @@ static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
   c->n1 = d->N + 1;
   c->nel = (long)d->nx * d->ny;
   c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
-  c->alpha = 0.5;
+  // alternating flux: v* from the element on the low-coordinate side of a face, (grad u)*
+  // from the one on the high side, i.e. alpha = 1 on an element's E and N faces and 0 on
+  // its W and S faces (wall faces take 1/2 in the kernels)
+  const bool alt = d->flux == GDW_FLUX_ALTERNATING;
+  c->alf[0] = c->alf[2] = alt ? 1.0 : 0.5;
+  c->alf[1] = c->alf[3] = alt ? 0.0 : 0.5;
   c->beta = d->flux == GDW_FLUX_UPWIND ? 0.5 * d->xi : 0.0;
   c->tau = d->flux == GDW_FLUX_UPWIND ? 0.5 / d->xi : 0.0;
   const bool pcg = d->solver == GDW_SOLVE_PCG || d->coeff_variable || d->mapped;
@@ -617,7 +624,7 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.n1 = c->n1;
   a.dt = dt;
   a.c2 = c->d.c2;
-  a.alpha = c->alpha;
+  for (int k = 0; k < 4; ++k) a.alf[k] = c->alf[k];
   a.beta = c->beta;
   a.tau = c->tau;
   a.invL = (const double*)c->invL;
@@ -657,7 +664,7 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.f_w = c->t_dev ? c->t_dev + 1 : nullptr;
   a.mapped = c->d.mapped;
   a.dt = dt;
-  a.alpha = c->alpha;
+  for (int k = 0; k < 4; ++k) a.alf[k] = c->alf[k];
   a.beta = c->beta;
   a.tau = c->tau;
   a.rtol = c->rtol;

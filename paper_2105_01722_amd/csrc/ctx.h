@@ -28,7 +28,8 @@ struct gdw_ctx {
   int n1 = 0;
   long nel = 0;
   size_t elem_bytes = 0;       // sizeof(T) of the time-loop arithmetic
-  double alpha = 0, beta = 0, tau = 0;
+  double alf[4] = {0, 0, 0, 0};   // alpha of the E, W, N, S faces (Sec. 2.2.1)
+  double beta = 0, tau = 0;
   // device buffers (time-loop type T)
   void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void* tr[2] = {nullptr, nullptr};

@@ -27,7 +27,8 @@ struct StageArgs {
   long nel;
   int nx, ny, n1;
   int bcbits;          // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
-  double dt, c2, alpha, beta, tau;
+  double dt, c2, beta, tau;
+  double alf[4];       // alpha of Sec. 2.2.1 on the E, W, N, S faces (1/2 on wall faces)
   // source term: nf terms (0..4), modal g_k at frc + k * frc_stride; the weights
   // fw[4 (stage - 1) + k] = sin(omega_k t_stage + phase_k) of the current step sit in
   // device memory (written by launch_source_step before the step's stages)

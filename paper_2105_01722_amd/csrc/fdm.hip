@@ -465,8 +465,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   for (int i = tid; i < 8 * n1; i += blockDim.x) sgh[i] = a.gh[i];
 
   // Phase A: modal face fluxes sigma_u = (1-alpha)(v_nb - v) - beta (a + a_nb),
-  // sigma_v = (1-alpha) a - alpha a_nb + tau (v_nb - v)  (Sec. 2.2.1)
-  const R alpha = a.alpha, beta = a.beta, tau = a.tau;
+  // sigma_v = (1-alpha) a - alpha a_nb + tau (v_nb - v)  (Sec. 2.2.1); alpha per face
+  // (the alternating flux is oriented: 1 on E and N faces, 0 on W and S), 1/2 on walls
+  const R beta = a.beta, tau = a.tau;
   for (int i = tid; i < ne * 4 * n1; i += blockDim.x) {
     const int el = i / (4 * n1);
     const int r = i - el * 4 * n1;
@@ -493,6 +494,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
       an = -an;
       vn = -vn;
     }
+    const R alpha = wall ? R(0.5) : (R)a.alf[f];
     const R jv = vn - vs;
     sig[(el * 8 + 2 * f) * n1 + j] = (R(1) - alpha) * jv - beta * (as + an);
     sig[(el * 8 + 2 * f + 1) * n1 + j] = (R(1) - alpha) * as - alpha * an + tau * jv;

@@ -67,7 +67,8 @@ struct PcgStageArgs {
   int nx, ny;
   int bcbits;           // gdw_bc of side f (0 E, 1 W, 2 N, 3 S) in bits 2f, 2f+1; 0: periodic
   int mapped;
-  double dt, alpha, beta, tau, rtol, rtol_inner;
+  double dt, beta, tau, rtol, rtol_inner;
+  double alf[4];        // alpha of Sec. 2.2.1 on the E, W, N, S faces (1/2 on wall faces)
   int maxit;
   int mixed;            // 1: FP32 operator for the inner PCG, FP64 residual refinement
   const int* fo;        // [nn+1] row starts of the full stencil rectangles

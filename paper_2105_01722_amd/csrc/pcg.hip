@@ -770,9 +770,10 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
       an = -an;
       vn = -vn;
     }
+    const double alpha = wall ? 0.5 : a.alf[f];
     const double jv = vn - vs;
-    sig[id * 2] = (1.0 - a.alpha) * jv - a.beta * (as + an);
-    sig[id * 2 + 1] = (1.0 - a.alpha) * as - a.alpha * an + a.tau * jv;
+    sig[id * 2] = (1.0 - alpha) * jv - a.beta * (as + an);
+    sig[id * 2 + 1] = (1.0 - alpha) * as - alpha * an + a.tau * jv;
   }
   __syncthreads();
   // lifts: per face and node l along the face,
