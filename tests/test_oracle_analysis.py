@@ -2,11 +2,11 @@
 dispersion analysis (Sec. 4) and spectral-radius study (Sec. 5).
 
 The paper reports both only in figures, so the pins are the properties it states:
-  * Sec. 5: the spectral radius grows linearly with p for the central and the upwind
-    flux, with periodic ends and with a Dirichlet left / Neumann right end (standard DG
+  * Sec. 5: the spectral radius grows linearly with p for the central, the alternating
+    and the upwind flux, with periodic ends and with a Dirichlet left / Neumann right end (standard DG
     grows like p^2); rho is proportional to 1/h, so rho h depends on p and not on N;
-  * Sec. 4: the central flux gives purely imaginary eigenvalues (no numerical damping),
-    the upwind flux none with positive real part; the physical mode of a well-resolved
+  * Sec. 4: the central and the alternating flux give purely imaginary eigenvalues (no
+    numerical damping), the upwind flux none with positive real part; the physical mode of a well-resolved
     Bloch wave has a phase error that is small and falls as p grows.
 
 The 1D operator is the oracle's 2D scheme restricted to y-independent states (the
@@ -29,7 +29,7 @@ def _spectrum(n, N, p, flux, bc=PERIODIC):
     return np.linalg.eigvals(L), prob
 
 
-@pytest.mark.parametrize("flux", ["central", "upwind"])
+@pytest.mark.parametrize("flux", ["central", "upwind", "alternating"])
 @pytest.mark.parametrize("bc", [PERIODIC, DIR_NEU])
 def test_spectral_radius_linear_in_p(flux, bc):
     rh = {}
@@ -54,19 +54,19 @@ def test_central_flux_spectrum_is_imaginary_upwind_has_no_growth(p):
     sqrt(eps) rho; those eigenvalues are checked to be that small and set apart.  A
     flipped sign of the upwind tau term gives Re / rho of order one.  (Any alpha with
     beta = tau = 0 conserves the energy, so this test does not see alpha.)"""
-    for flux in ("central", "upwind"):
+    for flux in ("central", "alternating", "upwind"):
         ev, _ = _spectrum(4, 9, p, flux)
         rho = np.abs(ev).max()
         zero = np.abs(ev) <= 1e-6 * rho
         assert zero.sum() >= 2
         rest = ev[~zero]
-        if flux == "central":
+        if flux != "upwind":
             assert np.abs(rest.real).max() <= 1e-12 * rho
         else:
             assert rest.real.max() <= 1e-12 * rho
 
 
-@pytest.mark.parametrize("flux", ["central", "upwind"])
+@pytest.mark.parametrize("flux", ["central", "upwind", "alternating"])
 def test_physical_mode_phase_error_falls_with_p(flux):
     """Bloch waves exp(i kappa x) on the periodic unit interval (4 elements, N = 9, 36
     cells): for kappa = 2 pi and 4 pi the eigenvalue nearest to i kappa has a relative
