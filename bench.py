@@ -30,11 +30,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
 # HBM bytes per launch of the FP64 stage kernel k_stage<double,*,17,4> on the workload
-# below, from rocprofv3 FETCH_SIZE / WRITE_SIZE (mean over the 4 stage variants), scaled
-# by a plain device copy's reading of the same counters (x2.0 read, x1.0 write); the
-# summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.  Set to None
-# whenever that kernel changes until the counters are taken again.
-FDM_STAGE_TRAFFIC = (319211.54 * 2.0 + 468832.59) * 1024.0
+# below, from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean over the 4 stage
+# variants), scaled by a plain device copy's reading of the same counters (x2.0 read,
+# x1.0 write); the summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.
+# Set to None whenever that kernel changes until the counters are taken again.
+FDM_STAGE_TRAFFIC = (318921.1 * 2.0 + 469083.7) * 1024.0
+# The same for the PCG stage kernel k_pcg_stage_group<*,717> on the 128 x 128, N = 12, p = 5
+# mapped workload (profiles/pcg_stage_128x128_N12_p5_fp64.md).
+PCG_STAGE_TRAFFIC = (2562770.0 * 2.0 + 174337.2) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -145,6 +148,28 @@ def _pcg_flops_per_step(st, nel, N, p):
     per_stage = nel * ((st["mean_it_S"] + 1) * (2 * nnz + pre) + 2 * nnz
                        + (st["mean_it_M"] + 1) * (2 * nnz + pre))
     return 4 * per_stage
+
+
+def _pcg_alg_bytes_per_dof_update(N, p, s=8):
+    """Algorithmic HBM bytes per DOF-update of the PCG path: the 32 s of the RK4 state plus,
+    per stage, the symmetric halves of S_K and M_J read once (s bytes per entry)."""
+    n1 = N + 1
+    nnz_sym = 0
+    for i in range(n1 * n1):
+        ix, iy = i % n1, i // n1
+        for j in range(i, n1 * n1):
+            jx, jy = j % n1, j // n1
+            # rows i, j couple when their windows overlap in both directions
+            if abs(ix - jx) <= p and abs(iy - jy) <= p and _gd_couple(ix, jx, N, p) \
+                    and _gd_couple(iy, jy, N, p):
+                nnz_sym += 1
+    return 32 * s + 4 * s * 2 * nnz_sym / (n1 * n1)
+
+
+def _gd_couple(i, j, N, p):
+    """Whether 1D GD nodes i and j share a cell window (their mass entry is non-zero)."""
+    lo = lambda k: min(max(k - (p - 1) // 2, 0), N - p)
+    return any(lo(k) <= i <= lo(k) + p and lo(k) <= j <= lo(k) + p for k in range(N))
 
 
 def _time_pcg(w, steps, warmup, rtol=1e-12, precision="fp64"):
@@ -502,6 +527,8 @@ def main():
         print("bench: pcg mixed %.3f ms/step" % (msm / ksteps), file=sys.stderr, flush=True)
         dmix = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(stm, st64))
         flops = _pcg_flops_per_step(its, pn * pn, pN, pw["p"]) * ksteps / (ms * 1e-3)
+        pbytes = _pcg_alg_bytes_per_dof_update(pN, pw["p"])
+        pach = pbytes * pdof * ksteps / (ms * 1e-3)
         out["pcg"] = {
             "workload": "128x128 mapped elements (X = x + 0.05 sin(2 pi x) sin(2 pi y), same for Y), "
                         "N=12, p=5, c^2 = 1 + 0.5 g (clipped smooth random field, length 0.1), upwind, "
@@ -510,8 +537,14 @@ def main():
             "value": pdof * ksteps / (ms * 1e-3), "unit": "DOF-updates/s", "dtype": "f64",
             "mean_it_S": its["mean_it_S"], "mean_it_M": its["mean_it_M"],
             "max_it_S": its["max_it_S"], "max_it_M": its["max_it_M"],
-            "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": 78.6,
-                         "unit": "TFLOP/s", "frac": flops / 78.6e12, "traffic": None,
+            "roofline": {"bound": "hbm", "achieved": pach / 1e9, "peak": HBM_PEAK / 1e9,
+                         "unit": "GB/s", "frac": pach / HBM_PEAK,
+                         "traffic": PCG_STAGE_TRAFFIC,
+                         "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
+                         "alg_bytes_per_dof_update": pbytes,
+                         "alg_bytes_per_launch": pbytes * pdof / 4,
+                         "avg_launch_us": ms * 1e3 / (4 * ksteps),
+                         "alu_achieved_tflops": flops / 1e12, "alu_frac_fp64": flops / 78.6e12,
                          "kernel": "k_pcg_stage_group<*,717> (4 stage variants; N+1 = 13, p = 5, operator in registers)"},
             "mixed": {"ms_per_step": msm / ksteps, "value": pdof * ksteps / (msm * 1e-3),
                       "speedup_vs_fp64": ms / msm, "mean_it_S": itm["mean_it_S"],
