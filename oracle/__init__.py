@@ -17,6 +17,9 @@ equations", arXiv:2105.01722, that it follows):
                  equation with the (alpha, beta, tau) fluxes (Sec. 2.2,
                  Sec. 2.2.1) on periodic Cartesian element grids, dense direct
                  local solves, classical RK4, discrete energy.
+* ``dg3d``    -- the same semi-discretisation on box elements in three dimensions
+                 (Sec. 2.2 and the d = 3 Kronecker forms of Sec. 3.1, Sec. 3.2).
+* ``analysis`` -- Bloch (dispersion) analysis of the scheme (Sec. 4).
 * ``general`` -- the same weak form on mapped elements with a variable c^2
                  (Sec. 7.1 and the mapped case the paper names there),
                  assembled by Gauss-Legendre quadrature, dense direct solves.
