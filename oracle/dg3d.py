@@ -175,20 +175,20 @@ def lifts(U, V, ops):
         su, sv = face_sigmas(tr[f][0], tr[f][1], nb[f][0], nb[f][1],
                              face_alphas(prob, f)[..., None, None], beta, tau)
         if f in ("E", "W"):          # face arrays [iz, iy]
-            mu = np.einsum("ac,bd,...cd->...ab", Mz, My, su)
-            mv = np.einsum("ac,bd,...cd->...ab", Mz, My, sv)
+            mu = np.einsum("ac,bd,...cd->...ab", Mz, My, su, optimize=True)
+            mv = np.einsum("ac,bd,...cd->...ab", Mz, My, sv, optimize=True)
             d = ops.dRx if f == "E" else -ops.dLx
             Fu += c2 * np.einsum("i,...zy->...zyi", d, mu)
             Fv[..., :, :, -1 if f == "E" else 0] += c2 * mv
         elif f in ("N", "S"):        # face arrays [iz, ix]
-            mu = np.einsum("ac,bd,...cd->...ab", Mz, Mx, su)
-            mv = np.einsum("ac,bd,...cd->...ab", Mz, Mx, sv)
+            mu = np.einsum("ac,bd,...cd->...ab", Mz, Mx, su, optimize=True)
+            mv = np.einsum("ac,bd,...cd->...ab", Mz, Mx, sv, optimize=True)
             d = ops.dRy if f == "N" else -ops.dLy
             Fu += c2 * np.einsum("j,...zx->...zjx", d, mu)
             Fv[..., :, -1 if f == "N" else 0, :] += c2 * mv
         else:                        # face arrays [iy, ix]
-            mu = np.einsum("ac,bd,...cd->...ab", My, Mx, su)
-            mv = np.einsum("ac,bd,...cd->...ab", My, Mx, sv)
+            mu = np.einsum("ac,bd,...cd->...ab", My, Mx, su, optimize=True)
+            mv = np.einsum("ac,bd,...cd->...ab", My, Mx, sv, optimize=True)
             d = ops.dRz if f == "T" else -ops.dLz
             Fu += c2 * np.einsum("k,...yx->...kyx", d, mu)
             Fv[..., -1 if f == "T" else 0, :, :] += c2 * mv
@@ -198,8 +198,9 @@ def lifts(U, V, ops):
 def apply_S3(U, ops):
     """(S_x (x) M_y (x) M_z + M_x (x) S_y (x) M_z + M_x (x) M_y (x) S_z) U per element."""
     e = "ka,jb,ic,...abc->...kji"
-    return (np.einsum(e, ops.Mz, ops.My, ops.Sx, U) + np.einsum(e, ops.Mz, ops.Sy, ops.Mx, U)
-            + np.einsum(e, ops.Sz, ops.My, ops.Mx, U))
+    return (np.einsum(e, ops.Mz, ops.My, ops.Sx, U, optimize=True)
+            + np.einsum(e, ops.Mz, ops.Sy, ops.Mx, U, optimize=True)
+            + np.einsum(e, ops.Sz, ops.My, ops.Mx, U, optimize=True))
 
 
 def rhs(U, V, ops):
