@@ -17,8 +17,11 @@
  *    Hx = Lx/nx, Hy = Ly/ny.  Node (ix, iy), 0 <= ix, iy <= N, of element e sits at
  *    (x0 + ex*Hx + ix*Hx/N, y0 + ey*Hy + iy*Hy/N) and is stored at flat offset
  *    e*(N+1)^2 + iy*(N+1) + ix.  Face nodes are duplicated per element (DG).
+ *  - 3D (desc.dim = 3): element e = (ez*ny + ey)*nx + ex adds [z0 + ez*Hz, ...] and node
+ *    (ix, iy, iz) is stored at e*(N+1)^3 + (iz*(N+1) + iy)*(N+1) + ix; faces T / B are the
+ *    z = R / z = L sides; the path is the constant-coefficient Cartesian one only.
  *  - Every nodal array passed in or out is a contiguous FP64 array of
- *    nx*ny*(N+1)^2 entries in DEVICE memory (hipMalloc'd or a torch CUDA tensor's
+ *    nx*ny*(N+1)^2 (3D: nx*ny*nz*(N+1)^3) entries in DEVICE memory (hipMalloc'd or a torch CUDA tensor's
  *    data_ptr), whatever the precision mode.  The library copies inputs into its own
  *    workspaces and never keeps a caller pointer.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every call
@@ -101,6 +104,10 @@ typedef struct {
   int pcg_maxit;       /* PCG iteration limit per element solve (<= 0: 200)                   */
   int bc[4];           /* gdw_bc of the sides x = x0 + Lx (E), x = x0 (W), y = y0 + Ly (N),
                           y = y0 (S); all zero: periodic in x and y                            */
+  int dim;             /* 2 (or 0) or 3: box elements nx x ny x nz (Sec. 2.2 with d = 3)       */
+  int nz;              /* 3D: elements in z                                                    */
+  double z0, Lz;       /* 3D: the box's z range [z0, z0 + Lz]                                  */
+  int bcz[2];          /* 3D: gdw_bc of the sides z = z0 + Lz (T), z = z0 (B)                  */
 } gdw_desc;
 
 typedef struct gdw_ctx gdw_ctx;   /* opaque; owns every device workspace */
@@ -116,7 +123,9 @@ const char* gdw_last_error(void);
  * S_j psi = lambda M_j psi with psi^T M_j psi = 1 (Sec. 3.2) in FP64 on the device.
  * Errors: EINVAL for a NULL pointer, p even or < 1, N < p, N + 1 > 32, nx or ny < 1, a
  * non-positive length, c2 or xi, an unknown enum, solver FDM with a variable
- * coefficient or a mapped mesh, a direction periodic on one side only; EUNSUPPORTED
+ * coefficient or a mapped mesh, a direction periodic on one side only, dim not 0, 2 or
+ * 3, or in 3D nz < 1 or Lz <= 0; EUNSUPPORTED in 3D for (N + 1)^3 > 1024 (one thread per
+ * modal index of an element) or anything but the constant-coefficient Cartesian path, and
  * for the PCG path with p > 7 or an element operator that does not fit the 160 KiB of
  * LDS of a workgroup, and for the PCG path in GDW_MIXED_FP32 with N + 1 outside
  * {9, 13, 17}; ENOMEM / EHIP from the device.  Uses the current HIP device;
@@ -149,7 +158,7 @@ gdw_status gdw_set_state(gdw_ctx* ctx, const double* U, const double* V, void* s
  * back to back, each at every node (device FP64, layout above); each g_k is represented
  * by its GD interpolant, like the initial data, so its load vector is M g_k (M_J g_k on
  * mapped elements) and it adds sum_k s_k(t) g_k to dv/dt (on the FDM path as the modal
- * coefficients of Sec. 3.2, computed here once).  RK4 evaluates the weights s_k at the
+ * coefficients of Sec. 3.2, computed here once).  2D only (EUNSUPPORTED in 3D).  RK4 evaluates the weights s_k at the
  * stage times t, t + dt/2, t + dt/2, t + dt: before each step a one-lane kernel computes
  * the step's weights from a device clock and advances it (also inside a batch's captured
  * step).
@@ -292,7 +301,8 @@ gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* strea
 typedef struct gdw_batch gdw_batch;
 
 /* Create the batch; 1 <= nprob <= 4096.  Errors: those of gdw_create for a problem
- * (the message names it); nothing is left allocated on error. */
+ * (the message names it), EUNSUPPORTED for a 3D problem; nothing is left allocated on
+ * error. */
 gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_batch** out);
 
 /* Context of problem i, owned by the batch: set its coefficients and state, read its

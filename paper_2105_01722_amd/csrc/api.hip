@@ -35,7 +35,7 @@ static void free_all(gdw_ctx* c) {
   for (auto& r : c->Y) for (auto& p : r) F(p);
   F(c->tr[0]); F(c->tr[1]); F(c->invL); F(c->lam); F(c->gh); F(c->frc); F(c->t_dev);
   F(c->y64[0]); F(c->y64[1]);
-  F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->epart); F(c->nonfinite);
+  F(c->Psx); F(c->Psy); F(c->Px); F(c->Py); F(c->Psz); F(c->Pz); F(c->epart); F(c->nonfinite);
   for (auto& p : c->own) F(p);
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
   F(c->el.Sreg); F(c->el.Mreg); F(c->el.msc);
@@ -88,6 +88,30 @@ static gdw_status validate(const gdw_desc* d) {
     set_error("a direction is periodic on both of its sides or on neither"); return GDW_EINVAL;
   }
   const bool pcg = d->solver == GDW_SOLVE_PCG || general;
+  if (d->dim != 0 && d->dim != 2 && d->dim != 3) { set_error("dim must be 2 or 3"); return GDW_EINVAL; }
+  if (d->dim == 3) {
+    if (d->nz < 1) { set_error("nz must be >= 1"); return GDW_EINVAL; }
+    if (!(d->Lz > 0) || !std::isfinite(d->Lz) || !std::isfinite(d->z0)) {
+      set_error("Lz must be finite and > 0"); return GDW_EINVAL;
+    }
+    for (int k = 0; k < 2; ++k)
+      if (d->bcz[k] != GDW_BC_PERIODIC && d->bcz[k] != GDW_BC_DIRICHLET && d->bcz[k] != GDW_BC_NEUMANN) {
+        set_error("unknown boundary kind"); return GDW_EINVAL;
+      }
+    if ((d->bcz[0] == GDW_BC_PERIODIC) != (d->bcz[1] == GDW_BC_PERIODIC)) {
+      set_error("a direction is periodic on both of its sides or on neither"); return GDW_EINVAL;
+    }
+    if (pcg) {
+      set_error("3D runs on the constant-coefficient Cartesian path only"); return GDW_EUNSUPPORTED;
+    }
+    if ((d->N + 1) * (d->N + 1) * (d->N + 1) > 1024) {
+      set_error("3D needs (N + 1)^3 <= 1024 (one thread per modal index of an element)");
+      return GDW_EUNSUPPORTED;
+    }
+    if (double(d->nx) * d->ny * d->nz * (d->N + 1) * (d->N + 1) * (d->N + 1) > 4.0e9) {
+      set_error("problem too large"); return GDW_EINVAL;
+    }
+  }
   if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
   if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
@@ -230,6 +254,73 @@ static gdw_status create_fdm(const gdw_desc* d, gdw_ctx* c) {
   return GDW_OK;
 }
 
+
+// Box elements in 3D: the same tables per direction, face tables of the six faces
+// [12][n1] (gE hE gW hW from x, gN hN gS hS from y, gT hT gB hB from z), Lambda over the
+// three modal indices (Sec. 3.2 with d = 3).
+static gdw_status create_fdm3(const gdw_desc* d, gdw_ctx* c) {
+  const int N = d->N, p = d->p, n1 = N + 1, n2 = n1 * n1, n3 = n2 * n1;
+  std::vector<double> Ps[3], lm[3], Mm[3], dL[3], dR[3];
+  const double H[3] = {d->Lx / d->nx, d->Ly / d->ny, d->Lz / d->nz};
+  gdw_status s;
+  for (int k = 0; k < 3; ++k)
+    if ((s = eigen_dir(N, p, H[k], Ps[k], lm[k], Mm[k], dL[k], dR[k])) != GDW_OK) return s;
+  std::vector<double> gh(12 * n1), invL(n3), lam(n3), P[3];
+  for (int dir = 0; dir < 3; ++dir) {
+    for (int k = 0; k < n1; ++k) {
+      double gR = 0, gL = 0;
+      for (int i = 0; i < n1; ++i) {
+        gR += dR[dir][i] * Ps[dir][i * n1 + k];
+        gL -= dL[dir][i] * Ps[dir][i * n1 + k];
+      }
+      gh[(4 * dir + 0) * n1 + k] = gR; gh[(4 * dir + 1) * n1 + k] = Ps[dir][N * n1 + k];
+      gh[(4 * dir + 2) * n1 + k] = gL; gh[(4 * dir + 3) * n1 + k] = Ps[dir][0 * n1 + k];
+    }
+    P[dir].resize(n2);
+    for (int k = 0; k < n1; ++k)
+      for (int i = 0; i < n1; ++i) {
+        double sum = 0;
+        for (int j = 0; j < n1; ++j) sum += Ps[dir][j * n1 + k] * Mm[dir][j * n1 + i];
+        P[dir][k * n1 + i] = sum;
+      }
+  }
+  for (int kz = 0; kz < n1; ++kz)
+    for (int ky = 0; ky < n1; ++ky)
+      for (int kx = 0; kx < n1; ++kx) {
+        const int i = (kz * n1 + ky) * n1 + kx;
+        const double l = lm[0][kx] + lm[1][ky] + lm[2][kz];
+        lam[i] = l;
+        invL[i] = i == 0 ? 1.0 : 1.0 / l;
+      }
+  if ((s = upload_tables(c, gh, invL, lam)) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Psx, Ps[0])) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Psy, Ps[1])) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Psz, Ps[2])) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Px, P[0])) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Py, P[1])) != GDW_OK) return s;
+  if ((s = upload_as<double>((void**)&c->Pz, P[2])) != GDW_OK) return s;
+  const size_t field = (size_t)c->nel * n3 * c->elem_bytes;
+  for (int r = 0; r < 3; ++r)
+    for (auto& ptr : c->Y[r]) {
+      if (r == 0 && c->elem_bytes == 4) continue;   // FP32 storage: y is y64
+      GDW_HIP(hipMalloc(&ptr, field));
+      GDW_HIP(hipMemset(ptr, 0, field));
+    }
+  if (c->elem_bytes == 4)
+    for (auto& ptr : c->y64) {
+      GDW_HIP(hipMalloc(&ptr, (size_t)c->nel * n3 * sizeof(double)));
+      GDW_HIP(hipMemset(ptr, 0, (size_t)c->nel * n3 * sizeof(double)));
+    }
+  const size_t trb = (size_t)c->nel * 12 * n2 * c->elem_bytes;
+  for (auto& t : c->tr) {
+    GDW_HIP(hipMalloc(&t, trb));
+    GDW_HIP(hipMemset(t, 0, trb));
+  }
+  GDW_HIP(hipMalloc(&c->epart, (c->npart + 1) * sizeof(double)));
+  GDW_HIP(hipMalloc(&c->nonfinite, sizeof(unsigned int)));
+  GDW_HIP(hipDeviceSynchronize());
+  return GDW_OK;
+}
 
 // ---------------------------------------------------------------------------------
 // PCG path set-up
@@ -409,18 +500,21 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
 static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
   c->d = *d;
   c->n1 = d->N + 1;
-  c->nel = (long)d->nx * d->ny;
+  c->dim = d->dim == 3 ? 3 : 2;
+  c->nel = (long)d->nx * d->ny * (c->dim == 3 ? d->nz : 1);
+  c->nn = c->n1 * c->n1 * (c->dim == 3 ? c->n1 : 1);
   c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
   // alternating flux: v* from the element on the low-coordinate side of a face, (grad u)*
   // from the one on the high side, i.e. alpha = 1 on an element's E and N faces and 0 on
   // its W and S faces (wall faces take 1/2 in the kernels)
   const bool alt = d->flux == GDW_FLUX_ALTERNATING;
-  c->alf[0] = c->alf[2] = alt ? 1.0 : 0.5;
-  c->alf[1] = c->alf[3] = alt ? 0.0 : 0.5;
+  c->alf[0] = c->alf[2] = c->alf[4] = alt ? 1.0 : 0.5;
+  c->alf[1] = c->alf[3] = c->alf[5] = alt ? 0.0 : 0.5;
   c->beta = d->flux == GDW_FLUX_UPWIND ? 0.5 * d->xi : 0.0;
   c->tau = d->flux == GDW_FLUX_UPWIND ? 0.5 / d->xi : 0.0;
   const bool pcg = d->solver == GDW_SOLVE_PCG || d->coeff_variable || d->mapped;
   c->solver = pcg ? GDW_SOLVE_PCG : GDW_SOLVE_FDM;
+  if (c->dim == 3) return create_fdm3(d, c);
   return pcg ? create_pcg(d, c) : create_fdm(d, c);
 }
 
@@ -480,9 +574,14 @@ static hipError_t set_state_t(gdw_ctx* c, const double* U, const double* V, hipS
   // FP64 storage: y = Y[0]; FP32 storage: y is the FP64 register y64 (traces in FP32)
   double* yu = sizeof(T) == 8 ? (double*)c->Y[0][0] : c->y64[0];
   double* yv = sizeof(T) == 8 ? (double*)c->Y[0][1] : c->y64[1];
+  c->trc = 0;
+  if (c->dim == 3) {
+    if ((e = launch_to_modal3<double>(U, yu, c->Px, c->Py, c->Pz, c->n1, c->nel, st)) != hipSuccess) return e;
+    if ((e = launch_to_modal3<double>(V, yv, c->Px, c->Py, c->Pz, c->n1, c->nel, st)) != hipSuccess) return e;
+    return launch_traces3<double, T>(yu, yv, (const double*)c->gh, (T*)c->tr[0], c->n1, c->nel, st);
+  }
   if ((e = launch_to_modal<double>(U, yu, c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
   if ((e = launch_to_modal<double>(V, yv, c->Px, c->Py, c->n1, c->nel, st)) != hipSuccess) return e;
-  c->trc = 0;
   return launch_traces<double, T>(yu, yv, (const double*)c->gh, (T*)c->tr[0], c->n1, c->nel, st);
 }
 
@@ -515,6 +614,7 @@ extern "C" gdw_status gdw_set_forcing(gdw_ctx* c, int nterms, const double* g_no
                                       const double* omega, const double* phase, void* stream) {
   if (!c) { set_error("ctx is NULL"); return GDW_EINVAL; }
   if (nterms < 0 || nterms > 4) { set_error("nterms must be in 0..4"); return GDW_EINVAL; }
+  if (c->dim == 3) { set_error("source terms are not offered in 3D"); return GDW_EUNSUPPORTED; }
   if (nterms > 0 && (!g_nodal || !omega || !phase)) { set_error("NULL argument"); return GDW_EINVAL; }
   for (int k = 0; k < nterms; ++k)
     if (!std::isfinite(omega[k]) || !std::isfinite(phase[k])) {
@@ -624,14 +724,17 @@ StageArgs<T> fdm_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.n1 = c->n1;
   a.dt = dt;
   a.c2 = c->d.c2;
-  for (int k = 0; k < 4; ++k) a.alf[k] = c->alf[k];
+  for (int k = 0; k < 6; ++k) a.alf[k] = c->alf[k];
   a.beta = c->beta;
   a.tau = c->tau;
   a.invL = (const double*)c->invL;
   a.lam = (const double*)c->lam;
   a.gh = (const double*)c->gh;
+  a.nz = c->dim == 3 ? c->d.nz : 1;
   a.bcbits = 0;
   for (int k = 0; k < 4; ++k) a.bcbits |= (c->d.bc[k] & 3) << (2 * k);
+  if (c->dim == 3)
+    for (int k = 0; k < 2; ++k) a.bcbits |= (c->d.bcz[k] & 3) << (2 * (4 + k));
   a.nf = c->nf;
   a.frc = (const T*)c->frc;
   a.frc_stride = c->nel * (long)c->n1 * c->n1;
@@ -701,7 +804,9 @@ static hipError_t run_t(gdw_ctx* c, double dt, int steps, hipStream_t st) {
     if (c->nf > 0 && (e = launch_source_step(c->t_dev, c->t_dev + 1, dt, src, st)) != hipSuccess)
       return e;
     for (int k = 0; k < 4; ++k)
-      if ((e = launch_stage<T>(k + 1, a[k], st)) != hipSuccess) return e;
+      if ((e = c->dim == 3 ? launch_stage3<T>(k + 1, a[k], st) : launch_stage<T>(k + 1, a[k], st)) !=
+          hipSuccess)
+        return e;
     c->t += dt;
   }
   return hipSuccess;
@@ -763,6 +868,11 @@ extern "C" gdw_status gdw_get_state(gdw_ctx* c, double* U, double* V, void* stre
     const size_t nodal = (size_t)c->nel * c->g.nn * sizeof(double);
     GDW_HIP(hipMemcpyAsync(U, c->Y[0][0], nodal, hipMemcpyDeviceToDevice, st));
     GDW_HIP(hipMemcpyAsync(V, c->Y[0][1], nodal, hipMemcpyDeviceToDevice, st));
+  } else if (c->dim == 3) {
+    const double* yu = c->elem_bytes == 8 ? (const double*)c->Y[0][0] : c->y64[0];
+    const double* yv = c->elem_bytes == 8 ? (const double*)c->Y[0][1] : c->y64[1];
+    GDW_HIP(launch_to_nodal3<double>(yu, U, c->Psx, c->Psy, c->Psz, c->n1, c->nel, st));
+    GDW_HIP(launch_to_nodal3<double>(yv, V, c->Psx, c->Psy, c->Psz, c->n1, c->nel, st));
   } else if (c->elem_bytes == 8) {
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][0], U, c->Psx, c->Psy, c->n1, c->nel, st));
     GDW_HIP(launch_to_nodal<double>((const double*)c->Y[0][1], V, c->Psx, c->Psy, c->n1, c->nel, st));
@@ -787,7 +897,7 @@ extern "C" gdw_status gdw_energy(gdw_ctx* c, double* E_host, void* stream) {
     GDW_HIP(launch_energy<double>(f64 ? (const double*)c->Y[0][0] : c->y64[0],
                                   f64 ? (const double*)c->Y[0][1] : c->y64[1],
                                   (const double*)c->lam, c->d.c2,
-                                  c->n1, c->nel, c->epart, c->npart, out, st));
+                                  c->nn, c->nel, c->epart, c->npart, out, st));
   }
   GDW_HIP(hipMemcpyAsync(E_host, out, sizeof(double), hipMemcpyDeviceToHost, st));
   GDW_HIP(hipStreamSynchronize(st));
@@ -800,12 +910,12 @@ extern "C" gdw_status gdw_get_stats(gdw_ctx* c, gdw_stats* out, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   std::memset(out, 0, sizeof(*out));
   out->steps_taken = c->steps_taken;
-  out->dof_updates = c->steps_taken * c->nel * (long long)c->n1 * c->n1;
+  out->dof_updates = c->steps_taken * c->nel * (long long)c->nn;
   out->n1 = c->n1;
   out->precision = c->d.precision;
   out->solver = c->solver;
   out->fail_elem = -1;
-  const long n = c->nel * (long)c->n1 * c->n1;
+  const long n = c->nel * (long)c->nn;
   GDW_HIP(hipMemsetAsync(c->nonfinite, 0, sizeof(unsigned int), st));
   for (int f = 0; f < 2; ++f) {
     const double* y = (c->solver == GDW_SOLVE_PCG || c->elem_bytes == 8) ? (const double*)c->Y[0][f]

@@ -382,6 +382,11 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
   if (!b) { set_error("host allocation failed"); return GDW_ENOMEM; }
   gdw_status s = GDW_OK;
   for (int i = 0; i < nprob && s == GDW_OK; ++i) {
+    if (descs[i].dim == 3) {
+      set_error("problem " + std::to_string(i) + ": 3D problems are not batched");
+      s = GDW_EUNSUPPORTED;
+      break;
+    }
     gdw_ctx* c = nullptr;
     s = gdw_create(&descs[i], &c);
     if (s == GDW_OK) b->ctx.push_back(c);

@@ -26,9 +26,11 @@ static constexpr int kFailNone = 0x7f7f7f7f;
 struct gdw_ctx {
   gdw_desc d{};
   int n1 = 0;
+  int dim = 2;                 // 2 or 3
+  int nn = 0;                  // nodes per element, n1^dim
   long nel = 0;
   size_t elem_bytes = 0;       // sizeof(T) of the time-loop arithmetic
-  double alf[4] = {0, 0, 0, 0};   // alpha of the E, W, N, S faces (Sec. 2.2.1)
+  double alf[6] = {0, 0, 0, 0, 0, 0};   // alpha of the E, W, N, S, T, B faces (Sec. 2.2.1)
   double beta = 0, tau = 0;
   // device buffers (time-loop type T)
   void* Y[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
@@ -42,6 +44,8 @@ struct gdw_ctx {
   double* Psy = nullptr;
   double* Px = nullptr;
   double* Py = nullptr;
+  double* Psz = nullptr;       // 3D: the z direction's tables
+  double* Pz = nullptr;
   double* epart = nullptr;     // energy partial sums + result
   unsigned int* nonfinite = nullptr;
   int npart = 1024;

@@ -403,6 +403,57 @@ __device__ __forceinline__ void st_state(T* p, T v) {
   else *p = v;
 }
 
+// The RK stage update of one modal coefficient g (both register schemes above): stores
+// what the stage writes and returns the new stage value (su, sv), whose traces go to the
+// next stage.  (ru, rv, xu, xv): the loaded in / aux words; (yu, yv): y in FP64 (FP32
+// storage only); (ub, vb): the stage value the right-hand side (ku, kv) was evaluated at.
+template <typename T, int STAGE>
+__device__ __forceinline__ void rk_stage_store(const StageArgs<T>& a, long g, T ru, T rv, T xu,
+                                               T xv, double yu, double yv, double ub, double vb,
+                                               double ku, double kv, double& su, double& sv) {
+  constexpr bool MIX = sizeof(T) == 4;
+  using R = double;
+  const R dt = a.dt;
+  if constexpr (MIX) {
+    if (STAGE == 4) {          // ru = dY4, xu = A
+      const R h6 = dt * (1.0 / 6.0);
+      su = yu + ((R)xu + (R)ru) * (1.0 / 3.0) + h6 * ku;
+      sv = yv + ((R)xv + (R)rv) * (1.0 / 3.0) + h6 * kv;
+      st_state(&a.y64_u[g], su);
+      st_state(&a.y64_v[g], sv);
+    } else {
+      const R w = STAGE == 3 ? dt : R(0.5) * dt;
+      const T nu = (T)(w * ku), nv = (T)(w * kv);     // the stored increment
+      st_state(&a.out_u[g], nu);
+      st_state(&a.out_v[g], nv);
+      if (STAGE == 2) {        // ru = dY2
+        st_state(&a.acc_u[g], (T)((R)ru + R(2) * (R)nu));
+        st_state(&a.acc_v[g], (T)((R)rv + R(2) * (R)nv));
+      }
+      su = yu + (R)nu;
+      sv = yv + (R)nv;
+    }
+  } else {
+    if (STAGE == 1) {          // the input is y itself
+      su = ub + R(0.5) * dt * ku;
+      sv = vb + R(0.5) * dt * kv;
+    } else if (STAGE == 2) {   // xu, xv = y
+      su = (R)xu + R(0.5) * dt * ku;
+      sv = (R)xv + R(0.5) * dt * kv;
+      st_state(&a.acc_u[g], (T)(ub + R(2) * su - (R)xu));
+      st_state(&a.acc_v[g], (T)(vb + R(2) * sv - (R)xv));
+    } else if (STAGE == 3) {   // xu, xv = y
+      su = (R)xu + dt * ku;
+      sv = (R)xv + dt * kv;
+    } else {                   // xu, xv = accumulator
+      su = ((R)xu + ub) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * ku;
+      sv = ((R)xv + vb) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * kv;
+    }
+    st_state(&a.out_u[g], (T)su);
+    st_state(&a.out_v[g], (T)sv);
+  }
+}
+
 // FRC: the source term is present (a.nf > 0); without it the kernel is compiled as
 // if it did not exist.
 template <typename T, int STAGE, int N1C, int EPB, bool FRC = false>
@@ -502,7 +553,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
   __syncthreads();
 
   // Phase B: modal right-hand side and the RK stage update
-  const R dt = a.dt, c2 = a.c2;
+  const R c2 = a.c2;
 #pragma unroll
   for (int l = 0; l < EPB; ++l) {
     if (l >= ne) break;
@@ -527,44 +578,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, long tile) {
         if (k < a.nf) kv += a.fw[4 * (STAGE - 1) + k] * (R)a.frc[k * a.frc_stride + g];
     }
     R su, sv;     // the new stage value (its traces go to the next stage)
-    if constexpr (MIX) {
-      if (STAGE == 4) {          // ru = dY4, xu = A
-        const R h6 = dt * (1.0 / 6.0);
-        su = yu[l] + ((R)xu[l] + (R)ru[l]) * (1.0 / 3.0) + h6 * ku;
-        sv = yv[l] + ((R)xv[l] + (R)rv[l]) * (1.0 / 3.0) + h6 * kv;
-        st_state(&a.y64_u[g], su);
-        st_state(&a.y64_v[g], sv);
-      } else {
-        const R w = STAGE == 3 ? dt : R(0.5) * dt;
-        const T nu = (T)(w * ku), nv = (T)(w * kv);     // the stored increment
-        st_state(&a.out_u[g], nu);
-        st_state(&a.out_v[g], nv);
-        if (STAGE == 2) {        // ru = dY2
-          st_state(&a.acc_u[g], (T)((R)ru[l] + R(2) * (R)nu));
-          st_state(&a.acc_v[g], (T)((R)rv[l] + R(2) * (R)nv));
-        }
-        su = yu[l] + (R)nu;
-        sv = yv[l] + (R)nv;
-      }
-    } else {
-      if (STAGE == 1) {          // the input is y itself
-        su = ub + R(0.5) * dt * ku;
-        sv = vb + R(0.5) * dt * kv;
-      } else if (STAGE == 2) {   // xu, xv = y
-        su = xu[l] + R(0.5) * dt * ku;
-        sv = xv[l] + R(0.5) * dt * kv;
-        st_state(&a.acc_u[g], (T)(ub + R(2) * su - xu[l]));
-        st_state(&a.acc_v[g], (T)(vb + R(2) * sv - xv[l]));
-      } else if (STAGE == 3) {   // xu, xv = y
-        su = xu[l] + dt * ku;
-        sv = xv[l] + dt * kv;
-      } else {                   // xu, xv = accumulator
-        su = (xu[l] + ub) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * ku;
-        sv = (xv[l] + vb) * R(1.0 / 3.0) + dt * R(1.0 / 6.0) * kv;
-      }
-      st_state(&a.out_u[g], (T)su);
-      st_state(&a.out_v[g], (T)sv);
-    }
+    rk_stage_store<T, STAGE>(a, g, ru[l], rv[l], xu[l], xv[l], yu[l], yv[l], ub, vb, ku, kv, su,
+                             sv);
     snew[(l * 2) * nn + tid] = su;
     snew[(l * 2 + 1) * nn + tid] = sv;
   }
@@ -801,10 +816,10 @@ int stage_group_occupancy(int stage, int n1, int epb) {
 }
 
 template <typename T>
-hipError_t launch_energy(const T* Ub, const T* Vb, const double* lam, double c2, int n1, long nel,
+hipError_t launch_energy(const T* Ub, const T* Vb, const double* lam, double c2, int nn, long nel,
                          double* part, int npart, double* out, hipStream_t st) {
-  const long total = nel * (long)n1 * n1;
-  hipLaunchKernelGGL(k_energy_partial<T>, dim3(npart), dim3(256), 0, st, Ub, Vb, lam, c2, n1 * n1,
+  const long total = nel * (long)nn;
+  hipLaunchKernelGGL(k_energy_partial<T>, dim3(npart), dim3(256), 0, st, Ub, Vb, lam, c2, nn,
                      total, part);
   hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, part, npart, out);
   return hipGetLastError();
@@ -819,6 +834,328 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------------
+// Box elements in three dimensions (Sec. 2.2 with d = 3; Sec. 3.1 / 3.2 Kronecker forms).
+//
+// The same modal-state scheme: Psi = Psi_x (x) Psi_y (x) Psi_z, Lambda = lambda_x (+)
+// lambda_y (+) lambda_z, and the face terms are rank one per face: on the east face
+// Psi^T F_u = c^2 (Psi_x^T dR_x) (x) (modal face coefficients of sigma_u), the face
+// coefficients indexed by the two tangential modes.  Traces [e][12][n1^2]: slot 2f
+// (a) and 2f + 1 (v) of face f = E, W, N, S, T, B; the face arrays are indexed
+// [kz][ky] (E, W), [kz][kx] (N, S) and [ky][kx] (T, B).
+// Thread map: one workgroup of n1^3 threads handles EPB consecutive elements, thread t
+// owns the modal index (kx, ky, kz) = (t mod n1, (t div n1) mod n1, t div n1^2).
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline size_t stage3_lds_doubles(int n1, int epb) {
+  return (size_t)12 * n1 + (size_t)epb * 12 * n1 * n1 + (size_t)epb * 2 * n1 * n1 * n1;
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+__device__ __forceinline__ void stage_tile3(const StageArgs<T>& a, long tile) {
+  constexpr bool MIX = sizeof(T) == 4;
+  using R = double;
+  const int n1 = N1C > 0 ? N1C : a.n1;
+  const int n2 = n1 * n1, n3 = n2 * n1;
+  const int tid = threadIdx.x;                   // blockDim.x == n3
+  const int kx = tid % n1, ky = (tid / n1) % n1, kz = tid / n2;
+  extern __shared__ unsigned char smem_raw[];
+  R* sgh = reinterpret_cast<R*>(smem_raw);       // [12][n1] face tables
+  R* sig = sgh + 12 * n1;                        // [EPB][12][n2] modal face fluxes
+  R* snew = sig + EPB * 12 * n2;                 // [EPB][2][n3] new stage values
+  const long e0 = tile * EPB;
+  const int ne = (int)min((long)EPB, a.nel - e0);
+
+  T ru[EPB], rv[EPB], xu[EPB], xv[EPB];
+  R yu[EPB], yv[EPB];
+#pragma unroll
+  for (int l = 0; l < EPB; ++l) {
+    ru[l] = rv[l] = xu[l] = xv[l] = T(0);
+    yu[l] = yv[l] = R(0);
+    if (l < ne) {
+      const long g = (e0 + l) * n3 + tid;
+      if constexpr (MIX) {
+        yu[l] = ld_state(&a.y64_u[g]);
+        yv[l] = ld_state(&a.y64_v[g]);
+        if (STAGE > 1) {
+          ru[l] = ld_state(&a.in_u[g]);
+          rv[l] = ld_state(&a.in_v[g]);
+        }
+        if (STAGE == 4) {
+          xu[l] = ld_state(&a.aux_u[g]);
+          xv[l] = ld_state(&a.aux_v[g]);
+        }
+      } else {
+        ru[l] = ld_state(&a.in_u[g]);
+        rv[l] = ld_state(&a.in_v[g]);
+        if (STAGE > 1) {
+          xu[l] = ld_state(&a.aux_u[g]);
+          xv[l] = ld_state(&a.aux_v[g]);
+        }
+      }
+    }
+  }
+  const R il = a.invL[tid], lm = a.lam[tid];
+  const R gEk = a.gh[0 * n1 + kx], hEk = a.gh[1 * n1 + kx];
+  const R gWk = a.gh[2 * n1 + kx], hWk = a.gh[3 * n1 + kx];
+  const R gNk = a.gh[4 * n1 + ky], hNk = a.gh[5 * n1 + ky];
+  const R gSk = a.gh[6 * n1 + ky], hSk = a.gh[7 * n1 + ky];
+  const R gTk = a.gh[8 * n1 + kz], hTk = a.gh[9 * n1 + kz];
+  const R gBk = a.gh[10 * n1 + kz], hBk = a.gh[11 * n1 + kz];
+  for (int i = tid; i < 12 * n1; i += blockDim.x) sgh[i] = a.gh[i];
+
+  // Phase A: modal face fluxes of the six faces (Sec. 2.2.1), mirror states on walls
+  const R beta = a.beta, tau = a.tau;
+  const long nxy = (long)a.nx * a.ny;
+  for (int i = tid; i < ne * 6 * n2; i += blockDim.x) {
+    const int el = i / (6 * n2);
+    const int r = i - el * 6 * n2;
+    const int f = r / n2, j = r - f * n2;
+    const long e = e0 + el;
+    const int ez = (int)(e / nxy);
+    const int rem = (int)(e - ez * nxy);
+    const int ey = rem / a.nx, ex = rem - (rem / a.nx) * a.nx;
+    const int kf = (a.bcbits >> (2 * f)) & 3;
+    int nbx = ex, nby = ey, nbz = ez, fnb;
+    bool wall;
+    if (f == 0) { wall = ex + 1 == a.nx; nbx = wall ? 0 : ex + 1; fnb = 1; }
+    else if (f == 1) { wall = ex == 0; nbx = wall ? a.nx - 1 : ex - 1; fnb = 0; }
+    else if (f == 2) { wall = ey + 1 == a.ny; nby = wall ? 0 : ey + 1; fnb = 3; }
+    else if (f == 3) { wall = ey == 0; nby = wall ? a.ny - 1 : ey - 1; fnb = 2; }
+    else if (f == 4) { wall = ez + 1 == a.nz; nbz = wall ? 0 : ez + 1; fnb = 5; }
+    else { wall = ez == 0; nbz = wall ? a.nz - 1 : ez - 1; fnb = 4; }
+    wall = wall && kf != 0;
+    const long enb = ((long)nbz * a.ny + nby) * a.nx + nbx;
+    const T* ts = a.tr_in + e * 12 * n2 + 2 * f * n2;
+    const T* tn = wall ? ts : a.tr_in + enb * 12 * n2 + 2 * fnb * n2;
+    const R as = ts[j], vs = ts[n2 + j];
+    R an = tn[j], vn = tn[n2 + j];
+    if (wall && kf == 1) {
+      an = -an;
+      vn = -vn;
+    }
+    const R alpha = wall ? R(0.5) : (R)a.alf[f];
+    const R jv = vn - vs;
+    sig[(el * 12 + 2 * f) * n2 + j] = (R(1) - alpha) * jv - beta * (as + an);
+    sig[(el * 12 + 2 * f + 1) * n2 + j] = (R(1) - alpha) * as - alpha * an + tau * jv;
+  }
+  __syncthreads();
+
+  // Phase B: modal right-hand side and the RK stage update
+  const R c2 = a.c2;
+  const int jx = kz * n1 + ky, jy = kz * n1 + kx, jz = ky * n1 + kx;
+#pragma unroll
+  for (int l = 0; l < EPB; ++l) {
+    if (l >= ne) break;
+    const R* s = sig + l * 12 * n2;
+    R ub = (R)ru[l], vb = (R)rv[l];
+    if constexpr (MIX) {
+      ub = STAGE == 1 ? yu[l] : yu[l] + (R)ru[l];
+      vb = STAGE == 1 ? yv[l] : yv[l] + (R)rv[l];
+    }
+    const R Lu = gEk * s[0 * n2 + jx] + gWk * s[2 * n2 + jx] + gNk * s[4 * n2 + jy] +
+                 gSk * s[6 * n2 + jy] + gTk * s[8 * n2 + jz] + gBk * s[10 * n2 + jz];
+    const R Lv = hEk * s[1 * n2 + jx] + hWk * s[3 * n2 + jx] + hNk * s[5 * n2 + jy] +
+                 hSk * s[7 * n2 + jy] + hTk * s[9 * n2 + jz] + hBk * s[11 * n2 + jz];
+    const R ku = vb + il * Lu;
+    const R kv = c2 * (Lv - lm * ub);
+    const long g = (e0 + l) * n3 + tid;
+    R su, sv;
+    rk_stage_store<T, STAGE>(a, g, ru[l], rv[l], xu[l], xv[l], yu[l], yv[l], ub, vb, ku, kv, su,
+                             sv);
+    snew[(l * 2) * n3 + tid] = su;
+    snew[(l * 2 + 1) * n3 + tid] = sv;
+  }
+  __syncthreads();
+
+  // Phase C: modal face traces of the new state for the next stage
+  for (int i = tid; i < ne * 12 * n2; i += blockDim.x) {
+    const int el = i / (12 * n2);
+    const int r = i - el * 12 * n2;
+    const int f2 = r / n2, j = r - f2 * n2;
+    const R* F = snew + (el * 2 + (f2 & 1)) * n3;
+    const R* gg = sgh + f2 * n1;
+    R acc = 0;
+    if (f2 < 4) {                 // x faces: j = kz n1 + ky, contract kx
+      for (int k = 0; k < n1; ++k) acc += gg[k] * F[j * n1 + k];
+    } else if (f2 < 8) {          // y faces: j = kz n1 + kx, contract ky
+      const int jz_ = j / n1, jx_ = j - jz_ * n1;
+      for (int k = 0; k < n1; ++k) acc += gg[k] * F[(jz_ * n1 + k) * n1 + jx_];
+    } else {                      // z faces: j = ky n1 + kx, contract kz
+      for (int k = 0; k < n1; ++k) acc += gg[k] * F[k * n2 + j];
+    }
+    a.tr_out[e0 * 12 * n2 + i] = (T)acc;
+  }
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+__global__ __launch_bounds__(1024) void k_stage3(StageArgs<T> a) {
+  stage_tile3<T, STAGE, N1C, EPB>(a, blockIdx.x);
+}
+
+// nodal -> modal on box elements: three 1D contractions through LDS (one workgroup per
+// element, any block size)
+template <typename T>
+__global__ void k_to_modal3(const double* __restrict__ U, T* __restrict__ Ub,
+                            const double* __restrict__ Px, const double* __restrict__ Py,
+                            const double* __restrict__ Pz, int n1, long nel) {
+  extern __shared__ double sh[];
+  const int n2 = n1 * n1, n3 = n2 * n1;
+  double* u = sh;
+  double* t1 = sh + n3;
+  const long e = blockIdx.x;
+  if (e >= nel) return;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) u[i] = U[e * n3 + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (iz, iy, kx)
+    const int zy = i / n1, kx = i - zy * n1;
+    double s = 0.0;
+    for (int ix = 0; ix < n1; ++ix) s += Px[kx * n1 + ix] * u[zy * n1 + ix];
+    t1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (iz, ky, kx)
+    const int iz = i / n2, ky = (i / n1) % n1, kx = i % n1;
+    double s = 0.0;
+    for (int iy = 0; iy < n1; ++iy) s += Py[ky * n1 + iy] * t1[(iz * n1 + iy) * n1 + kx];
+    u[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (kz, ky, kx)
+    const int kz = i / n2, yx = i - kz * n2;
+    double s = 0.0;
+    for (int iz = 0; iz < n1; ++iz) s += Pz[kz * n1 + iz] * u[iz * n2 + yx];
+    Ub[e * n3 + i] = (T)s;
+  }
+}
+
+// modal -> nodal: U = (Psi_z (x) Psi_y (x) Psi_x) Ubar
+template <typename T>
+__global__ void k_to_nodal3(const T* __restrict__ Ub, double* __restrict__ U,
+                            const double* __restrict__ Psx, const double* __restrict__ Psy,
+                            const double* __restrict__ Psz, int n1, long nel) {
+  extern __shared__ double sh[];
+  const int n2 = n1 * n1, n3 = n2 * n1;
+  double* u = sh;
+  double* t1 = sh + n3;
+  const long e = blockIdx.x;
+  if (e >= nel) return;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) u[i] = (double)Ub[e * n3 + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (kz, ky, ix)
+    const int zy = i / n1, ix = i - zy * n1;
+    double s = 0.0;
+    for (int kx = 0; kx < n1; ++kx) s += Psx[ix * n1 + kx] * u[zy * n1 + kx];
+    t1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (kz, iy, ix)
+    const int kz = i / n2, iy = (i / n1) % n1, ix = i % n1;
+    double s = 0.0;
+    for (int ky = 0; ky < n1; ++ky) s += Psy[iy * n1 + ky] * t1[(kz * n1 + ky) * n1 + ix];
+    u[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) {      // (iz, iy, ix)
+    const int iz = i / n2, yx = i - iz * n2;
+    double s = 0.0;
+    for (int kz = 0; kz < n1; ++kz) s += Psz[iz * n1 + kz] * u[kz * n2 + yx];
+    U[e * n3 + i] = s;
+  }
+}
+
+// modal face traces of a 3D state (set_state; the stage kernels write their own)
+template <typename S, typename T>
+__global__ void k_traces3(const S* __restrict__ Ub, const S* __restrict__ Vb,
+                          const double* __restrict__ gh, T* __restrict__ tr, int n1, long nel) {
+  const int n2 = n1 * n1, n3 = n2 * n1;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nel * 12 * n2) return;
+  const long e = i / (12 * n2);
+  const int r = (int)(i - e * 12 * n2);
+  const int f2 = r / n2, j = r - f2 * n2;
+  const S* F = ((f2 & 1) ? Vb : Ub) + e * n3;
+  const double* g = gh + f2 * n1;
+  double acc = 0;
+  if (f2 < 4) {
+    for (int k = 0; k < n1; ++k) acc += g[k] * (double)F[j * n1 + k];
+  } else if (f2 < 8) {
+    const int jz = j / n1, jx = j - jz * n1;
+    for (int k = 0; k < n1; ++k) acc += g[k] * (double)F[(jz * n1 + k) * n1 + jx];
+  } else {
+    for (int k = 0; k < n1; ++k) acc += g[k] * (double)F[k * n2 + j];
+  }
+  tr[i] = (T)acc;
+}
+
+template <typename T>
+hipError_t launch_to_modal3(const double* U, T* Ub, const double* Px, const double* Py,
+                            const double* Pz, int n1, long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  const size_t sh = 2 * (size_t)n1 * n1 * n1 * sizeof(double);
+  hipLaunchKernelGGL(k_to_modal3<T>, dim3((unsigned)nel), dim3(256), sh, st, U, Ub, Px, Py, Pz,
+                     n1, nel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_to_nodal3(const T* Ub, double* U, const double* Psx, const double* Psy,
+                            const double* Psz, int n1, long nel, hipStream_t st) {
+  if (nel == 0) return hipSuccess;
+  const size_t sh = 2 * (size_t)n1 * n1 * n1 * sizeof(double);
+  hipLaunchKernelGGL(k_to_nodal3<T>, dim3((unsigned)nel), dim3(256), sh, st, Ub, U, Psx, Psy, Psz,
+                     n1, nel);
+  return hipGetLastError();
+}
+
+template <typename S, typename T>
+hipError_t launch_traces3(const S* Ub, const S* Vb, const double* gh, T* tr, int n1, long nel,
+                          hipStream_t st) {
+  const long total = nel * 12 * n1 * n1;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_traces3<S, T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     Ub, Vb, gh, tr, n1, nel);
+  return hipGetLastError();
+}
+
+template <typename T, int STAGE, int N1C, int EPB>
+static hipError_t launch_stage3_t(const StageArgs<T>& a, hipStream_t st) {
+  const int n1 = a.n1;
+  const size_t sh = stage3_lds_doubles(n1, EPB) * sizeof(double);
+  const unsigned nblk = (unsigned)((a.nel + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_stage3<T, STAGE, N1C, EPB>), dim3(nblk), dim3(n1 * n1 * n1), sh, st, a);
+  return hipGetLastError();
+}
+
+// Elements per workgroup: 2 where the tile fits 64 KiB of LDS, else 1.
+template <typename T, int STAGE, int N1C>
+static hipError_t dispatch3_epb(const StageArgs<T>& a, hipStream_t st) {
+  if (a.n1 * a.n1 * a.n1 > 1024) return hipErrorInvalidValue;
+  if (stage3_lds_doubles(a.n1, 2) * sizeof(double) <= 65536)
+    return launch_stage3_t<T, STAGE, N1C, 2>(a, st);
+  return launch_stage3_t<T, STAGE, N1C, 1>(a, st);
+}
+
+template <typename T, int STAGE>
+static hipError_t dispatch3_n1(const StageArgs<T>& a, hipStream_t st) {
+  switch (a.n1) {
+    case 9: return dispatch3_epb<T, STAGE, 9>(a, st);
+    case 10: return dispatch3_epb<T, STAGE, 10>(a, st);
+    default: return dispatch3_epb<T, STAGE, 0>(a, st);
+  }
+}
+
+template <typename T>
+hipError_t launch_stage3(int stage, const StageArgs<T>& a, hipStream_t st) {
+  if (a.nel == 0) return hipSuccess;
+  switch (stage) {
+    case 1: return dispatch3_n1<T, 1>(a, st);
+    case 2: return dispatch3_n1<T, 2>(a, st);
+    case 3: return dispatch3_n1<T, 3>(a, st);
+    default: return dispatch3_n1<T, 4>(a, st);
+  }
+}
+
 #define GDW_INST(T)                                                                              \
   template hipError_t launch_to_modal<T>(const double*, T*, const double*, const double*, int,    \
                                          long, hipStream_t);                                     \
@@ -831,7 +1168,12 @@ hipError_t launch_count_nonfinite(const T* a, long n, unsigned int* cnt, hipStre
   template hipError_t launch_count_nonfinite<T>(const T*, long, unsigned int*, hipStream_t);       \
   template hipError_t launch_stage_group<T>(int, int, int, const StageArgs<T>*, const long*, int, \
                                             unsigned, hipStream_t);                              \
-  template int stage_group_occupancy<T>(int, int, int);
+  template int stage_group_occupancy<T>(int, int, int);                                          \
+  template hipError_t launch_to_modal3<T>(const double*, T*, const double*, const double*,        \
+                                          const double*, int, long, hipStream_t);                 \
+  template hipError_t launch_to_nodal3<T>(const T*, double*, const double*, const double*,        \
+                                          const double*, int, long, hipStream_t);                 \
+  template hipError_t launch_stage3<T>(int, const StageArgs<T>&, hipStream_t);
 
 GDW_INST(double)
 GDW_INST(float)
@@ -839,5 +1181,9 @@ template hipError_t launch_traces<double, double>(const double*, const double*, 
                                                   double*, int, long, hipStream_t);
 template hipError_t launch_traces<double, float>(const double*, const double*, const double*,
                                                  float*, int, long, hipStream_t);
+template hipError_t launch_traces3<double, double>(const double*, const double*, const double*,
+                                                   double*, int, long, hipStream_t);
+template hipError_t launch_traces3<double, float>(const double*, const double*, const double*,
+                                                  float*, int, long, hipStream_t);
 
 }  // namespace gdw

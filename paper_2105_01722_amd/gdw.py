@@ -30,7 +30,8 @@ class gdw_desc(ctypes.Structure):
                 ("flux", ctypes.c_int), ("xi", ctypes.c_double), ("precision", ctypes.c_int),
                 ("solver", ctypes.c_int), ("coeff_variable", ctypes.c_int), ("mapped", ctypes.c_int),
                 ("pcg_rtol", ctypes.c_double), ("pcg_maxit", ctypes.c_int),
-                ("bc", ctypes.c_int * 4)]
+                ("bc", ctypes.c_int * 4), ("dim", ctypes.c_int), ("nz", ctypes.c_int),
+                ("z0", ctypes.c_double), ("Lz", ctypes.c_double), ("bcz", ctypes.c_int * 2)]
 
 
 class gdw_stats(ctypes.Structure):
@@ -172,9 +173,11 @@ def gdw_destroy(ctx):
 # --- convenience wrapper -----------------------------------------------------------------
 def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", solver="auto",
               Lx=1.0, Ly=1.0, x0=0.0, y0=0.0, coeff_variable=False, mapped=False,
-              pcg_rtol=1e-12, pcg_maxit=200, bc=("periodic",) * 4):
+              pcg_rtol=1e-12, pcg_maxit=200, bc=("periodic",) * 4, nz=0, z0=0.0, Lz=1.0,
+              bcz=("periodic",) * 2):
     """A gdw_desc from keyword arguments (names as in include/gdw.h); bc: the kinds of
-    the E, W, N, S sides ("periodic", "dirichlet", "neumann" or the gdw_bc values)."""
+    the E, W, N, S sides ("periodic", "dirichlet", "neumann" or the gdw_bc values).
+    nz > 0 makes a 3D problem of nx x ny x nz box elements (bcz: the T, B sides)."""
     d = gdw_desc()
     d.nx, d.ny, d.N, d.p = nx, ny, N, p
     d.x0, d.y0, d.Lx, d.Ly = x0, y0, Lx, Ly
@@ -192,6 +195,12 @@ def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", so
         raise ValueError("bc: four side kinds (E, W, N, S)")
     for k, b in enumerate(bc):
         d.bc[k] = _BC[b] if isinstance(b, str) else int(b)
+    if nz:
+        d.dim, d.nz, d.z0, d.Lz = 3, nz, z0, Lz
+        if len(bcz) != 2:
+            raise ValueError("bcz: two side kinds (T, B)")
+        for k, b in enumerate(bcz):
+            d.bcz[k] = _BC[b] if isinstance(b, str) else int(b)
     return d
 
 
@@ -204,8 +213,13 @@ class Solver:
 
     def _attach(self, d, ctx):
         self.desc = d
-        self.shape = (d.ny, d.nx, d.N + 1, d.N + 1)
-        self.n = d.nx * d.ny * (d.N + 1) ** 2
+        if d.dim == 3:
+            self.shape = (d.nz, d.ny, d.nx, d.N + 1, d.N + 1, d.N + 1)
+        else:
+            self.shape = (d.ny, d.nx, d.N + 1, d.N + 1)
+        self.n = 1
+        for k in self.shape:
+            self.n *= k
         self._owned = ctx is None
         self.ctx = gdw_create(d) if ctx is None else ctx
 

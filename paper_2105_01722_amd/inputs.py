@@ -140,3 +140,54 @@ def batch_specs(seed=4, n_prob=64):
 def cfl_dt(N, n, cfl=0.5, L=1.0):
     """dt = CFL * h with h = L / (n N) the cell width."""
     return cfl * L / (n * N)
+
+
+# ---- box elements in 3D ----------------------------------------------------------------
+def node_coords3(nx, ny, nz, N, Lx=1.0, Ly=1.0, Lz=1.0, x0=0.0, y0=0.0, z0=0.0):
+    """Cartesian node coordinates of a 3D grid, each [nz, ny, nx, N+1 (iz), N+1 (iy),
+    N+1 (ix)], from the global node index (face copies bitwise equal)."""
+    n1 = N + 1
+    gx = (np.arange(nx)[:, None] * N + np.arange(n1)[None, :]) * (Lx / (nx * N)) + x0
+    gy = (np.arange(ny)[:, None] * N + np.arange(n1)[None, :]) * (Ly / (ny * N)) + y0
+    gz = (np.arange(nz)[:, None] * N + np.arange(n1)[None, :]) * (Lz / (nz * N)) + z0
+    shp = (nz, ny, nx, n1, n1, n1)
+    X = np.broadcast_to(gx[None, None, :, None, None, :], shp)
+    Y = np.broadcast_to(gy[None, :, None, None, :, None], shp)
+    Z = np.broadcast_to(gz[:, None, None, :, None, None], shp)
+    return X, Y, Z
+
+
+def fourier_modes3(seed, n_modes=8, kmax=8):
+    """(kx, ky, kz, a, theta) for n_modes modes, |k| <= kmax, k != 0, a ~ N(0,1)/|k|^2,
+    theta ~ U[0, 2 pi) (the 3D analogue of fourier_modes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = range(-kmax, kmax + 1)
+    ks = [(i, j, k) for i in r for j in r for k in r if 0 < i * i + j * j + k * k <= kmax * kmax]
+    out = []
+    for _ in range(n_modes):
+        kx, ky, kz = ks[int(rng.integers(len(ks)))]
+        a = float(rng.standard_normal()) / float(kx * kx + ky * ky + kz * kz)
+        th = float(rng.uniform(0.0, 2 * np.pi))
+        out.append((kx, ky, kz, a, th))
+    return out
+
+
+def fourier_field3(modes, X, Y, Z, t=0.0, c=1.0, deriv=False):
+    """sum_m a_m cos(2 pi |k_m| c t) cos(2 pi k_m . x + theta_m) on node arrays of
+    node_coords3 (deriv: its time derivative).  Evaluated per element row through the
+    separable factors, so that large grids need no full-size temporaries per mode."""
+    nz, ny, nx, n1 = X.shape[0], X.shape[1], X.shape[2], X.shape[3]
+    xs = np.asarray(X[0, 0, :, 0, 0, :])      # [nx, n1]
+    ys = np.asarray(Y[0, :, 0, 0, :, 0])      # [ny, n1]
+    zs = np.asarray(Z[:, 0, 0, :, 0, 0])      # [nz, n1]
+    out = np.zeros((nz, ny, nx, n1, n1, n1))
+    for kx, ky, kz, a, th in modes:
+        w = 2 * np.pi * np.sqrt(kx * kx + ky * ky + kz * kz) * c
+        amp = -a * w * np.sin(w * t) if deriv else a * np.cos(w * t)
+        ex = np.exp(2j * np.pi * kx * xs)     # [nx, n1]
+        ey = np.exp(2j * np.pi * ky * ys)
+        ez = np.exp(2j * np.pi * kz * zs) * np.exp(1j * th)
+        # [nz, ny, nx, iz, iy, ix]
+        out += amp * np.real(ez[:, None, None, :, None, None] * ey[None, :, None, None, :, None]
+                             * ex[None, None, :, None, None, :])
+    return out

@@ -156,3 +156,28 @@ def test_bench_refuses_several_gpus_before_touching_a_device():
                          cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 2
     assert "one GPU" in out.stderr
+
+
+def test_3d_requests_outside_the_box_path_are_refused():
+    """3D runs on the constant-coefficient Cartesian path only, with (N + 1)^3 <= 1024;
+    validation refuses the rest before any device work, and a batch refuses 3D members."""
+    from paper_2105_01722_amd import gdw
+    for kw, status in ((dict(solver="pcg"), gdw.GDW_EUNSUPPORTED),
+                       (dict(coeff_variable=True), gdw.GDW_EUNSUPPORTED),
+                       (dict(N=10), gdw.GDW_EUNSUPPORTED),
+                       (dict(Lz=-1.0), gdw.GDW_EINVAL),
+                       (dict(bcz=("dirichlet", "periodic")), gdw.GDW_EINVAL)):
+        args = dict(nx=2, ny=2, N=8, p=3, nz=2)
+        args.update(kw)
+        d = gdw.make_desc(**args)
+        with pytest.raises(gdw.GdwError) as ei:
+            gdw.gdw_create(d)
+        assert ei.value.status == status, (kw, ei.value)
+    d = gdw.make_desc(nx=2, ny=2, N=8, p=3)
+    d.dim = 4
+    with pytest.raises(gdw.GdwError) as ei:
+        gdw.gdw_create(d)
+    assert ei.value.status == gdw.GDW_EINVAL
+    with pytest.raises(gdw.GdwError) as ei:
+        gdw.Batch([dict(nx=2, ny=2, N=8, p=3, nz=2)])
+    assert ei.value.status == gdw.GDW_EUNSUPPORTED
