@@ -13,7 +13,8 @@ time; inputs resident in HBM).  Also reported: the FP32-storage mode, the error 
 both against the exact solution, the roofline of the stage kernel (algorithmic HBM
 bytes per launch / measured average launch time), the variable-coefficient mapped PCG
 workload in FP64 and in mixed precision (`pcg`), the same grid as the headline with
-Dirichlet walls (`walls`), the learned preconditioner (`learned`),
+Dirichlet walls (`walls`), box elements in 3D (`fdm3d`), the learned preconditioner
+(`learned`),
 the 64-problem batch (`batch`) and the FP64 CPU oracle timed on a bounded sample on the
 host (`cpu_baseline`).
 """
@@ -124,6 +125,59 @@ def _time_walls(steps, warmup, n=256, N=16, p=5, cfl=0.15, k=4, l=3):
                         "u0 = sin(%d pi x) sin(%d pi y), v0 = 0, RK4 dt = 0.15 h" % (k, l),
             "ms_per_step": ms / steps, "value": ndof * steps / (ms * 1e-3),
             "unit": "DOF-updates/s", "dtype": "f64", "rel_err_vs_exact": err}
+
+
+def _time_3d(steps, warmup, n=48, N=8, p=3, cfl=0.12, seed=2, precision="fp64"):
+    """Box elements in 3D: the periodic unit cube, n^3 elements of N^3 GD cells, degree p,
+    upwind flux, RK4 with dt = 0.12 h (the largest stable value on the dense spectrum is
+    0.17 h), initial data 8 seeded 3D Fourier modes (|k| <= 8, amplitude N(0,1)/|k|^2),
+    v0 = 0; the error against the exact standing-wave solution is taken on every 5th
+    element in each direction."""
+    import torch
+    from paper_2105_01722_amd import gdw, inputs
+    X, Y, Z = inputs.node_coords3(n, n, n, N)
+    modes = inputs.fourier_modes3(seed)
+    U0 = torch.from_numpy(inputs.fourier_field3(modes, X, Y, Z)).cuda()
+    dt = cfl / (n * N)
+    s = gdw.Solver(n, n, N, p, nz=n, flux="upwind", xi=1.0, precision=precision)
+    s.set_state(U0, torch.zeros_like(U0))
+    del U0
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.run(dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    U, V = s.get_state()
+    s.stats()
+    s.close()
+    sl = (slice(None, None, 5),) * 3
+    T = dt * (steps + warmup)
+    Xs, Ys, Zs = X[sl], Y[sl], Z[sl]
+    Ue = inputs.fourier_field3(modes, Xs, Ys, Zs, t=T)
+    Ve = inputs.fourier_field3(modes, Xs, Ys, Zs, t=T, deriv=True)
+    Uh, Vh = U[sl].cpu().numpy(), V[sl].cpu().numpy()
+    ndof = n ** 3 * (N + 1) ** 3
+    launches = 4 * steps
+    alg = 32 * 8 * ndof / 4          # survey count per launch: 32 s per DOF-update
+    return {"workload": "3D periodic unit cube, %d^3 box elements, N=%d, p=%d, upwind, RK4 dt = "
+                        "%.2f h, 8 seeded 3D Fourier modes" % (n, N, p, cfl),
+            "dof_per_field": ndof, "steps": steps, "ms_per_step": ms / steps,
+            "value": ndof * steps / (ms * 1e-3), "unit": "DOF-updates/s",
+            "dtype": "f64" if precision == "fp64" else "f32 increments / f64 register",
+            "rel_err_vs_exact": float(np.linalg.norm(Uh - Ue) / np.linalg.norm(Ue)),
+            "rel_err_v_vs_exact": float(np.linalg.norm(Vh - Ve) / np.linalg.norm(Ve)),
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
+                         "achieved": alg / (ms * 1e-3 / launches) / 1e9,
+                         "frac": alg / (ms * 1e-3 / launches) / HBM_PEAK,
+                         "alg_bytes_per_launch": alg, "alg_bytes_per_dof_update": 256,
+                         "avg_launch_us": ms * 1e3 / launches,
+                         "kernel": "k_stage3<double,*,9,2> (4 stage variants)"}}
 
 
 def _pcg_workload(n=128, N=12, p=5, grf_seed=3, mode_seed=2):
@@ -417,6 +471,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage mode")
     ap.add_argument("--no-walls", action="store_true", help="skip the Dirichlet-wall run")
     ap.add_argument("--no-pcg", action="store_true", help="skip the variable-coefficient PCG workload")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D box-element workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems section")
     ap.add_argument("--batch-only", action="store_true",
@@ -516,6 +571,14 @@ def main():
         out["walls"]["ms_vs_periodic"] = out["walls"]["ms_per_step"] / (ms64 / args.steps)
         print("bench: walls %.3f ms/step" % out["walls"]["ms_per_step"], file=sys.stderr,
               flush=True)
+    if not args.no_3d:
+        out["fdm3d"] = _time_3d(args.steps, args.warmup)
+        out["fdm3d"]["fp32"] = _time_3d(args.steps, args.warmup, precision="fp32")
+        for k in ("workload", "dof_per_field", "steps", "roofline", "unit"):
+            out["fdm3d"]["fp32"].pop(k)
+        print("bench: 3d %.3f ms/step (fp32 %.3f)" % (out["fdm3d"]["ms_per_step"],
+                                                      out["fdm3d"]["fp32"]["ms_per_step"]),
+              file=sys.stderr, flush=True)
     if not args.no_pcg:
         pw = _pcg_workload()
         pn, pN = pw["n"], pw["N"]
