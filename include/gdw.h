@@ -282,8 +282,10 @@ gdw_status gdw_precond_data(gdw_ctx* ctx, float* samples, float* targets, void* 
  * Errors: EINVAL if the network is not 64 -> ... -> (N+1)^2 - 1 or before gdw_set_coeff. */
 gdw_status gdw_set_precond_mlp(gdw_ctx* ctx, gdw_mlp* mlp, void* stream);
 
-/* PCG path: o given directly (device FP32 [n_el][(N+1)^2 - 1]); NULL restores the plain
- * preconditioner. */
+/* PCG path: o given directly: device FP32, contiguous [n_el][(N+1)^2 - 1] with
+ * n_el = nx * ny, read in full on the given stream (the caller keeps it alive until that
+ * read has run); NULL restores the plain preconditioner.  The length cannot be checked
+ * here: a shorter buffer is an out-of-bounds device read. */
 gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* stream);
 
 /* ---------------------------------------------------------------------------------

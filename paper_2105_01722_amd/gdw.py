@@ -286,7 +286,12 @@ class Solver:
         if o is None:
             _check(lib.gdw_set_precond_log(self.ctx, None, _stream(stream)), "gdw_set_precond_log")
             return
+        d = self.desc
+        n = d.nx * d.ny * ((d.N + 1) ** 2 - 1)
         o = torch.as_tensor(o, dtype=torch.float32, device="cuda").contiguous()
+        if o.numel() != n:
+            raise ValueError("log_scale must hold nx * ny * ((N+1)^2 - 1) = %d entries, got %d"
+                             % (n, o.numel()))
         _check(lib.gdw_set_precond_log(self.ctx, ctypes.c_void_p(o.data_ptr()), _stream(stream)),
                "gdw_set_precond_log")
         torch.cuda.current_stream().synchronize()

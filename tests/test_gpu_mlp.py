@@ -133,6 +133,8 @@ def test_corrections_keep_the_solution_and_fallback():
     Uo, Vo = general.run(U0, V0, ops, dt, steps)
     Up, _, st_plain = _run(s, U0, V0, dt, steps)
     _, tgt = s.precond_data()
+    with pytest.raises(ValueError):
+        s.set_precond_log(tgt.reshape(-1)[:-1])   # one entry short: refused in the binding
     s.set_precond_log(tgt)
     Ua, _, st_exact = _run(s, U0, V0, dt, steps)
     bad = np.full(tgt.shape, np.nan, dtype=np.float32)
