@@ -40,7 +40,7 @@ static void free_all(gdw_ctx* c) {
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
   F(c->el.Sreg); F(c->el.Mreg); F(c->el.msc);
   F(c->el.w); F(c->el.sc); F(c->el.face);
-  F(c->el.dlog); F(c->xS); F(c->xM); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
+  F(c->el.dlog); F(c->xS); F(c->xM); F(c->Fu); F(c->Fv); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
 }
 
@@ -465,6 +465,10 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
     const size_t nb = (size_t)nel * pcg_reg_slots(n1, p) * c->blk_threads * sizeof(double);
     GDW_HIP(hipMalloc(&c->el.Sreg, nb));
     if (d->mapped) GDW_HIP(hipMalloc(&c->el.Mreg, nb));
+    if (pcg_split_key(pcg_family_key(n1, p, 1, 0))) {
+      GDW_HIP(hipMalloc(&c->Fu, nodal));
+      GDW_HIP(hipMalloc(&c->Fv, nodal));
+    }
   }
   GDW_HIP(hipMalloc(&c->d_pargs, 4 * sizeof(PcgStageArgs)));
   GDW_HIP(hipMalloc(&c->d_pel, 2 * sizeof(long)));
@@ -754,6 +758,8 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.el = c->el;
   a.xS = c->xS;
   a.xM = c->xM;
+  a.Fu = c->Fu;
+  a.Fv = c->Fv;
   a.its = c->its;
   a.fail = c->fail;
   a.nel = c->nel;
@@ -831,11 +837,18 @@ static hipError_t run_pcg(gdw_ctx* c, double dt, int steps, hipStream_t st) {
   }
   c->pargs_used = 1;
   const int key = pcg_group_key(c->h_pargs[0]);
+  const bool split = pcg_split_key(key) && c->Fu != nullptr;
   const SourceTerms src = source_terms(c);
   for (int s = 0; s < steps; ++s) {
     if (c->nf > 0 && (e = launch_source_step(c->t_dev, c->t_dev + 1, dt, src, st)) != hipSuccess)
       return e;
     for (int k = 0; k < 4; ++k) {
+      if (split) {
+        if ((e = launch_pcg_split_stage(k + 1, key, c->d_pargs + k, c->h_pargs[k], c->p_threads,
+                                        c->p_lds, st)) != hipSuccess)
+          return e;
+        continue;
+      }
       const unsigned grid = pcg_group_grid(k + 1, key, c->p_threads, c->p_lds, c->nel);
       if ((e = launch_pcg_stage_group(k + 1, key, c->d_pargs + k, c->d_pel, 1, grid, c->p_threads,
                                       c->p_lds, st)) != hipSuccess)

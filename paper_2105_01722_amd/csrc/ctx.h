@@ -67,6 +67,8 @@ struct gdw_ctx {
   void* own[24] = {};          // device tables of g (freed with the context)
   double* xS = nullptr;
   double* xM = nullptr;
+  double* Fu = nullptr;     // split PCG stage: lifts F_u, F_v (then r) of every element
+  double* Fv = nullptr;
   int* its = nullptr;
   int* fail = nullptr;
   double* coords = nullptr;    // Cartesian X, Y, constant c^2 when not given

@@ -61,6 +61,8 @@ struct PcgStageArgs {
   double* tr_out;
   double* xS;           // [nel][nn] warm start / solution of S_hat y = F_u
   double* xM;           // [nel][nn] warm start / solution of M_J z = r
+  double* Fu;           // split stage: [nel][nn] F_u of the lift kernel
+  double* Fv;           // split stage: [nel][nn] F_v, replaced by r = F_v - S_K U
   int* its;             // [nel][4]: sum S iterations, sum M iterations, max S, max M
   int* fail;            // smallest element id that hit maxit (0x7f7f7f7f if none)
   long nel;
@@ -137,6 +139,14 @@ int pcg_group_key(const PcgStageArgs& a);
 // Block size and LDS of a problem launched alone (sets full / Q / nnz_full of the row
 // layout); 0 if it does not fit a workgroup.
 int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds);
+// Split stage of the register-operator families (key with bit 64, FP64), one problem:
+// lifts (F_u, F_v), the S_hat solve (with r = F_v - S_K U and, on Cartesian elements, the
+// exact M_J solve), the M_J solve (mapped elements) and the RK update with the new traces.
+// a: device copy of the stage's arguments (Fu, Fv set); threads / lds from
+// pcg_single_shape.
+hipError_t launch_pcg_split_stage(int stage, int key, const PcgStageArgs* a, const PcgStageArgs& h,
+                                  int threads, size_t lds, hipStream_t st);
+bool pcg_split_key(int key);
 // Persistent grid of the grouped kernel of family `key` for nel elements.
 unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel);
 size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);

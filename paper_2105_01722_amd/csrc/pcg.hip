@@ -55,8 +55,9 @@ __device__ inline double wave_sum(double v) {
 
 // Deterministic workgroup sum of K values held by the threads t < nact (the other
 // threads pass zeros and may be anywhere in the workgroup); fixed wave order.
-// red: 16*K doubles.  Every thread returns the sums.
-template <int K>
+// red: 16*K doubles.  Every thread returns the sums.  TRAIL = false leaves out the closing
+// barrier: the caller then passes another barrier before red is written again.
+template <int K, bool TRAIL = true>
 __device__ inline void block_sum(double (&v)[K], double* red, int nact) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = (nact + 63) >> 6;
@@ -74,7 +75,7 @@ __device__ inline void block_sum(double (&v)[K], double* red, int nact) {
     for (int i = 0; i < nw; ++i) s += red[k * 16 + i];
     v[k] = s;
   }
-  __syncthreads();
+  if constexpr (TRAIL) __syncthreads();
 }
 
 // Deterministic workgroup sum of two values over all threads (fixed wave order).
@@ -700,8 +701,9 @@ __device__ __forceinline__ double sum8(double v) {
 
 // Load the element's data and form the lifts: Fu = F_u, rv = F_v (the caller subtracts
 // S_K U).  `after_first_barrier` runs once the element data are in LDS (operator load
-// overlap).  Tables from stage_tables must be in place.
-template <int STAGE, typename F>
+// overlap).  Tables from stage_tables must be in place.  NODAL = false: only the lifts (the
+// nodal state, warm starts and element scalars are not loaded).
+template <int STAGE, bool NODAL = true, typename F>
 __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long e,
                                                StageCommon& C, F&& after_first_barrier) {
   const PcgGeom& g = a.g;
@@ -723,7 +725,7 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
   }
   const double* fc = C.T.fc;
   C.ub = C.vb = C.yu = C.yv = C.xs0 = C.xm0 = C.wt = 0.0;
-  if (own) {
+  if (NODAL && own) {
     C.ub = a.in_u[e * nn + t];
     C.vb = a.in_v[e * nn + t];
     if (STAGE > 1) {
@@ -737,12 +739,14 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
     C.wt = a.el.w[e * nn + t];
     C.ms = a.el.msc ? a.el.msc[e * nn + t] : 1.0;
   }
-  const double* sc = a.el.sc + e * 8;
-  C.cw = sc[0];
-  C.kbr = sc[1];
-  C.kbs = sc[2];
-  C.d00 = sc[3];
-  C.area = sc[4];
+  if constexpr (NODAL) {
+    const double* sc = a.el.sc + e * 8;
+    C.cw = sc[0];
+    C.kbr = sc[1];
+    C.kbs = sc[2];
+    C.d00 = sc[3];
+    C.area = sc[4];
+  }
   const int ex = (int)(e % a.nx), ey = (int)(e / a.nx);
   __syncthreads();
   after_first_barrier();
@@ -838,8 +842,9 @@ __device__ __forceinline__ void stage_prologue(const PcgStageArgs& a, const long
 
 // RK stage update from dU/dt = V + y, dV/dt = z, outputs, warm starts, traces of the new
 // value and iteration counters.  Starts with a barrier-free register phase; y, z are the
-// owner thread's solution entries.
-template <int STAGE>
+// owner thread's solution entries.  SPLIT: y and z were stored by the solve kernels, which
+// also keep the counters; only the update and the traces are done here.
+template <int STAGE, bool SPLIT = false>
 __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long e,
                                                const StageCommon& C, double y, double z,
                                                int itS, int itM, int swS = 0, int swM = 0) {
@@ -873,14 +878,16 @@ __device__ __forceinline__ void stage_epilogue(const PcgStageArgs& a, const long
     }
     a.out_u[gi] = nu;
     a.out_v[gi] = nv;
-    a.xS[gi] = y;
-    a.xM[gi] = z;
+    if constexpr (!SPLIT) {
+      a.xS[gi] = y;
+      a.xM[gi] = z;
+    }
     C.U[t] = nu;
     C.V[t] = nv;
   }
   __syncthreads();
   face_traces_lds(g, C.T, C.U, C.V, C.lines, a.tr_out + e * 4 * g.nq * 2);
-  if (t == 0) {
+  if (!SPLIT && t == 0) {
     int* its = a.its + e * kItsPer;
     its[0] += itS > a.maxit ? a.maxit : itS;
     its[1] += itM > a.maxit ? a.maxit : itM;
@@ -1220,11 +1227,14 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
     __syncthreads();
     ax = apply(W.U);
   }
+  // The reductions leave out their closing barrier: every later write of red comes after
+  // the barrier that publishes R, and each return passes one barrier.
   double s2[2] = {own ? wt * x : 0.0, own ? bval * bval : 0.0};
-  block_sum<2>(s2, red, nn);
+  block_sum<2, false>(s2, red, nn);
   const double bb = s2[1];
   if (bb == 0.0) {
     x = 0.0;
+    __syncthreads();
     return 0;
   }
   double r = own ? bval - ax - cw * s2[0] * wt : 0.0;
@@ -1239,9 +1249,12 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
   }
   double q = apply(W.U);
   double s4[4] = {r * u, q * u, wt * u, r * r};
-  block_sum<4>(s4, red, nn);
+  block_sum<4, false>(s4, red, nn);
   const double tol2 = rtol * rtol * bb;
-  if (s4[3] <= tol2) return 0;
+  if (s4[3] <= tol2) {
+    __syncthreads();
+    return 0;
+  }
   double gam = s4[0];
   double alpha = gam / (s4[1] + cw * s4[2] * s4[2]);
   double pv = u, sv = q + cw * s4[2] * wt;
@@ -1259,8 +1272,11 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
     }
     q = apply(W.U);
     double sr[4] = {r * u, q * u, wt * u, r * r};
-    block_sum<4>(sr, red, nn);
-    if (sr[3] <= tol2) return it;
+    block_sum<4, false>(sr, red, nn);
+    if (sr[3] <= tol2) {
+      __syncthreads();
+      return it;
+    }
     const double gn = sr[0];
     const double dn = sr[1] + cw * sr[2] * sr[2];
     const double beta = gn / gam;
@@ -1269,6 +1285,7 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
     sv = (q + cw * sr[2] * wt) + beta * sv;
     gam = gn;
   }
+  __syncthreads();
   return maxit + 1;
 }
 
@@ -1543,9 +1560,10 @@ struct RegOp {
 template <int N1C, int P>
 __device__ __forceinline__ void reg_gather(const PcgStageArgs& a,
                                            const BlockSolve<N1C, double, kRegMaxThreads>& W,
-                                           RegOp<N1C, P>& R, const double* __restrict__ reg) {
+                                           RegOp<N1C, P>& R, const double* __restrict__ reg,
+                                           int t = -1) {
   constexpr int n1 = N1C, NP = N1C + 1, WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
-  const int t = threadIdx.x;
+  if (t < 0) t = threadIdx.x;
   const int T = a.blk_threads;
 #pragma unroll
   for (int i = 0; i < CH; ++i)
@@ -1597,9 +1615,14 @@ __device__ __forceinline__ double reg_apply(const BlockSolve<N1C, double, kRegMa
   __syncthreads();
   double y = 0.0;
   if (t < n1 * n1) {
+    // the row's partials (one per jy of its band, WB = WM slots a row), all loads first
     const int wiy = st_w(t / n1, P, N1C - 1);
-    const double* pr = W.P + t * W.WB;
-    for (int q = 0; q < wiy; ++q) y += pr[q];
+    const double* pr = W.P + t * WM;
+    double pv[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) pv[q] = q < wiy ? pr[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < WM; ++q) y += pv[q];
   }
   return y;
 }
@@ -1877,6 +1900,609 @@ void k_pcg_stage_group(
       pcg2_stage_elem<STAGE, N1C>(a, b - el_start[pi], W, C);
     }
     __syncthreads();   // the next element reuses the LDS
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Split stage of the register-operator families (FP64).  The fused stage kernel pays, one
+// element per CU at a time, the latency of the element's loads, face fluxes, lifts and
+// traces inside its persistent loop.  Here those parts run as streaming kernels with many
+// elements resident per CU, and the persistent kernels hold only the element solves:
+//   k_pcg_lift<STAGE>     F_u, F_v from the traces (Sec. 2.2.1)              -> Fu, Fv
+//   k_pcg_solve<0, ...>   r = F_v - S_K U (-> Fv) and S_hat y = F_u (-> xS); on Cartesian
+//                         elements also M_J z = r by the exact inverse (-> xM)
+//   k_pcg_solve<1, ...>   M_J z = r on mapped elements (-> xM)
+//   k_pcg_update<STAGE>   the RK update from (y, z) and the traces of the new state
+// The arithmetic of every part is that of the fused kernel, so both give the same state.
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline size_t split_lds_doubles(const PcgGeom& g) {
+  return (size_t)4 * g.nn + 4 * g.nq * 2 + 16 * g.n1 + 64;
+}
+
+// LDS of the streaming kernels; the tables are read through the caches.
+__device__ __forceinline__ void split_carve(const PcgGeom& g, double* sp, StageCommon& C) {
+  const int nn = g.nn, n1 = g.n1, nq = g.nq;
+  C.U = sp;     sp += nn;
+  C.V = sp;     sp += nn;
+  C.Fu = sp;    sp += nn;
+  C.rv = sp;    sp += nn;
+  C.sig = sp;   sp += 4 * nq * 2;
+  C.lines = sp; sp += 16 * n1;
+  C.red = sp;
+  C.lamr = nullptr;
+  C.T = FaceTabs{g.cb, g.cd, g.gw, g.dL, g.dR, nullptr, g.cs, g.ck0, g.ck1};
+  C.gtab = true;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict__ args) {
+  extern __shared__ double shd[];
+  const PcgStageArgs& a = *args;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn;
+  StageCommon C;
+  split_carve(g, shd, C);
+  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+    stage_prologue<STAGE, false>(a, e, C, []() {});
+    if (t < nn) {
+      a.Fu[e * nn + t] = C.Fu[t];
+      a.Fv[e * nn + t] = C.rv[t];
+    }
+    __syncthreads();
+  }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(512) void k_pcg_update(const PcgStageArgs* __restrict__ args) {
+  extern __shared__ double shd[];
+  const PcgStageArgs& a = *args;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x, nn = g.nn;
+  StageCommon C;
+  split_carve(g, shd, C);
+  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+    double y = 0.0, z = 0.0;
+    C.ub = C.vb = C.yu = C.yv = 0.0;
+    if (t < nn) {
+      const long gi = e * nn + t;
+      C.ub = a.in_u[gi];
+      C.vb = a.in_v[gi];
+      if (STAGE > 1) {
+        C.yu = a.aux_u[gi];
+        C.yv = a.aux_v[gi];
+      }
+      y = a.xS[gi];
+      z = a.xM[gi];
+    }
+    C.T.fc = a.el.face + e * 4 * g.nq * 3;
+    stage_epilogue<STAGE, true>(a, e, C, y, z, 0, 0);
+    __syncthreads();
+  }
+}
+
+// doubles and ints of the solve kernels' LDS
+template <int N1C>
+__host__ __device__ constexpr size_t solve_lds_doubles(int WB) {
+  return (size_t)N1C * N1C * WB + 6 * (N1C + 1) * (N1C + 1) + 64 + (N1C + 1);
+}
+
+__device__ __forceinline__ void split_count(const PcgStageArgs& a, long e, int slot, int it) {
+  int* its = a.its + e * kItsPer;
+  its[slot] += it > a.maxit ? a.maxit : it;
+  if (it > its[slot + 2]) its[slot + 2] = it;
+  if (it > a.maxit) atomicMin(a.fail, (int)e);
+}
+
+template <int OP, int N1C, int P>
+__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs* __restrict__ args) {
+  extern __shared__ double shd[];
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const PcgStageArgs& a = *args;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  const bool own = t < nn;
+  const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
+  BlockSolve<N1C, double, kRegMaxThreads> W;
+  W.A = nullptr;
+  W.K = a.blk_K;
+  W.CH = a.blk_CH;
+  W.WB = a.blk_WB;
+  W.p = g.p;
+  W.N = g.N;
+  double* sp = shd;
+  W.P = sp;    sp += nn * W.WB;
+  W.R = sp;    sp += NP * NP;
+  W.U = sp;    sp += NP * NP;
+  W.T = sp;    sp += NP * NP;
+  W.Z = sp;    sp += NP * NP;
+  W.DI = sp;   sp += NP * NP;
+  W.Psi = sp;  sp += NP * NP;
+  double* red = sp;  sp += 64;
+  double* lamr = sp; sp += NP;
+  int* jc = reinterpret_cast<int*>(sp);
+  W.boff = nullptr;
+  W.jc = jc;
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  for (int i = t; i < 5 * NP * NP; i += blockDim.x) W.R[i] = 0.0;   // R U T Z DI (padding)
+  for (int i = t; i < NP * NP; i += blockDim.x) {
+    const int r = i / NP, k = i - (i / NP) * NP;
+    W.Psi[i] = (r < n1 && k < n1) ? g.Psi[r * n1 + k] : 0.0;
+  }
+  for (int i = t; i < n1; i += blockDim.x) lamr[i] = g.lamr[i];
+  __syncthreads();
+  const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads;
+  RegOp<N1C, P> R;
+  auto apply = [&W, &R](const double* v) { return reg_apply(W, R, v); };
+  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+    const long gi = e * nn + t;
+    const double* scp = a.el.sc + e * 8;
+    if constexpr (OP == 0) {
+      double ub = 0.0, fu = 0.0, fv = 0.0, x0 = 0.0, wt = 0.0, dl = 0.0;
+      if (own) {
+        ub = a.in_u[gi];
+        fu = a.Fu[gi];
+        fv = a.Fv[gi];
+        x0 = a.xS[gi];
+        wt = a.el.w[gi];
+        if (a.el.dlog) dl = (double)a.el.dlog[gi];
+      }
+      const double cw = scp[0], kbr = scp[1], kbs = scp[2], d00 = scp[3], area = scp[4];
+      if (own) W.U[pidx] = ub;
+      reg_gather(a, W, R, a.el.Sreg + e * per);
+      __syncthreads();
+      const double su = apply(W.U);
+      const double rv = own ? fv - su : 0.0;      // r = -S_K U + F_v
+      if (a.mapped) {
+        if (own) a.Fv[gi] = rv;
+      } else {
+        // Cartesian: the preconditioner is the exact inverse of M_J
+        double bb1[1] = {rv * rv};
+        if (own) {
+          W.DI[pidx] = 1.0 / area;
+          W.R[pidx] = rv;
+        }
+        block_sum<1>(bb1, red, nn);
+        blk_pinv(W, W.R, W.U);
+        if (own) a.xM[gi] = W.U[pidx];
+        if (t == 0) split_count(a, e, 1, bb1[0] > 0.0 ? 1 : 0);
+      }
+      // ---- S_hat y = F_u --------------------------------------------------------------
+      if (own) {
+        const int kx = t % n1, ky = t / n1;
+        double dS = t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky];
+        if (a.el.dlog && t > 0) dS *= exp(dl);
+        W.DI[pidx] = 1.0 / dS;
+      }
+      double y = x0;
+      int itS = blk_solve_g(W, apply, red, y, own ? fu : 0.0, cw, wt, a.rtol, a.maxit, false);
+      if (itS > a.maxit && a.el.dlog) {
+        if (own) {
+          const int kx = t % n1, ky = t / n1;
+          W.DI[pidx] = 1.0 / (t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky]);
+        }
+        y = x0;
+        itS = blk_solve_g(W, apply, red, y, own ? fu : 0.0, cw, wt, a.rtol, a.maxit, false);
+      }
+      if (own) a.xS[gi] = y;
+      if (t == 0) split_count(a, e, 0, itS);
+    } else {
+      // ---- M_J z = r (mapped elements) ------------------------------------------------
+      double rv = 0.0, z = 0.0, ms = 1.0;
+      if (own) {
+        rv = a.Fv[gi];
+        z = a.xM[gi];
+        if (a.el.msc) ms = a.el.msc[gi];
+        W.DI[pidx] = 1.0 / scp[4];
+      }
+      reg_gather(a, W, R, a.el.Mreg + e * per);
+      const int itM = blk_solve_g(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
+                                  false, a.el.msc != nullptr, ms);
+      if (own) a.xM[gi] = z;
+      if (t == 0) split_count(a, e, 1, itM);
+    }
+    __syncthreads();   // the next element reuses the LDS
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Solve kernels with the CG vectors on one wave (N + 1 <= 16).  In the kernels above every
+// owner thread holds one node, so each iteration needs four workgroup barriers (publish r,
+// preconditioner, operator partials, reduction).  Here wave 0 holds the whole vectors of
+// the solve in the operand layout of the preconditioner's matrix-core chain (lane
+// l = 16 g + c owns the nodes (ix, iy) = (c, 4 s + g), s = 0..3), so the preconditioner
+// reads and writes registers, the dot products are wave reductions (DPP, no LDS), and the
+// only workgroup traffic of an iteration is the operator product: wave 0 publishes u in LDS,
+// every work unit forms its partial row sums, wave 0 adds them.  Two barriers per
+// iteration; the recurrence and its arithmetic are those of blk_solve_g.
+// ---------------------------------------------------------------------------------
+template <int N1C>
+struct W0Lane {
+  int g, c;
+  __device__ __forceinline__ bool ok(int s) const { return c < N1C && 4 * s + g < N1C; }
+  // node (c, 4 s + g): its index iy * (N + 1) + ix, and on the padded grid of the LDS vectors
+  __device__ __forceinline__ int node(int s) const { return (4 * s + g) * N1C + c; }
+  __device__ __forceinline__ int pad(int s) const { return (4 * s + g) * (N1C + 1) + c; }
+};
+
+template <int N1C>
+__device__ __forceinline__ W0Lane<N1C> w0_lane() {
+  W0Lane<N1C> L;
+  const int t = threadIdx.x & 63;
+  L.g = t >> 4;
+  L.c = t & 15;
+  return L;
+}
+
+// Partial row sums of the operator product of every work unit (no barrier).
+template <int N1C, int P>
+__device__ __forceinline__ void reg_units(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                          const RegOp<N1C, P>& R, const double* __restrict__ x) {
+  constexpr int WM = RegOp<N1C, P>::W, CH = RegOp<N1C, P>::CH;
+  if (R.ni > 0) {
+    double xs[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) xs[q] = q < R.wx ? x[R.xoff + q] : 0.0;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < WM; ++q) acc += R.a[i][q] * xs[q];
+      if (i < R.ni) W.P[R.pd[i]] = acc;
+    }
+  }
+}
+
+// Wave 0: the rows of its nodes, each the sum of its partials in slot order.
+template <int N1C, int P>
+__device__ __forceinline__ void w0_rows(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                        const W0Lane<N1C>& L, double (&y)[4]) {
+  constexpr int WM = RegOp<N1C, P>::W;
+  double pv[4][WM];                      // all loads first
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int wiy = L.ok(s) ? st_w(4 * s + L.g, P, N1C - 1) : 0;
+    const double* pr = W.P + L.node(s) * WM;
+#pragma unroll
+    for (int q = 0; q < WM; ++q) pv[s][q] = q < wiy ? pr[q] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < WM; ++q) a += pv[s][q];
+    y[s] = a;
+  }
+}
+
+// Wave 0: out = Psi_2 diag(di) Psi_2^T r on registers (the chain of blk_pinv_mfma).
+__device__ __forceinline__ void w0_pinv(const double (&psk)[4], const double (&pks)[4],
+                                        const double (&di)[4], const double (&r)[4],
+                                        double (&out)[4]) {
+  pcg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(r[s], psk[s], acc, 0, 0, 0);
+  pcg_d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[s], psk[s], acc2, 0, 0, 0);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc2[s] *= di[s];
+  pcg_d4 acc3 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc2[s], pks[s], acc3, 0, 0, 0);
+  pcg_d4 acc4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc4 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc3[s], pks[s], acc4, 0, 0, 0);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) out[s] = acc4[s];
+}
+
+struct W0Pre {
+  double psk[4], pks[4];   // Psi[4 s + g][c], Psi[c][4 s + g] (0 outside)
+};
+
+// Wave 0: u = sc P^-1 (sc r) (sc = 1 when not scaled), written to W.U as well.
+template <int N1C>
+__device__ __forceinline__ void w0_precond(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                           const W0Lane<N1C>& L, const W0Pre& Pp,
+                                           const double (&di)[4], const double (&sc)[4],
+                                           bool scaled, const double (&r)[4], double (&u)[4]) {
+  double rs[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) rs[s] = L.ok(s) ? (scaled ? r[s] * sc[s] : r[s]) : 0.0;
+  w0_pinv(Pp.psk, Pp.pks, di, rs, u);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (scaled) u[s] *= sc[s];
+    if (L.ok(s)) W.U[L.pad(s)] = u[s];
+  }
+}
+
+__device__ __forceinline__ double w0_dot(const double (&a)[4], const double (&b)[4]) {
+  double v = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) v += a[s] * b[s];
+  return wave_sum(v);
+}
+
+// s_waitcnt immediate of gfx9-family targets that waits for vmcnt(0) only
+// (vmcnt = bits 3:0 and 15:14, expcnt = bits 6:4, lgkmcnt = bits 11:8).
+constexpr int kWaitVm0 = 0x0F70;
+
+// Control word of the product rounds (LDS), written by wave 0 lane 0 before the first
+// barrier of a round.
+constexpr int kRoundProduct = 0, kRoundEnd = 1;
+
+// Wave 0: one operator product.  U holds the input (written by wave 0 before the call); the
+// work-unit waves form the partials between the two barriers; wave 0 then adds its rows.
+template <int N1C, int P>
+__device__ __forceinline__ void w0_product(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                           const W0Lane<N1C>& L, int* ctl, double (&y)[4]) {
+  if (threadIdx.x == 0) *ctl = kRoundProduct;
+  __syncthreads();
+  __syncthreads();
+  w0_rows<N1C, P>(W, L, y);
+}
+
+// Wave 0: end of an element for the work-unit waves (they then gather the next operator).
+__device__ __forceinline__ void w0_end(int* ctl) {
+  if (threadIdx.x == 0) *ctl = kRoundEnd;
+  __syncthreads();
+  __syncthreads();
+}
+
+// Work-unit waves: the product rounds of one element, until wave 0 ends it.
+template <int N1C, int P>
+__device__ __forceinline__ void unit_rounds(const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                            const RegOp<N1C, P>& R, const int* ctl) {
+  for (;;) {
+    __syncthreads();
+    const int cmd = __builtin_amdgcn_readfirstlane(*ctl);   // one value per wave: a scalar branch
+    if (cmd == kRoundProduct) reg_units(W, R, W.U);
+    __syncthreads();
+    if (cmd == kRoundEnd) return;
+  }
+}
+
+// Wave 0: PCG on (A + cw w w^T) x = b with the single-reduction recurrence of blk_solve_g;
+// x, b, w, di, sc are wave 0's (entries outside the element 0), x is the warm start on entry
+// and the solution on return; returns the iteration count (maxit + 1: no convergence).
+template <int N1C, int P>
+__device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const W0Lane<N1C>& L,
+                        const W0Pre& Pp, int* ctl, double (&x)[4], const double (&b)[4],
+                        const double (&w)[4], const double (&di)[4], const double (&sc)[4],
+                        bool scaled, double cw, double rtol, int maxit) {
+  double r[4], u[4], q[4], pv[4], sv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (L.ok(s)) W.U[L.pad(s)] = x[s];
+  w0_product<N1C, P>(W, L, ctl, q);
+  const double wx = w0_dot(w, x), bb = w0_dot(b, b);
+  if (bb == 0.0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x[s] = 0.0;
+    return 0;
+  }
+  const double tol2 = rtol * rtol * bb;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r[s] = L.ok(s) ? b[s] - q[s] - cw * wx * w[s] : 0.0;
+  w0_precond(W, L, Pp, di, sc, scaled, r, u);
+  // The scalars are kept as 1/gamma and 1/alpha, so that an iteration needs the two
+  // reciprocals 1/ru and 1/(dn - beta ru / alpha), which do not depend on each other,
+  // instead of three divisions in sequence.
+  double alpha = 0.0, igam = 0.0, ialpha = 0.0;
+  for (int it = 0;; ++it) {
+    w0_product<N1C, P>(W, L, ctl, q);
+    const double ru = w0_dot(r, u), qu = w0_dot(q, u), wu = w0_dot(w, u), rr = w0_dot(r, r);
+    if (rr <= tol2) return it;
+    const double dn = qu + cw * wu * wu;
+    const double iru = 1.0 / ru;
+    if (it == 0) {
+      ialpha = dn * iru;
+      alpha = ru / dn;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        pv[s] = u[s];
+        sv[s] = q[s] + cw * wu * w[s];
+      }
+    } else {
+      const double beta = ru * igam;
+      const double den = dn - beta * ru * ialpha;
+      alpha = ru / den;
+      ialpha = den * iru;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        pv[s] = u[s] + beta * pv[s];
+        sv[s] = (q[s] + cw * wu * w[s]) + beta * sv[s];
+      }
+    }
+    igam = iru;
+    if (it == maxit) return maxit + 1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      x[s] += alpha * pv[s];
+      r[s] -= alpha * sv[s];
+    }
+    w0_precond(W, L, Pp, di, sc, scaled, r, u);
+  }
+}
+
+// Wave 0 of the solve kernels: everything but the products.
+template <int OP, int N1C, int P>
+__device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
+                                           const BlockSolve<N1C, double, kRegMaxThreads>& W,
+                                           const W0Lane<N1C>& L, const W0Pre& Pp, int* ctl) {
+  constexpr int nn = N1C * N1C;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  const long e0 = e * nn;
+  const double* scp = a.el.sc + e * 8;
+  const double one[4] = {1.0, 1.0, 1.0, 1.0};
+  if constexpr (OP == 0) {
+    double ub[4] = {}, fu[4] = {}, fv[4] = {}, x0[4] = {}, wt[4] = {}, dl[4] = {};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (L.ok(s)) {
+        const long gi = e0 + L.node(s);
+        ub[s] = a.in_u[gi];
+        fu[s] = a.Fu[gi];
+        fv[s] = a.Fv[gi];
+        x0[s] = a.xS[gi];
+        wt[s] = a.el.w[gi];
+        if (a.el.dlog) dl[s] = (double)a.el.dlog[gi];
+      }
+    const double cw = scp[0], kbr = scp[1], kbs = scp[2], d00 = scp[3], area = scp[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (L.ok(s)) W.U[L.pad(s)] = ub[s];
+    double su[4], rv[4];
+    w0_product<N1C, P>(W, L, ctl, su);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) rv[s] = L.ok(s) ? fv[s] - su[s] : 0.0;   // r = -S_K U + F_v
+    if (a.mapped) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (L.ok(s)) a.Fv[e0 + L.node(s)] = rv[s];
+    } else {
+      // Cartesian: the preconditioner is the exact inverse of M_J
+      double dm[4], z[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) dm[s] = L.ok(s) ? 1.0 / area : 0.0;
+      const double bb = w0_dot(rv, rv);
+      w0_pinv(Pp.psk, Pp.pks, dm, rv, z);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (L.ok(s)) a.xM[e0 + L.node(s)] = z[s];
+      if (t == 0) split_count(a, e, 1, bb > 0.0 ? 1 : 0);
+    }
+    // ---- S_hat y = F_u ----------------------------------------------------------------
+    // pass 1 with the plain preconditioner when the corrected one did not converge
+    double y[4];
+    int itS = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double di[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int iy = 4 * s + L.g;
+        double dS = 1.0;
+        if (L.ok(s)) {
+          dS = (L.c == 0 && iy == 0) ? d00 : kbr * g.lamr[L.c] + kbs * g.lamr[iy];
+          if (pass == 0 && a.el.dlog && !(L.c == 0 && iy == 0)) dS *= exp(dl[s]);
+        }
+        di[s] = L.ok(s) ? 1.0 / dS : 0.0;
+        y[s] = x0[s];
+      }
+      itS = w0_solve<N1C, P>(W, L, Pp, ctl, y, fu, wt, di, one, false, cw, a.rtol, a.maxit);
+      if (!(a.el.dlog && itS > a.maxit)) break;
+    }
+    w0_end(ctl);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (L.ok(s)) a.xS[e0 + L.node(s)] = y[s];
+    if (t == 0) split_count(a, e, 0, itS);
+  } else {
+    // ---- M_J z = r (mapped elements) --------------------------------------------------
+    double rv[4] = {}, z[4] = {}, ms[4] = {1.0, 1.0, 1.0, 1.0}, di[4];
+    const double zero[4] = {};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (L.ok(s)) {
+        const long gi = e0 + L.node(s);
+        rv[s] = a.Fv[gi];
+        z[s] = a.xM[gi];
+        if (a.el.msc) ms[s] = a.el.msc[gi];
+      }
+    const double area = scp[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) di[s] = L.ok(s) ? 1.0 / area : 0.0;
+    const int itM = w0_solve<N1C, P>(W, L, Pp, ctl, z, rv, zero, di, ms, a.el.msc != nullptr, 0.0,
+                                     a.rtol, a.maxit);
+    w0_end(ctl);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (L.ok(s)) a.xM[e0 + L.node(s)] = z[s];
+    if (t == 0) split_count(a, e, 1, itM);
+  }
+}
+
+// Solve kernels: wave 0 runs the recurrence (w0_element), waves 1.. hold the operator in
+// registers (unit u = threadIdx.x - 64 of the slot-ordered copy) and form the products.  The
+// two roles meet only at the barriers of the product rounds, so each keeps its own registers.
+template <int OP, int N1C, int P>
+__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(const PcgStageArgs* __restrict__ args) {
+  static_assert(N1C <= 16, "one matrix-core tile");
+  extern __shared__ double shd[];
+  constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  const PcgStageArgs& a = *args;
+  const PcgGeom& g = a.g;
+  const int t = threadIdx.x;
+  BlockSolve<N1C, double, kRegMaxThreads> W;
+  W.A = nullptr;
+  W.K = a.blk_K;
+  W.CH = a.blk_CH;
+  W.WB = a.blk_WB;
+  W.p = g.p;
+  W.N = g.N;
+  double* sp = shd;
+  W.P = sp;  sp += nn * W.WB;
+  W.U = sp;  sp += NP * NP;
+  W.R = W.T = W.Z = W.DI = W.Psi = nullptr;
+  int* ctl = reinterpret_cast<int*>(sp);
+  int* jc = ctl + 1;
+  W.boff = nullptr;
+  W.jc = jc;
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  for (int i = t; i < NP * NP; i += blockDim.x) W.U[i] = 0.0;
+  __syncthreads();
+  // The roles branch on the wave index held in a scalar register, so that each wave jumps
+  // over the other role's code (and its barriers) instead of running it with no lanes on.
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  if (wave == 0) {
+    const W0Lane<N1C> L = w0_lane<N1C>();
+    W0Pre Pp;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + L.g;
+      const bool in = L.c < n1 && k < n1;
+      Pp.psk[s] = in ? g.Psi[k * n1 + L.c] : 0.0;
+      Pp.pks[s] = in ? g.Psi[L.c * n1 + k] : 0.0;
+    }
+    for (long e = blockIdx.x; e < a.nel; e += gridDim.x) w0_element<OP, N1C, P>(a, e, W, L, Pp, ctl);
+  } else {
+    // two operator buffers: the next element's entries load while this element's rounds run
+    const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads;
+    const double* op = OP == 0 ? a.el.Sreg : a.el.Mreg;
+    const int u = t - 64;
+    if constexpr (RegOp<N1C, P>::CH * RegOp<N1C, P>::W > 48) {
+      // one buffer where two would not fit the registers
+      RegOp<N1C, P> R;
+      for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+        reg_gather(a, W, R, op + e * per, u);
+        unit_rounds<N1C, P>(W, R, ctl);
+      }
+      return;
+    }
+    // Each buffer is waited for (vmcnt(0), the units issue no other vector memory operation)
+    // at the end of the rounds that overlap its loads, so that the rounds of an element
+    // never wait on the loads of the next one.
+    RegOp<N1C, P> R0, R1;
+    long e = blockIdx.x;
+    if (e < a.nel) reg_gather(a, W, R0, op + e * per, u);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    while (e < a.nel) {
+      const long e1 = e + gridDim.x;
+      if (e1 < a.nel) reg_gather(a, W, R1, op + e1 * per, u);
+      unit_rounds<N1C, P>(W, R0, ctl);
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      if (e1 >= a.nel) break;
+      const long e2 = e1 + gridDim.x;
+      if (e2 < a.nel) reg_gather(a, W, R0, op + e2 * per, u);
+      unit_rounds<N1C, P>(W, R1, ctl);
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      e = e2;
+    }
   }
 }
 
@@ -2280,6 +2906,96 @@ int pcg_family_key(int n1, int p, int v2, int mixed) {
 }
 
 int pcg_group_key(const PcgStageArgs& a) { return pcg_family_key(a.g.n1, a.g.p, a.v2, a.mixed); }
+
+// ---- split stage (host) ---------------------------------------------------------------
+bool pcg_split_key(int key) { return (key & 64) != 0 && pcg_key_known(key); }
+
+static int split_threads(const PcgGeom& g) {
+  const int b = ((g.nn + 63) / 64) * 64;
+  return b < 128 ? 128 : b;
+}
+
+template <int N1C, int P>
+static hipError_t split_solve(int op, const PcgStageArgs* a, const PcgStageArgs& h, int threads,
+                              hipStream_t st) {
+  if constexpr (N1C <= 16) {
+    if (64 + h.blk_threads <= kRegMaxThreads) {
+      // vectors on wave 0, work units on the waves after it
+      const size_t lds = ((size_t)N1C * N1C * h.blk_WB + (N1C + 1) * (N1C + 1)) * sizeof(double) +
+                         (size_t)(h.blk_K + 1) * sizeof(int);
+      const int thr = 64 + h.blk_threads;
+      const void* k = op == 0 ? (const void*)k_pcg_solve_w0<0, N1C, P>
+                              : (const void*)k_pcg_solve_w0<1, N1C, P>;
+      const unsigned grid = persistent_grid(k, thr, lds, h.nel);
+      if (op == 0)
+        hipLaunchKernelGGL((k_pcg_solve_w0<0, N1C, P>), dim3(grid), dim3(thr), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_pcg_solve_w0<1, N1C, P>), dim3(grid), dim3(thr), lds, st, a);
+      return hipGetLastError();
+    }
+  }
+  const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
+  const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P> : (const void*)k_pcg_solve<1, N1C, P>;
+  const unsigned grid = persistent_grid(k, threads, lds, h.nel);
+  if (op == 0)
+    hipLaunchKernelGGL((k_pcg_solve<0, N1C, P>), dim3(grid), dim3(threads), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_pcg_solve<1, N1C, P>), dim3(grid), dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+static hipError_t split_solve_key(int key, int op, const PcgStageArgs* a, const PcgStageArgs& h,
+                                  int threads, hipStream_t st) {
+  switch (key) {
+    case GDW_REG_KEY(9, 3): return split_solve<9, 3>(op, a, h, threads, st);
+    case GDW_REG_KEY(9, 5): return split_solve<9, 5>(op, a, h, threads, st);
+    case GDW_REG_KEY(9, 7): return split_solve<9, 7>(op, a, h, threads, st);
+    case GDW_REG_KEY(13, 3): return split_solve<13, 3>(op, a, h, threads, st);
+    case GDW_REG_KEY(13, 5): return split_solve<13, 5>(op, a, h, threads, st);
+    case GDW_REG_KEY(13, 7): return split_solve<13, 7>(op, a, h, threads, st);
+    case GDW_REG_KEY(17, 3): return split_solve<17, 3>(op, a, h, threads, st);
+    case GDW_REG_KEY(17, 5): return split_solve<17, 5>(op, a, h, threads, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int STAGE>
+static hipError_t split_stream(int part, const PcgStageArgs* a, const PcgStageArgs& h,
+                               hipStream_t st) {
+  const int threads = split_threads(h.g);
+  const size_t lds = split_lds_doubles(h.g) * sizeof(double);
+  const void* k = part == 0 ? (const void*)k_pcg_lift<STAGE> : (const void*)k_pcg_update<STAGE>;
+  const unsigned grid = persistent_grid(k, threads, lds, h.nel);
+  if (part == 0)
+    hipLaunchKernelGGL(k_pcg_lift<STAGE>, dim3(grid), dim3(threads), lds, st, a);
+  else
+    hipLaunchKernelGGL(k_pcg_update<STAGE>, dim3(grid), dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+static hipError_t split_stream_stage(int stage, int part, const PcgStageArgs* a,
+                                     const PcgStageArgs& h, hipStream_t st) {
+  switch (stage) {
+    case 1: return split_stream<1>(part, a, h, st);
+    case 2: return split_stream<2>(part, a, h, st);
+    case 3: return split_stream<3>(part, a, h, st);
+    default: return split_stream<4>(part, a, h, st);
+  }
+}
+
+hipError_t launch_pcg_split_stage(int stage, int key, const PcgStageArgs* a, const PcgStageArgs& h,
+                                  int threads, size_t lds, hipStream_t st) {
+  (void)lds;
+  if (h.nel == 0) return hipSuccess;
+  if (!pcg_split_key(key) || h.Fu == nullptr || h.Fv == nullptr || h.g.nn > 512 ||
+      threads > kRegMaxThreads || threads < h.blk_threads)
+    return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = split_stream_stage(stage, 0, a, h, st)) != hipSuccess) return e;
+  if ((e = split_solve_key(key, 0, a, h, threads, st)) != hipSuccess) return e;
+  if (h.mapped && (e = split_solve_key(key, 1, a, h, threads, st)) != hipSuccess) return e;
+  return split_stream_stage(stage, 1, a, h, st);
+}
 
 int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds) {
   if (a.v2) {
