@@ -40,7 +40,7 @@ static void free_all(gdw_ctx* c) {
   F(c->el.S); F(c->el.M); F(c->el.Shi); F(c->el.Slo); F(c->el.Mhi); F(c->el.Mlo);
   F(c->el.Sreg); F(c->el.Mreg); F(c->el.msc);
   F(c->el.w); F(c->el.sc); F(c->el.face);
-  F(c->el.dlog); F(c->xS); F(c->xM); F(c->Fu); F(c->Fv); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
+  F(c->el.dlog); F(c->el.dscale); F(c->xS); F(c->xM); F(c->Fu); F(c->Fv); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
 }
 
@@ -1238,6 +1238,7 @@ extern "C" gdw_status gdw_precond_data(gdw_ctx* c, float* samples, float* target
 static gdw_status ensure_dlog(gdw_ctx* c) {
   if (!c->el.dlog) {
     GDW_HIP(hipMalloc(&c->el.dlog, (size_t)c->nel * c->g.nn * sizeof(float)));
+    GDW_HIP(hipMalloc(&c->el.dscale, (size_t)c->nel * c->g.nn * sizeof(double)));
     args_changed(c);
   }
   return GDW_OK;
@@ -1250,13 +1251,15 @@ extern "C" gdw_status gdw_set_precond_log(gdw_ctx* c, const float* log_scale, vo
   if (!log_scale) {
     GDW_HIP(hipStreamSynchronize(st));
     if (c->el.dlog) (void)hipFree(c->el.dlog);
+    if (c->el.dscale) (void)hipFree(c->el.dscale);
     c->el.dlog = nullptr;
+    c->el.dscale = nullptr;
     args_changed(c);
     return GDW_OK;
   }
   gdw_status s = ensure_dlog(c);
   if (s != GDW_OK) return s;
-  GDW_HIP(launch_set_dlog(log_scale, c->nel, c->g.nn, c->el.dlog, st));
+  GDW_HIP(launch_set_dlog(log_scale, c->nel, c->g.nn, c->el.dlog, c->el.dscale, st));
   return GDW_OK;
 }
 
@@ -1276,7 +1279,7 @@ extern "C" gdw_status gdw_set_precond_mlp(gdw_ctx* c, gdw_mlp* m, void* stream) 
   hipError_t e = hipMalloc(&out, (size_t)c->nel * (c->g.nn - 1) * sizeof(float));
   if (e == hipSuccess) e = launch_precond_data(c->g, c->el, c->c2n, c->Bs, smp, nullptr, c->nel, st);
   if (e == hipSuccess && mlp_forward_all(m, smp, c->nel, out, st) != GDW_OK) e = hipErrorUnknown;
-  if (e == hipSuccess) e = launch_set_dlog(out, c->nel, c->g.nn, c->el.dlog, st);
+  if (e == hipSuccess) e = launch_set_dlog(out, c->nel, c->g.nn, c->el.dlog, c->el.dscale, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(smp);
   if (out) (void)hipFree(out);

@@ -34,7 +34,8 @@ hipError_t mlp_adam(MlpNet& net, float lr, hipStream_t st);
 hipError_t mlp_refresh_half(MlpNet& net, hipStream_t st);
 hipError_t launch_precond_data(const PcgGeom& g, const PcgElem& el, const double* c2n, const double* Bs,
                                float* samples, float* targets, long nel, hipStream_t st);
-hipError_t launch_set_dlog(const float* out, long nel, int nn, float* dlog, hipStream_t st);
+hipError_t launch_set_dlog(const float* out, long nel, int nn, float* dlog, double* dscale,
+                           hipStream_t st);
 // p[0 .. n) = 0 (a kernel, so that it may be captured into a graph)
 hipError_t launch_zero_f64(double* p, long n, hipStream_t st);
 

@@ -260,8 +260,10 @@ __global__ __launch_bounds__(256) void k_precond_data(PcgGeom g, PcgElem el, con
   }
 }
 
-// dlog[e][0] = 0, dlog[e][k] = sanitised out[e][k-1]: non-finite -> 0 (plain), |o| <= 8
-__global__ void k_set_dlog(const float* __restrict__ out, long nel, int nn, float* __restrict__ dlog) {
+// dlog[e][0] = 0, dlog[e][k] = sanitised out[e][k-1]: non-finite -> 0 (plain), |o| <= 8;
+// dscale = exp(dlog)
+__global__ void k_set_dlog(const float* __restrict__ out, long nel, int nn, float* __restrict__ dlog,
+                           double* __restrict__ dscale) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nel * nn) return;
   const long e = i / nn;
@@ -270,6 +272,7 @@ __global__ void k_set_dlog(const float* __restrict__ out, long nel, int nn, floa
   if (!isfinite(o)) o = 0.f;
   o = fminf(fmaxf(o, -8.f), 8.f);
   dlog[i] = o;
+  dscale[i] = exp((double)o);
 }
 
 hipError_t launch_precond_data(const PcgGeom& g, const PcgElem& el, const double* c2n, const double* Bs,
@@ -280,10 +283,11 @@ hipError_t launch_precond_data(const PcgGeom& g, const PcgElem& el, const double
   return hipGetLastError();
 }
 
-hipError_t launch_set_dlog(const float* out, long nel, int nn, float* dlog, hipStream_t st) {
+hipError_t launch_set_dlog(const float* out, long nel, int nn, float* dlog, double* dscale,
+                           hipStream_t st) {
   const long n = nel * nn;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_dlog, dim3(nb(n)), dim3(256), 0, st, out, nel, nn, dlog);
+  hipLaunchKernelGGL(k_set_dlog, dim3(nb(n)), dim3(256), 0, st, out, nel, nn, dlog, dscale);
   return hipGetLastError();
 }
 

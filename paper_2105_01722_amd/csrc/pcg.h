@@ -41,6 +41,7 @@ struct PcgElem {
   double* sc;           // [nel][8]: kappa/area, kbar_rr, kbar_ss, kappa*area, area, int c^2 J
   double* face;         // [nel][4][nq][3]: (K Nh)_r, (K Nh)_s, c^2 s_J at face points
   float* dlog;          // [nel][nn] log-scale of the S preconditioner diagonal (NULL: plain)
+  double* dscale;       // [nel][nn] exp(dlog), set with dlog
   double* Sreg;         // register kernels: S_K in work-unit slot order,
   double* Mreg;         // [nel][slots][blk_threads] (0 in padding slots); M_J alike
   double* msc;          // [nel][nn] nodal scale of the M_J preconditioner (mapped meshes)

@@ -1916,32 +1916,29 @@ void k_pcg_stage_group(
 // The arithmetic of every part is that of the fused kernel, so both give the same state.
 // ---------------------------------------------------------------------------------
 __host__ __device__ inline size_t split_lds_doubles(const PcgGeom& g) {
-  return (size_t)4 * g.nn + 4 * g.nq * 2 + 16 * g.n1 + 64;
+  return common_doubles(g);
+}
+__host__ __device__ inline size_t split_lds_bytes(const PcgGeom& g) {
+  return split_lds_doubles(g) * sizeof(double) + common_ints(g) * sizeof(int);
 }
 
-// LDS of the streaming kernels; the tables are read through the caches.
-__device__ __forceinline__ void split_carve(const PcgGeom& g, double* sp, StageCommon& C) {
-  const int nn = g.nn, n1 = g.n1, nq = g.nq;
-  C.U = sp;     sp += nn;
-  C.V = sp;     sp += nn;
-  C.Fu = sp;    sp += nn;
-  C.rv = sp;    sp += nn;
-  C.sig = sp;   sp += 4 * nq * 2;
-  C.lines = sp; sp += 16 * n1;
-  C.red = sp;
-  C.lamr = nullptr;
-  C.T = FaceTabs{g.cb, g.cd, g.gw, g.dL, g.dR, nullptr, g.cs, g.ck0, g.ck1};
-  C.gtab = true;
+// LDS of the streaming kernels: the element-independent tables once per workgroup, the
+// element's face data per element (the layout of stage_carve).
+__device__ __forceinline__ void split_carve(const PcgGeom& g, StageCommon& C) {
+  extern __shared__ double shd[];
+  double* sp = shd;
+  int* ip = reinterpret_cast<int*>(shd + split_lds_doubles(g));
+  stage_carve(g, sp, ip, C);
+  stage_load_tables(g, nullptr, 0, C);
 }
 
 template <int STAGE>
 __global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict__ args) {
-  extern __shared__ double shd[];
   const PcgStageArgs& a = *args;
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn;
   StageCommon C;
-  split_carve(g, shd, C);
+  split_carve(g, C);      // tables visible after the prologue's first barrier
   for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
     stage_prologue<STAGE, false>(a, e, C, []() {});
     if (t < nn) {
@@ -1954,12 +1951,12 @@ __global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict
 
 template <int STAGE>
 __global__ __launch_bounds__(512) void k_pcg_update(const PcgStageArgs* __restrict__ args) {
-  extern __shared__ double shd[];
   const PcgStageArgs& a = *args;
   const PcgGeom& g = a.g;
   const int t = threadIdx.x, nn = g.nn;
   StageCommon C;
-  split_carve(g, shd, C);
+  split_carve(g, C);
+  double* fcl = const_cast<double*>(C.T.fc);
   for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
     double y = 0.0, z = 0.0;
     C.ub = C.vb = C.yu = C.yv = 0.0;
@@ -1974,7 +1971,9 @@ __global__ __launch_bounds__(512) void k_pcg_update(const PcgStageArgs* __restri
       y = a.xS[gi];
       z = a.xM[gi];
     }
-    C.T.fc = a.el.face + e * 4 * g.nq * 3;
+    const double* fcg = a.el.face + e * 4 * g.nq * 3;
+    for (int i = t; i < 4 * g.nq * 3; i += blockDim.x) fcl[i] = fcg[i];
+    // (the epilogue's first barrier publishes the face data and the tables)
     stage_epilogue<STAGE, true>(a, e, C, y, z, 0, 0);
     __syncthreads();
   }
@@ -2351,7 +2350,7 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
         fv[s] = a.Fv[gi];
         x0[s] = a.xS[gi];
         wt[s] = a.el.w[gi];
-        if (a.el.dlog) dl[s] = (double)a.el.dlog[gi];
+        if (a.el.dlog) dl[s] = a.el.dscale[gi];
       }
     const double cw = scp[0], kbr = scp[1], kbs = scp[2], d00 = scp[3], area = scp[4];
 #pragma unroll
@@ -2389,7 +2388,7 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
         double dS = 1.0;
         if (L.ok(s)) {
           dS = (L.c == 0 && iy == 0) ? d00 : kbr * g.lamr[L.c] + kbs * g.lamr[iy];
-          if (pass == 0 && a.el.dlog && !(L.c == 0 && iy == 0)) dS *= exp(dl[s]);
+          if (pass == 0 && a.el.dlog && !(L.c == 0 && iy == 0)) dS *= dl[s];
         }
         di[s] = L.ok(s) ? 1.0 / dS : 0.0;
         y[s] = x0[s];
@@ -2963,7 +2962,7 @@ template <int STAGE>
 static hipError_t split_stream(int part, const PcgStageArgs* a, const PcgStageArgs& h,
                                hipStream_t st) {
   const int threads = split_threads(h.g);
-  const size_t lds = split_lds_doubles(h.g) * sizeof(double);
+  const size_t lds = split_lds_bytes(h.g);
   const void* k = part == 0 ? (const void*)k_pcg_lift<STAGE> : (const void*)k_pcg_update<STAGE>;
   const unsigned grid = persistent_grid(k, threads, lds, h.nel);
   if (part == 0)
