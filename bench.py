@@ -36,9 +36,11 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, B/s
 # x1.0 write); the summary with its commands is profiles/fdm_stage_256x256_N16_p5_fp64.md.
 # Set to None whenever that kernel changes until the counters are taken again.
 FDM_STAGE_TRAFFIC = (318921.1 * 2.0 + 469083.7) * 1024.0
-# The same for the PCG stage kernel k_pcg_stage_group<*,717> on the 128 x 128, N = 12, p = 5
-# mapped workload (profiles/pcg_stage_128x128_N12_p5_fp64.md).
-PCG_STAGE_TRAFFIC = (2562770.0 * 2.0 + 174337.2) * 1024.0
+# The same for one RK stage of the PCG path on the 128 x 128, N = 12, p = 5 mapped workload:
+# the sum over its four launches (k_pcg_lift, k_pcg_solve_w0<0,13,5>, k_pcg_solve_w0<1,13,5>,
+# k_pcg_update; profiles/pcg_stage_128x128_N12_p5_fp64.md).
+PCG_STAGE_TRAFFIC = ((112150.3 + 1236712.2 + 1213141.7 + 117189.7) * 2.0
+                     + (44032.0 + 44561.2 + 22544.0 + 128789.4)) * 1024.0
 
 
 def _workload(n=256, N=16, p=5, seed=2, cfl=0.15):
@@ -603,12 +605,13 @@ def main():
             "roofline": {"bound": "hbm", "achieved": pach / 1e9, "peak": HBM_PEAK / 1e9,
                          "unit": "GB/s", "frac": pach / HBM_PEAK,
                          "traffic": PCG_STAGE_TRAFFIC,
-                         "traffic_unit": "HBM bytes per launch (counters, copy-calibrated)",
+                         "traffic_unit": "HBM bytes per RK stage (counters, copy-calibrated)",
                          "alg_bytes_per_dof_update": pbytes,
-                         "alg_bytes_per_launch": pbytes * pdof / 4,
-                         "avg_launch_us": ms * 1e3 / (4 * ksteps),
+                         "alg_bytes_per_stage": pbytes * pdof / 4,
+                         "avg_stage_us": ms * 1e3 / (4 * ksteps),
                          "alu_achieved_tflops": flops / 1e12, "alu_frac_fp64": flops / 78.6e12,
-                         "kernel": "k_pcg_stage_group<*,717> (4 stage variants; N+1 = 13, p = 5, operator in registers)"},
+                         "kernel": "RK stage of 4 launches: k_pcg_lift, k_pcg_solve_w0<0,13,5> "
+                                   "(S_hat), k_pcg_solve_w0<1,13,5> (M_J), k_pcg_update"},
             "mixed": {"ms_per_step": msm / ksteps, "value": pdof * ksteps / (msm * 1e-3),
                       "speedup_vs_fp64": ms / msm, "mean_it_S": itm["mean_it_S"],
                       "mean_it_M": itm["mean_it_M"], "mean_refine_sweeps": itm["mean_refine"],
