@@ -46,6 +46,12 @@ struct PcgClass {
   std::vector<int> members;
   PcgStageArgs* d_args[4] = {nullptr, nullptr, nullptr, nullptr};
   long* d_el = nullptr;
+  // split stage (register-operator families): d_args[k] holds the members' arguments
+  // followed by those of the mapped members again (the M_J solves walk only these)
+  bool split = false;
+  int n_mapped = 0;
+  long* d_el_m = nullptr;
+  std::vector<long> h_el, h_el_m;   // host copies of d_el, d_el_m
 };
 
 }  // namespace
@@ -81,6 +87,7 @@ static void free_classes(gdw_batch* b) {
   for (auto& c : b->pcg) {
     for (auto& p : c.d_args) if (p) (void)hipFree(p);
     if (c.d_el) (void)hipFree(c.d_el);
+    if (c.d_el_m) (void)hipFree(c.d_el_m);
   }
 }
 
@@ -147,6 +154,63 @@ static gdw_status upload_pcg_args(gdw_batch* b, PcgClass& c, int stage,
   GDW_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(PcgStageArgs), hipMemcpyHostToDevice));
   *lds_out = lds;
   return GDW_OK;
+}
+
+// Mapped members of a split class, in member order.
+static std::vector<int> mapped_members(const PcgClass& c, const std::vector<gdw_ctx*>& ctx) {
+  std::vector<int> m;
+  for (int i : c.members)
+    if (ctx[i]->d.mapped) m.push_back(i);
+  return m;
+}
+
+static gdw_status upload_split_args(gdw_batch* b, PcgClass& c, int stage,
+                                    const std::vector<double>& dt) {
+  std::vector<PcgStageArgs> h;
+  for (int i : c.members) h.push_back(pcg_stage_args(b->ctx[i], stage, dt[i]));
+  for (int i : mapped_members(c, b->ctx)) h.push_back(pcg_stage_args(b->ctx[i], stage, dt[i]));
+  PcgStageArgs*& d = c.d_args[stage - 1];
+  if (!d) GDW_HIP(hipMalloc(&d, h.size() * sizeof(PcgStageArgs)));
+  GDW_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(PcgStageArgs), hipMemcpyHostToDevice));
+  return GDW_OK;
+}
+
+static gdw_status upload_split_el(PcgClass& c, const std::vector<gdw_ctx*>& ctx) {
+  const std::vector<int> m = mapped_members(c, ctx);
+  std::vector<long> t(m.size() + 1, 0);
+  for (size_t k = 0; k < m.size(); ++k) t[k + 1] = t[k] + ctx[m[k]]->nel;
+  c.n_mapped = (int)m.size();
+  c.h_el_m = t;
+  c.h_el.assign(c.members.size() + 1, 0);
+  for (size_t k = 0; k < c.members.size(); ++k) c.h_el[k + 1] = c.h_el[k] + ctx[c.members[k]]->nel;
+  if (!c.d_el_m) GDW_HIP(hipMalloc(&c.d_el_m, t.size() * sizeof(long)));
+  GDW_HIP(hipMemcpy(c.d_el_m, t.data(), t.size() * sizeof(long), hipMemcpyHostToDevice));
+  return GDW_OK;
+}
+
+// A register-operator class runs the split stage when every member has its lift buffers and
+// the members share the block layout (a function of N, p and the precision, so equal
+// layouts mean equal unit tables).
+static bool split_class(const PcgClass& c, const std::vector<gdw_ctx*>& ctx) {
+  if (!pcg_split_key(c.n1) || c.members.empty()) return false;
+  const gdw_ctx* x0 = ctx[c.members[0]];
+  for (int i : c.members) {
+    const gdw_ctx* x = ctx[i];
+    if (!x->Fu || !x->Fv || x->n1 != x0->n1 || x->d.p != x0->d.p ||
+        x->blk_threads != x0->blk_threads || x->blk_K != x0->blk_K || x->blk_CH != x0->blk_CH ||
+        x->blk_WB != x0->blk_WB)
+      return false;
+  }
+  return true;
+}
+
+static hipError_t launch_split_class(gdw_batch* b, const PcgClass& c, int stage,
+                                     const std::vector<double>& dt, hipStream_t st) {
+  const PcgStageArgs h = pcg_stage_args(b->ctx[c.members[0]], stage, dt[c.members[0]]);
+  const int np = (int)c.members.size();
+  const PcgStageArgs* d = c.d_args[stage - 1];
+  return launch_pcg_split_group(stage, c.n1, d, c.d_el, c.h_el.data(), np, d + np, c.d_el_m,
+                                c.h_el_m.data(), c.n_mapped, h, c.threads, st);
 }
 
 static gdw_status upload_pcg_el(PcgClass& c, const std::vector<gdw_ctx*>& ctx) {
@@ -233,6 +297,22 @@ static gdw_status tune_fdm(gdw_batch* b, FdmClass& c, const std::vector<double>&
 
 static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>& dt,
                            hipStream_t st, std::string& log) {
+  if (c.split) {
+    // persistent grids sized by occupancy; the block layout fixes the block sizes
+    (void)dt;
+    (void)st;
+    gdw_status s;
+    if ((s = upload_pcg_el(c, b->ctx)) != GDW_OK || (s = upload_split_el(c, b->ctx)) != GDW_OK)
+      return s;
+    c.threads = b->ctx[c.members[0]]->blk_threads;
+    c.grid = 0;
+    c.lds = 0;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "  pcg key=%d: split stage, %d of %zu members mapped\n", c.n1,
+                  c.n_mapped, c.members.size());
+    log += buf;
+    return GDW_OK;
+  }
   // scratch warm starts / counters (copies of the real ones)
   std::vector<PcgScratch> scr;
   gdw_status s = GDW_OK;
@@ -314,6 +394,10 @@ static gdw_status build_graph(gdw_batch* b, const std::vector<double>& dt) {
     }
   for (auto& c : b->pcg)
     for (int k = 1; k <= 4; ++k) {
+      if (c.split) {
+        if ((s = upload_split_args(b, c, k, dt)) != GDW_OK) return s;
+        continue;
+      }
       size_t lds;
       if ((s = upload_pcg_args(b, c, k, dt, c.threads, nullptr, &lds)) != GDW_OK) return s;
       c.lds = std::max(c.lds, lds);
@@ -331,8 +415,9 @@ static gdw_status build_graph(gdw_batch* b, const std::vector<double>& dt) {
     }
     for (auto& c : b->pcg) {
       if (e != hipSuccess) break;
-      e = launch_pcg_stage_group(k, c.n1, c.d_args[k - 1], c.d_el, (int)c.members.size(), c.grid,
-                                 c.threads, c.lds, b->cap);
+      if (c.split) e = launch_split_class(b, c, k, dt, b->cap);
+      else e = launch_pcg_stage_group(k, c.n1, c.d_args[k - 1], c.d_el, (int)c.members.size(),
+                                      c.grid, c.threads, c.lds, b->cap);
     }
   }
   hipGraph_t g = nullptr;
@@ -364,8 +449,12 @@ static void make_plan(gdw_batch* b, const std::string& log) {
     else if (c.n1 & 64) std::snprintf(fam, sizeof fam, "blocks n1=%d (registers, p=%d)", c.n1 & 31, c.n1 >> 7);
     else if (c.n1 & 32) std::snprintf(fam, sizeof fam, "mixed n1=%d", c.n1 & 31);
     else std::snprintf(fam, sizeof fam, "blocks n1=%d", c.n1 & 31);
-    std::snprintf(buf, sizeof buf, "pcg %s: %zu problems, threads=%d grid=%u lds=%zu\n", fam,
-                  c.members.size(), c.threads, c.grid, c.lds);
+    if (c.split)
+      std::snprintf(buf, sizeof buf, "pcg %s: %zu problems, split stage (%d mapped)\n", fam,
+                    c.members.size(), c.n_mapped);
+    else
+      std::snprintf(buf, sizeof buf, "pcg %s: %zu problems, threads=%d grid=%u lds=%zu\n", fam,
+                    c.members.size(), c.threads, c.grid, c.lds);
     p += buf;
   }
   b->plan = p + "candidates:\n" + log;
@@ -424,6 +513,7 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
       }
     }
   }
+  for (auto& c : b->pcg) c.split = split_class(c, b->ctx);
   if (s == GDW_OK && !b->pcg.empty() && pcg_group_prepare() != hipSuccess) {
     set_error("batch: cannot raise the LDS limit of the PCG stage kernels");
     s = GDW_EHIP;

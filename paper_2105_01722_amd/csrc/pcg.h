@@ -147,6 +147,16 @@ int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds);
 // pcg_single_shape.
 hipError_t launch_pcg_split_stage(int stage, int key, const PcgStageArgs* a, const PcgStageArgs& h,
                                   int threads, size_t lds, hipStream_t st);
+// The same over a group of problems of one family (all members share N, p and the block
+// layout; h is the host copy of a member's arguments): the lifts, the S_hat solves and the
+// updates walk the nprob members of args (member k owns elements el_start[k] ..
+// el_start[k + 1] - 1; h_el_start is the host copy of that table); the M_J solves walk the
+// nprob_m members of args_m (the mapped ones, with their own tables; none if 0).
+hipError_t launch_pcg_split_group(int stage, int key, const PcgStageArgs* args,
+                                  const long* el_start, const long* h_el_start, int nprob,
+                                  const PcgStageArgs* args_m, const long* el_start_m,
+                                  const long* h_el_start_m, int nprob_m, const PcgStageArgs& h,
+                                  int threads, hipStream_t st);
 bool pcg_split_key(int key);
 // Persistent grid of the grouped kernel of family `key` for nel elements.
 unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel);

@@ -1922,24 +1922,66 @@ __host__ __device__ inline size_t split_lds_bytes(const PcgGeom& g) {
   return split_lds_doubles(g) * sizeof(double) + common_ints(g) * sizeof(int);
 }
 
-// LDS of the streaming kernels: the element-independent tables once per workgroup, the
-// element's face data per element (the layout of stage_carve).
+// Elements of a split launch: those of one problem (GRP = false: args[0].nel of them), or
+// those of the n members of a group one after another (GRP: member k owns the elements
+// start[k] .. start[k + 1] - 1, start[n] is the total).  The members of a group share N, p
+// and the block layout, so one LDS layout serves all of them.  The single-problem kernels
+// are separate instances, so that they carry no member bookkeeping.
+template <bool GRP>
+struct ElemRange {
+  const long* start;
+  int n;
+  __device__ __forceinline__ long total(const PcgStageArgs* args) const {
+    if constexpr (GRP) return start[n];
+    return args[0].nel;
+  }
+  // member of element b, searched onward from member k (the elements of a workgroup come
+  // in increasing order)
+  __device__ __forceinline__ int member(long b, int k) const {
+    if constexpr (GRP) {
+      while (k + 1 < n && b >= start[k + 1]) ++k;
+      return k;
+    }
+    return 0;
+  }
+  __device__ __forceinline__ long first(int k) const {
+    if constexpr (GRP) return start[k];
+    return 0;
+  }
+};
+
+// LDS of the streaming kernels: the element-independent tables (loaded again when a
+// workgroup moves on to another member) and the element's face data (the layout of
+// stage_carve).
 __device__ __forceinline__ void split_carve(const PcgGeom& g, StageCommon& C) {
   extern __shared__ double shd[];
   double* sp = shd;
   int* ip = reinterpret_cast<int*>(shd + split_lds_doubles(g));
   stage_carve(g, sp, ip, C);
-  stage_load_tables(g, nullptr, 0, C);
 }
 
-template <int STAGE>
-__global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict__ args) {
-  const PcgStageArgs& a = *args;
-  const PcgGeom& g = a.g;
-  const int t = threadIdx.x, nn = g.nn;
+template <int STAGE, bool GRP>
+__global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict__ args,
+                                                  const long* __restrict__ el_start, int nprob) {
+  const ElemRange<GRP> rg{el_start, nprob};
+  const int t = threadIdx.x, nn = args[0].g.nn;
   StageCommon C;
-  split_carve(g, C);      // tables visible after the prologue's first barrier
-  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+  split_carve(args[0].g, C);
+  if constexpr (!GRP) stage_load_tables(args[0].g, nullptr, 0, C);
+  const long total = rg.total(args);
+  int k = 0;
+  [[maybe_unused]] int cur = -1;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    k = rg.member(b, k);
+    const PcgStageArgs& a = args[k];
+    // (the previous element ended with a barrier; the prologue's first one publishes)
+    if constexpr (GRP) {
+      if (k != cur) {
+        stage_load_tables(a.g, nullptr, 0, C);
+        cur = k;
+      }
+    }
+    const long e = b - rg.first(k);
     stage_prologue<STAGE, false>(a, e, C, []() {});
     if (t < nn) {
       a.Fu[e * nn + t] = C.Fu[t];
@@ -1949,15 +1991,29 @@ __global__ __launch_bounds__(512) void k_pcg_lift(const PcgStageArgs* __restrict
   }
 }
 
-template <int STAGE>
-__global__ __launch_bounds__(512) void k_pcg_update(const PcgStageArgs* __restrict__ args) {
-  const PcgStageArgs& a = *args;
-  const PcgGeom& g = a.g;
-  const int t = threadIdx.x, nn = g.nn;
+template <int STAGE, bool GRP>
+__global__ __launch_bounds__(512) void k_pcg_update(const PcgStageArgs* __restrict__ args,
+                                                    const long* __restrict__ el_start, int nprob) {
+  const ElemRange<GRP> rg{el_start, nprob};
+  const int t = threadIdx.x, nn = args[0].g.nn;
   StageCommon C;
-  split_carve(g, C);
+  split_carve(args[0].g, C);
   double* fcl = const_cast<double*>(C.T.fc);
-  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+  if constexpr (!GRP) stage_load_tables(args[0].g, nullptr, 0, C);
+  const long total = rg.total(args);
+  int k = 0;
+  [[maybe_unused]] int cur = -1;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    k = rg.member(b, k);
+    const PcgStageArgs& a = args[k];
+    const PcgGeom& g = a.g;
+    if constexpr (GRP) {
+      if (k != cur) {
+        stage_load_tables(g, nullptr, 0, C);
+        cur = k;
+      }
+    }
+    const long e = b - rg.first(k);
     double y = 0.0, z = 0.0;
     C.ub = C.vb = C.yu = C.yv = 0.0;
     if (t < nn) {
@@ -1992,22 +2048,24 @@ __device__ __forceinline__ void split_count(const PcgStageArgs& a, long e, int s
   if (it > a.maxit) atomicMin(a.fail, (int)e);
 }
 
-template <int OP, int N1C, int P>
-__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs* __restrict__ args) {
+template <int OP, int N1C, int P, bool GRP>
+__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs* __restrict__ args,
+                                                               const long* __restrict__ el_start,
+                                                               int nprob) {
   extern __shared__ double shd[];
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
-  const PcgStageArgs& a = *args;
-  const PcgGeom& g = a.g;
+  const ElemRange<GRP> rg{el_start, nprob};
+  const PcgStageArgs& a0 = args[0];
   const int t = threadIdx.x;
   const bool own = t < nn;
   const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
   BlockSolve<N1C, double, kRegMaxThreads> W;
   W.A = nullptr;
-  W.K = a.blk_K;
-  W.CH = a.blk_CH;
-  W.WB = a.blk_WB;
-  W.p = g.p;
-  W.N = g.N;
+  W.K = a0.blk_K;
+  W.CH = a0.blk_CH;
+  W.WB = a0.blk_WB;
+  W.p = a0.g.p;
+  W.N = a0.g.N;
   double* sp = shd;
   W.P = sp;    sp += nn * W.WB;
   W.R = sp;    sp += NP * NP;
@@ -2021,18 +2079,36 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs
   int* jc = reinterpret_cast<int*>(sp);
   W.boff = nullptr;
   W.jc = jc;
-  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a0.blk_jc[i];
   for (int i = t; i < 5 * NP * NP; i += blockDim.x) W.R[i] = 0.0;   // R U T Z DI (padding)
-  for (int i = t; i < NP * NP; i += blockDim.x) {
-    const int r = i / NP, k = i - (i / NP) * NP;
-    W.Psi[i] = (r < n1 && k < n1) ? g.Psi[r * n1 + k] : 0.0;
-  }
-  for (int i = t; i < n1; i += blockDim.x) lamr[i] = g.lamr[i];
+  // the eigenbasis tables of member k (a group reloads them when a workgroup changes member)
+  auto load_tables = [&](const PcgGeom& g) {
+    for (int i = t; i < NP * NP; i += blockDim.x) {
+      const int r = i / NP, q = i - (i / NP) * NP;
+      W.Psi[i] = (r < n1 && q < n1) ? g.Psi[r * n1 + q] : 0.0;
+    }
+    for (int i = t; i < n1; i += blockDim.x) lamr[i] = g.lamr[i];
+  };
+  if constexpr (!GRP) load_tables(a0.g);
   __syncthreads();
-  const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads;
+  const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a0.blk_threads;
   RegOp<N1C, P> R;
   auto apply = [&W, &R](const double* v) { return reg_apply(W, R, v); };
-  for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
+  const long total = rg.total(args);
+  int k = 0;
+  [[maybe_unused]] int cur = -1;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    k = rg.member(b, k);
+    const PcgStageArgs& a = args[k];
+    const PcgGeom& g = a.g;
+    if constexpr (GRP) {
+      if (k != cur) {   // (the previous element ended with a barrier)
+        load_tables(g);
+        cur = k;
+        __syncthreads();
+      }
+    }
+    const long e = b - rg.first(k);
     const long gi = e * nn + t;
     const double* scp = a.el.sc + e * 8;
     if constexpr (OP == 0) {
@@ -2429,21 +2505,22 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
 // Solve kernels: wave 0 runs the recurrence (w0_element), waves 1.. hold the operator in
 // registers (unit u = threadIdx.x - 64 of the slot-ordered copy) and form the products.  The
 // two roles meet only at the barriers of the product rounds, so each keeps its own registers.
-template <int OP, int N1C, int P>
-__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(const PcgStageArgs* __restrict__ args) {
+template <int OP, int N1C, int P, bool GRP>
+__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(
+    const PcgStageArgs* __restrict__ args, const long* __restrict__ el_start, int nprob) {
   static_assert(N1C <= 16, "one matrix-core tile");
   extern __shared__ double shd[];
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
-  const PcgStageArgs& a = *args;
-  const PcgGeom& g = a.g;
+  const ElemRange<GRP> rg{el_start, nprob};
+  const PcgStageArgs& a0 = args[0];
   const int t = threadIdx.x;
   BlockSolve<N1C, double, kRegMaxThreads> W;
   W.A = nullptr;
-  W.K = a.blk_K;
-  W.CH = a.blk_CH;
-  W.WB = a.blk_WB;
-  W.p = g.p;
-  W.N = g.N;
+  W.K = a0.blk_K;
+  W.CH = a0.blk_CH;
+  W.WB = a0.blk_WB;
+  W.p = a0.g.p;
+  W.N = a0.g.N;
   double* sp = shd;
   W.P = sp;  sp += nn * W.WB;
   W.U = sp;  sp += NP * NP;
@@ -2452,33 +2529,61 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(const PcgStageA
   int* jc = ctl + 1;
   W.boff = nullptr;
   W.jc = jc;
-  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a.blk_jc[i];
+  for (int i = t; i < W.K; i += blockDim.x) jc[i] = a0.blk_jc[i];
   for (int i = t; i < NP * NP; i += blockDim.x) W.U[i] = 0.0;
   __syncthreads();
+  const long total = rg.total(args);
   // The roles branch on the wave index held in a scalar register, so that each wave jumps
   // over the other role's code (and its barriers) instead of running it with no lanes on.
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   if (wave == 0) {
     const W0Lane<N1C> L = w0_lane<N1C>();
     W0Pre Pp;
+    // the eigenbasis in the operand layout of the transforms (a group reloads it when the
+    // workgroup changes member)
+    auto load_pre = [&](const PcgGeom& g) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = 4 * s + L.g;
-      const bool in = L.c < n1 && k < n1;
-      Pp.psk[s] = in ? g.Psi[k * n1 + L.c] : 0.0;
-      Pp.pks[s] = in ? g.Psi[L.c * n1 + k] : 0.0;
+      for (int s = 0; s < 4; ++s) {
+        const int q = 4 * s + L.g;
+        const bool in = L.c < n1 && q < n1;
+        Pp.psk[s] = in ? g.Psi[q * n1 + L.c] : 0.0;
+        Pp.pks[s] = in ? g.Psi[L.c * n1 + q] : 0.0;
+      }
+    };
+    if constexpr (!GRP) load_pre(a0.g);
+    int k = 0;
+    [[maybe_unused]] int cur = -1;
+    for (long b = blockIdx.x; b < total; b += gridDim.x) {
+      k = rg.member(b, k);
+      const PcgStageArgs& a = args[k];
+      if constexpr (GRP) {
+        if (k != cur) {
+          load_pre(a.g);
+          cur = k;
+        }
+      }
+      w0_element<OP, N1C, P>(a, b - rg.first(k), W, L, Pp, ctl);
     }
-    for (long e = blockIdx.x; e < a.nel; e += gridDim.x) w0_element<OP, N1C, P>(a, e, W, L, Pp, ctl);
   } else {
     // two operator buffers: the next element's entries load while this element's rounds run
-    const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a.blk_threads;
-    const double* op = OP == 0 ? a.el.Sreg : a.el.Mreg;
+    const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a0.blk_threads;
     const int u = t - 64;
+    const double* op0 = OP == 0 ? a0.el.Sreg : a0.el.Mreg;
+    int k = 0;
+    // slot-ordered operator of element b (b increases from call to call)
+    auto opr = [&](long b) -> const double* {
+      if constexpr (GRP) {
+        k = rg.member(b, k);
+        const PcgStageArgs& a = args[k];
+        return (OP == 0 ? a.el.Sreg : a.el.Mreg) + (b - rg.first(k)) * per;
+      }
+      return op0 + b * per;
+    };
     if constexpr (RegOp<N1C, P>::CH * RegOp<N1C, P>::W > 48) {
       // one buffer where two would not fit the registers
       RegOp<N1C, P> R;
-      for (long e = blockIdx.x; e < a.nel; e += gridDim.x) {
-        reg_gather(a, W, R, op + e * per, u);
+      for (long b = blockIdx.x; b < total; b += gridDim.x) {
+        reg_gather(a0, W, R, opr(b), u);
         unit_rounds<N1C, P>(W, R, ctl);
       }
       return;
@@ -2487,20 +2592,20 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(const PcgStageA
     // at the end of the rounds that overlap its loads, so that the rounds of an element
     // never wait on the loads of the next one.
     RegOp<N1C, P> R0, R1;
-    long e = blockIdx.x;
-    if (e < a.nel) reg_gather(a, W, R0, op + e * per, u);
+    long b = blockIdx.x;
+    if (b < total) reg_gather(a0, W, R0, opr(b), u);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    while (e < a.nel) {
-      const long e1 = e + gridDim.x;
-      if (e1 < a.nel) reg_gather(a, W, R1, op + e1 * per, u);
+    while (b < total) {
+      const long b1 = b + gridDim.x;
+      if (b1 < total) reg_gather(a0, W, R1, opr(b1), u);
       unit_rounds<N1C, P>(W, R0, ctl);
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
-      if (e1 >= a.nel) break;
-      const long e2 = e1 + gridDim.x;
-      if (e2 < a.nel) reg_gather(a, W, R0, op + e2 * per, u);
+      if (b1 >= total) break;
+      const long b2 = b1 + gridDim.x;
+      if (b2 < total) reg_gather(a0, W, R0, opr(b2), u);
       unit_rounds<N1C, P>(W, R1, ctl);
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
-      e = e2;
+      b = b2;
     }
   }
 }
@@ -2914,86 +3019,160 @@ static int split_threads(const PcgGeom& g) {
   return b < 128 ? 128 : b;
 }
 
-template <int N1C, int P>
-static hipError_t split_solve(int op, const PcgStageArgs* a, const PcgStageArgs& h, int threads,
-                              hipStream_t st) {
+// Elements of a split launch (device args, optional member table with its host copy, the
+// member count and the element total).
+struct SplitSet {
+  const PcgStageArgs* args;
+  const long* el_start;
+  const long* h_start;
+  int nprob;
+  long total;
+};
+
+template <int N1C, int P, bool GRP>
+static hipError_t split_solve_t(int op, const SplitSet& S, const PcgStageArgs& h, int threads,
+                                hipStream_t st) {
   if constexpr (N1C <= 16) {
     if (64 + h.blk_threads <= kRegMaxThreads) {
       // vectors on wave 0, work units on the waves after it
       const size_t lds = ((size_t)N1C * N1C * h.blk_WB + (N1C + 1) * (N1C + 1)) * sizeof(double) +
                          (size_t)(h.blk_K + 1) * sizeof(int);
       const int thr = 64 + h.blk_threads;
-      const void* k = op == 0 ? (const void*)k_pcg_solve_w0<0, N1C, P>
-                              : (const void*)k_pcg_solve_w0<1, N1C, P>;
-      const unsigned grid = persistent_grid(k, thr, lds, h.nel);
+      const void* k = op == 0 ? (const void*)k_pcg_solve_w0<0, N1C, P, GRP>
+                              : (const void*)k_pcg_solve_w0<1, N1C, P, GRP>;
+      const unsigned grid = persistent_grid(k, thr, lds, S.total);
       if (op == 0)
-        hipLaunchKernelGGL((k_pcg_solve_w0<0, N1C, P>), dim3(grid), dim3(thr), lds, st, a);
+        hipLaunchKernelGGL((k_pcg_solve_w0<0, N1C, P, GRP>), dim3(grid), dim3(thr), lds, st,
+                           S.args, S.el_start, S.nprob);
       else
-        hipLaunchKernelGGL((k_pcg_solve_w0<1, N1C, P>), dim3(grid), dim3(thr), lds, st, a);
+        hipLaunchKernelGGL((k_pcg_solve_w0<1, N1C, P, GRP>), dim3(grid), dim3(thr), lds, st,
+                           S.args, S.el_start, S.nprob);
       return hipGetLastError();
     }
   }
   const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
-  const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P> : (const void*)k_pcg_solve<1, N1C, P>;
-  const unsigned grid = persistent_grid(k, threads, lds, h.nel);
+  const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, GRP>
+                          : (const void*)k_pcg_solve<1, N1C, P, GRP>;
+  const unsigned grid = persistent_grid(k, threads, lds, S.total);
   if (op == 0)
-    hipLaunchKernelGGL((k_pcg_solve<0, N1C, P>), dim3(grid), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_pcg_solve<0, N1C, P, GRP>), dim3(grid), dim3(threads), lds, st, S.args,
+                       S.el_start, S.nprob);
   else
-    hipLaunchKernelGGL((k_pcg_solve<1, N1C, P>), dim3(grid), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_pcg_solve<1, N1C, P, GRP>), dim3(grid), dim3(threads), lds, st, S.args,
+                       S.el_start, S.nprob);
   return hipGetLastError();
 }
 
-static hipError_t split_solve_key(int key, int op, const PcgStageArgs* a, const PcgStageArgs& h,
+template <int N1C, int P>
+static hipError_t split_solve(int op, const SplitSet& S, const PcgStageArgs& h, int threads,
+                              hipStream_t st) {
+  if constexpr (N1C <= 16) {
+    if (S.el_start) return split_solve_t<N1C, P, true>(op, S, h, threads, st);
+  } else {
+    if (S.el_start) return hipErrorInvalidValue;   // launched per member (split_solves)
+  }
+  return split_solve_t<N1C, P, false>(op, S, h, threads, st);
+}
+
+static hipError_t split_solve_key(int key, int op, const SplitSet& S, const PcgStageArgs& h,
                                   int threads, hipStream_t st) {
   switch (key) {
-    case GDW_REG_KEY(9, 3): return split_solve<9, 3>(op, a, h, threads, st);
-    case GDW_REG_KEY(9, 5): return split_solve<9, 5>(op, a, h, threads, st);
-    case GDW_REG_KEY(9, 7): return split_solve<9, 7>(op, a, h, threads, st);
-    case GDW_REG_KEY(13, 3): return split_solve<13, 3>(op, a, h, threads, st);
-    case GDW_REG_KEY(13, 5): return split_solve<13, 5>(op, a, h, threads, st);
-    case GDW_REG_KEY(13, 7): return split_solve<13, 7>(op, a, h, threads, st);
-    case GDW_REG_KEY(17, 3): return split_solve<17, 3>(op, a, h, threads, st);
-    case GDW_REG_KEY(17, 5): return split_solve<17, 5>(op, a, h, threads, st);
+    case GDW_REG_KEY(9, 3): return split_solve<9, 3>(op, S, h, threads, st);
+    case GDW_REG_KEY(9, 5): return split_solve<9, 5>(op, S, h, threads, st);
+    case GDW_REG_KEY(9, 7): return split_solve<9, 7>(op, S, h, threads, st);
+    case GDW_REG_KEY(13, 3): return split_solve<13, 3>(op, S, h, threads, st);
+    case GDW_REG_KEY(13, 5): return split_solve<13, 5>(op, S, h, threads, st);
+    case GDW_REG_KEY(13, 7): return split_solve<13, 7>(op, S, h, threads, st);
+    case GDW_REG_KEY(17, 3): return split_solve<17, 3>(op, S, h, threads, st);
+    case GDW_REG_KEY(17, 5): return split_solve<17, 5>(op, S, h, threads, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int STAGE>
-static hipError_t split_stream(int part, const PcgStageArgs* a, const PcgStageArgs& h,
+template <int STAGE, bool GRP>
+static hipError_t split_stream(int part, const SplitSet& S, const PcgStageArgs& h,
                                hipStream_t st) {
   const int threads = split_threads(h.g);
   const size_t lds = split_lds_bytes(h.g);
-  const void* k = part == 0 ? (const void*)k_pcg_lift<STAGE> : (const void*)k_pcg_update<STAGE>;
-  const unsigned grid = persistent_grid(k, threads, lds, h.nel);
+  const void* k = part == 0 ? (const void*)k_pcg_lift<STAGE, GRP>
+                            : (const void*)k_pcg_update<STAGE, GRP>;
+  const unsigned grid = persistent_grid(k, threads, lds, S.total);
   if (part == 0)
-    hipLaunchKernelGGL(k_pcg_lift<STAGE>, dim3(grid), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_pcg_lift<STAGE, GRP>), dim3(grid), dim3(threads), lds, st, S.args,
+                       S.el_start, S.nprob);
   else
-    hipLaunchKernelGGL(k_pcg_update<STAGE>, dim3(grid), dim3(threads), lds, st, a);
+    hipLaunchKernelGGL((k_pcg_update<STAGE, GRP>), dim3(grid), dim3(threads), lds, st, S.args,
+                       S.el_start, S.nprob);
   return hipGetLastError();
 }
 
-static hipError_t split_stream_stage(int stage, int part, const PcgStageArgs* a,
+template <int STAGE>
+static hipError_t split_stream_g(int part, const SplitSet& S, const PcgStageArgs& h,
+                                 hipStream_t st) {
+  return S.el_start ? split_stream<STAGE, true>(part, S, h, st)
+                    : split_stream<STAGE, false>(part, S, h, st);
+}
+
+static hipError_t split_stream_stage(int stage, int part, const SplitSet& S,
                                      const PcgStageArgs& h, hipStream_t st) {
   switch (stage) {
-    case 1: return split_stream<1>(part, a, h, st);
-    case 2: return split_stream<2>(part, a, h, st);
-    case 3: return split_stream<3>(part, a, h, st);
-    default: return split_stream<4>(part, a, h, st);
+    case 1: return split_stream_g<1>(part, S, h, st);
+    case 2: return split_stream_g<2>(part, S, h, st);
+    case 3: return split_stream_g<3>(part, S, h, st);
+    default: return split_stream_g<4>(part, S, h, st);
   }
+}
+
+// The solves of a set.  The per-node solve kernels (N + 1 = 17) sit at the register limit,
+// where the member bookkeeping of a grouped walk costs spills (N + 1 = 17, p = 5: 66 VGPRs
+// instead of 29); their groups launch one solve per member instead.
+static hipError_t split_solves(int key, int op, const SplitSet& S, const PcgStageArgs& h,
+                               int threads, hipStream_t st) {
+  if (S.total == 0) return hipSuccess;
+  if (S.el_start == nullptr || (key & 31) <= 16) return split_solve_key(key, op, S, h, threads, st);
+  for (int k = 0; k < S.nprob; ++k) {
+    const long n = S.h_start[k + 1] - S.h_start[k];
+    if (n == 0) continue;
+    const SplitSet one{S.args + k, nullptr, nullptr, 1, n};
+    const hipError_t e = split_solve_key(key, op, one, h, threads, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t split_stage(int stage, int key, const SplitSet& all, const SplitSet& mapped,
+                              const PcgStageArgs& h, int threads, hipStream_t st) {
+  if (all.total == 0) return hipSuccess;
+  if (!pcg_split_key(key) || h.Fu == nullptr || h.Fv == nullptr || h.g.nn > 512 ||
+      threads > kRegMaxThreads || threads < h.blk_threads)
+    return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = split_stream_stage(stage, 0, all, h, st)) != hipSuccess) return e;
+  if ((e = split_solves(key, 0, all, h, threads, st)) != hipSuccess) return e;
+  if ((e = split_solves(key, 1, mapped, h, threads, st)) != hipSuccess) return e;
+  return split_stream_stage(stage, 1, all, h, st);
 }
 
 hipError_t launch_pcg_split_stage(int stage, int key, const PcgStageArgs* a, const PcgStageArgs& h,
                                   int threads, size_t lds, hipStream_t st) {
   (void)lds;
-  if (h.nel == 0) return hipSuccess;
-  if (!pcg_split_key(key) || h.Fu == nullptr || h.Fv == nullptr || h.g.nn > 512 ||
-      threads > kRegMaxThreads || threads < h.blk_threads)
+  const SplitSet all{a, nullptr, nullptr, 1, h.nel};
+  const SplitSet mapped{a, nullptr, nullptr, 1, h.mapped ? h.nel : 0};
+  return split_stage(stage, key, all, mapped, h, threads, st);
+}
+
+hipError_t launch_pcg_split_group(int stage, int key, const PcgStageArgs* args,
+                                  const long* el_start, const long* h_el_start, int nprob,
+                                  const PcgStageArgs* args_m, const long* el_start_m,
+                                  const long* h_el_start_m, int nprob_m, const PcgStageArgs& h,
+                                  int threads, hipStream_t st) {
+  if (nprob <= 0 || el_start == nullptr || h_el_start == nullptr ||
+      (nprob_m > 0 && (args_m == nullptr || el_start_m == nullptr || h_el_start_m == nullptr)))
     return hipErrorInvalidValue;
-  hipError_t e;
-  if ((e = split_stream_stage(stage, 0, a, h, st)) != hipSuccess) return e;
-  if ((e = split_solve_key(key, 0, a, h, threads, st)) != hipSuccess) return e;
-  if (h.mapped && (e = split_solve_key(key, 1, a, h, threads, st)) != hipSuccess) return e;
-  return split_stream_stage(stage, 1, a, h, st);
+  const SplitSet all{args, el_start, h_el_start, nprob, h_el_start[nprob]};
+  const SplitSet mapped{args_m, el_start_m, h_el_start_m, nprob_m,
+                        nprob_m > 0 ? h_el_start_m[nprob_m] : 0};
+  return split_stage(stage, key, all, mapped, h, threads, st);
 }
 
 int pcg_single_shape(PcgStageArgs& a, int* threads, size_t* lds) {
