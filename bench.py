@@ -349,8 +349,6 @@ def _batch_section(steps, seed=4, n_prob=64):
     for sp in specs:
         n, N, p = sp["n"], sp["N"], sp["p"]
         if sp["variable"]:
-            if N == 16 and p == 7:
-                p = 5          # the FP64 element operator of (16, 7) exceeds a workgroup's LDS
             probs.append(dict(nx=n, ny=n, N=N, p=p, flux="upwind", solver="pcg",
                               coeff_variable=True, mapped=True, pcg_rtol=1e-12))
             dts.append(BATCH_CFL_VAR[p] / (n * N))
@@ -397,8 +395,8 @@ def _batch_section(steps, seed=4, n_prob=64):
     return {
         "workload": "%d independent periodic problems: n ~ U{16..128}^2 elements, N ~ U{8,12,16}, "
                     "p ~ U{3,5,7} (seed %d); even-numbered: c = 1 Cartesian, FP32 storage; "
-                    "odd-numbered: mapped mesh, c^2 = 1 + 0.5 g, FP64 PCG rtol 1e-12 (p = 5 where "
-                    "N = 16, p = 7); upwind; dt = CFL h per problem" % (n_prob, seed),
+                    "odd-numbered: mapped mesh, c^2 = 1 + 0.5 g, FP64 PCG rtol 1e-12; upwind; "
+                    "dt = CFL h per problem" % (n_prob, seed),
         "problems": len(probs), "dof_total": tot_dof, "steps": steps,
         "value": tot_dof * steps / (total_ms * 1e-3), "unit": "DOF-updates/s",
         "step_ms_p50": float(np.percentile(st, 50)), "step_ms_p99": float(np.percentile(st, 99)),

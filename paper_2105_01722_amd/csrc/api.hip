@@ -424,7 +424,11 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
       return GDW_EUNSUPPORTED;
     }
   }
-  if (pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
+  // the split stage's solve kernels keep no operator in LDS; the fused stage kernel does
+  const bool split_stage = c->blk_v2 && c->blk_gidx != nullptr &&
+                           d->precision != GDW_MIXED_FP32 &&
+                           pcg_split_key(pcg_family_key(g.n1, g.p, 1, 0));
+  if (!split_stage && pcg_stage_lds_bytes(g, 0) > 160 * 1024) {
     set_error("element operator does not fit the LDS of a workgroup (reduce N or p)");
     return GDW_EUNSUPPORTED;
   }

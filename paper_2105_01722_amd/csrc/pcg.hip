@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 #include "pcg.h"
@@ -1535,8 +1536,8 @@ __device__ __forceinline__ void pcg2_stage_elem(const PcgStageArgs& a, const lon
 __host__ __device__ constexpr int blk_band_c(int k, int p, int N) {
   return (k + p < N ? k + p : N) - (k - p > 0 ? k - p : 0) + 1;
 }
-__host__ __device__ constexpr int blk_ch_c(int n1, int p, int maxt) {
-  for (int ch = 1; ch <= 8; ++ch) {
+__host__ __device__ constexpr int blk_ch_c(int n1, int p, int maxt, int chmax = 8) {
+  for (int ch = 1; ch <= chmax; ++ch) {
     int kk = 0;
     for (int jy = 0; jy < n1; ++jy) kk += (blk_band_c(jy, p, n1 - 1) + ch - 1) / ch;
     if (n1 * kk <= maxt) return ch;
@@ -1616,6 +1617,103 @@ __device__ __forceinline__ double reg_apply(const BlockSolve<N1C, double, kRegMa
   double y = 0.0;
   if (t < n1 * n1) {
     // the row's partials (one per jy of its band, WB = WM slots a row), all loads first
+    const int wiy = st_w(t / n1, P, N1C - 1);
+    const double* pr = W.P + t * WM;
+    double pv[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) pv[q] = q < wiy ? pr[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < WM; ++q) y += pv[q];
+  }
+  return y;
+}
+
+// ---------------------------------------------------------------------------------
+// Streamed family (N + 1 = 17, p = 7): on 512 threads a work unit has CH = 9 rows of
+// W = 15 entries, which do not fit its registers beside the CG state, so every product
+// reads them from the slot-ordered copy in memory (a wave's loads of one slot are one
+// contiguous run), one row of the unit at a time.  The unit geometry is that of reg_gather.
+// ---------------------------------------------------------------------------------
+constexpr int kMemMaxThreads = kRegMaxThreads;
+constexpr int kMemMaxCh = 16;
+
+template <int N1C, int P>
+struct MemUnit {
+  static constexpr int W = 2 * P + 1 < N1C ? 2 * P + 1 : N1C;
+  static constexpr int CH = blk_ch_c(N1C, P, kMemMaxThreads, kMemMaxCh);
+  static_assert(CH > 0, "no chunk height fits the thread limit");
+  int xoff;          // jy * NP + lo(ix): first x value of the unit
+  int ni;            // rows of the unit (0: no unit)
+  int ix, jy, iy0;   // column, block row and first row of the unit
+};
+
+// Tallest work unit of a register family (the streamed family's units are not held in
+// registers).
+static int pcg_unit_chmax(int n1, int p) { return n1 == 17 && p == 7 ? kMemMaxCh : 8; }
+
+template <int N1C, int P>
+__device__ __forceinline__ void mem_unit(const BlockSolve<N1C, double, kMemMaxThreads>& W,
+                                         MemUnit<N1C, P>& G) {
+  constexpr int n1 = N1C, NP = N1C + 1, CH = MemUnit<N1C, P>::CH;
+  const int t = threadIdx.x;
+  G.xoff = 0;
+  G.ni = 0;
+  G.ix = G.jy = G.iy0 = 0;
+  if (t < n1 * W.K) {
+    const int k = t / n1, ix = t - k * n1;
+    const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
+    const int lox = st_lo(ix, P);
+    const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
+    const int i0 = c * CH;
+    G.xoff = jy * NP + lox;
+    G.ni = min(CH, wy - i0);
+    G.ix = ix;
+    G.jy = jy;
+    G.iy0 = loy + i0;
+  }
+}
+
+// y_t = (A x)_t for owner threads, as reg_apply, with the entries read from `reg` (the
+// element's slot-ordered copy, kMemMaxThreads threads a slot), three rows of the unit at a
+// time.  The copy
+// holds zeros in the padding slots, so a row's W entries are read without a test (the x
+// values they meet lie inside the padded vector, whose entries are finite).
+template <int N1C, int P>
+__device__ __forceinline__ double mem_apply(const BlockSolve<N1C, double, kMemMaxThreads>& W,
+                                            const MemUnit<N1C, P>& G,
+                                            const double* __restrict__ reg,
+                                            const double* __restrict__ x) {
+  constexpr int n1 = N1C, WM = MemUnit<N1C, P>::W;
+  const int t = threadIdx.x;
+  if (G.ni > 0) {
+    double xs[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) xs[q] = x[G.xoff + q];
+    const double* rp = reg + t;
+    constexpr int rs = kMemMaxThreads;   // slot stride (the family's block size)
+    // rows in groups of three: a group's loads are in flight together
+#pragma unroll 1
+    for (int i0 = 0; i0 < G.ni; i0 += 3) {
+      double v[3][WM];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < WM; ++q)
+          v[r][q] = i0 + r < G.ni ? rp[(r * WM + q) * rs] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < WM; ++q) acc += v[r][q] * xs[q];
+        const int iy = G.iy0 + i0 + r;
+        if (i0 + r < G.ni) W.P[(iy * n1 + G.ix) * W.WB + (G.jy - st_lo(iy, P))] = acc;
+      }
+      rp += 3 * WM * rs;
+    }
+  }
+  __syncthreads();
+  double y = 0.0;
+  if (t < n1 * n1) {
     const int wiy = st_w(t / n1, P, N1C - 1);
     const double* pr = W.P + t * WM;
     double pv[WM];
@@ -2048,18 +2146,21 @@ __device__ __forceinline__ void split_count(const PcgStageArgs& a, long e, int s
   if (it > a.maxit) atomicMin(a.fail, (int)e);
 }
 
-template <int OP, int N1C, int P, bool GRP>
-__global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs* __restrict__ args,
-                                                               const long* __restrict__ el_start,
-                                                               int nprob) {
+// MEM: the streamed family (operator entries read from memory in every product).
+template <int OP, int N1C, int P, bool GRP, bool MEM = false>
+__global__ __launch_bounds__(MEM ? kMemMaxThreads : kRegMaxThreads)
+void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__ el_start,
+                 int nprob) {
   extern __shared__ double shd[];
   constexpr int n1 = N1C, NP = N1C + 1, nn = N1C * N1C;
+  constexpr int MT = MEM ? kMemMaxThreads : kRegMaxThreads;
+  using Unit = std::conditional_t<MEM, MemUnit<N1C, P>, RegOp<N1C, P>>;
   const ElemRange<GRP> rg{el_start, nprob};
   const PcgStageArgs& a0 = args[0];
   const int t = threadIdx.x;
   const bool own = t < nn;
   const int pidx = own ? (t / n1) * NP + (t - (t / n1) * n1) : 0;
-  BlockSolve<N1C, double, kRegMaxThreads> W;
+  BlockSolve<N1C, double, MT> W;
   W.A = nullptr;
   W.K = a0.blk_K;
   W.CH = a0.blk_CH;
@@ -2091,9 +2192,20 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs
   };
   if constexpr (!GRP) load_tables(a0.g);
   __syncthreads();
-  const size_t per = (size_t)RegOp<N1C, P>::CH * RegOp<N1C, P>::W * a0.blk_threads;
-  RegOp<N1C, P> R;
-  auto apply = [&W, &R](const double* v) { return reg_apply(W, R, v); };
+  const int T = a0.blk_threads;
+  const size_t per = (size_t)Unit::CH * Unit::W * T;
+  Unit R;
+  const double* opb = nullptr;   // MEM: the element's slot-ordered operator
+  if constexpr (MEM) mem_unit(W, R);
+  auto apply = [&W, &R, &opb](const double* v) {
+    if constexpr (MEM) return mem_apply(W, R, opb, v);
+    else return reg_apply(W, R, v);
+  };
+  // the element's operator: into the registers, or where the products read it
+  auto take = [&](const PcgStageArgs& a, const double* op) {
+    if constexpr (MEM) opb = op;
+    else reg_gather(a, W, R, op);
+  };
   const long total = rg.total(args);
   int k = 0;
   [[maybe_unused]] int cur = -1;
@@ -2123,7 +2235,7 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs
       }
       const double cw = scp[0], kbr = scp[1], kbs = scp[2], d00 = scp[3], area = scp[4];
       if (own) W.U[pidx] = ub;
-      reg_gather(a, W, R, a.el.Sreg + e * per);
+      take(a, a.el.Sreg + e * per);
       __syncthreads();
       const double su = apply(W.U);
       const double rv = own ? fv - su : 0.0;      // r = -S_K U + F_v
@@ -2169,7 +2281,7 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve(const PcgStageArgs
         if (a.el.msc) ms = a.el.msc[gi];
         W.DI[pidx] = 1.0 / scp[4];
       }
-      reg_gather(a, W, R, a.el.Mreg + e * per);
+      take(a, a.el.Mreg + e * per);
       const int itM = blk_solve_g(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
                                   false, a.el.msc != nullptr, ms);
       if (own) a.xM[gi] = z;
@@ -2753,7 +2865,7 @@ __global__ void k_reg_permute(const double* __restrict__ half, const int* __rest
 
 int pcg_reg_slots(int n1, int p) {
   if (!(pcg_family_key(n1, p, 1, 0) & 64)) return 0;
-  return blk_ch_c(n1, p, kRegMaxThreads) * std::min(2 * p + 1, n1);
+  return blk_ch_c(n1, p, kRegMaxThreads, pcg_unit_chmax(n1, p)) * std::min(2 * p + 1, n1);
 }
 
 hipError_t launch_reg_permute(const double* half, const int* gidx, int nst, int slots,
@@ -2821,7 +2933,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
   // the register-operator kernels run on fewer threads with taller chunks
   const bool reg = (pcg_family_key(n1, p, 1, mixed) & 64) != 0;
   const int maxt = reg ? kRegMaxThreads : kBlkMaxThreads;
-  const int chmax = reg ? 8 : 4;
+  const int chmax = reg ? pcg_unit_chmax(n1, p) : 4;
   boff.assign(nn, 0);
   int off = 0, wb = 0;
   for (int jy = 0; jy < n1; ++jy)
@@ -2837,7 +2949,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
     if (n1 * kk <= maxt) break;
   }
   if (ch > chmax || kk > 255) return 0;
-  if (reg && ch != blk_ch_c(n1, p, kRegMaxThreads)) return 0;   // the kernel's compiled CH
+  if (reg && ch != blk_ch_c(n1, p, maxt, chmax)) return 0;   // the kernel's compiled CH
   jc.clear();
   for (int jy = 0; jy < n1; ++jy) {
     const int nc = (st_w(jy, p, N) + ch - 1) / ch;
@@ -2920,11 +3032,14 @@ int pcg_args_shape(PcgStageArgs& a, int threads, size_t* lds) {
   X(GDW_REG_KEY(9, 3)) X(GDW_REG_KEY(9, 5)) X(GDW_REG_KEY(9, 7)) X(GDW_REG_KEY(13, 3))   \
   X(GDW_REG_KEY(13, 5)) X(GDW_REG_KEY(13, 7)) X(GDW_REG_KEY(17, 3)) X(GDW_REG_KEY(17, 5))
 
+// The streamed family has the split stage only (no fused stage kernel).
+#define GDW_MEM_KEY GDW_REG_KEY(17, 7)
+
 static bool pcg_key_known(int key) {
 #define GDW_K(k) if (key == (k)) return true;
   GDW_PCG_KEYS(GDW_K)
 #undef GDW_K
-  return false;
+  return key == GDW_MEM_KEY;
 }
 
 template <int STAGE, int N1C>
@@ -3074,9 +3189,29 @@ static hipError_t split_solve(int op, const SplitSet& S, const PcgStageArgs& h, 
   return split_solve_t<N1C, P, false>(op, S, h, threads, st);
 }
 
+// Solves of the streamed family: one problem per launch (groups launch per member).
+template <int N1C, int P>
+static hipError_t split_solve_mem(int op, const SplitSet& S, const PcgStageArgs& h, int threads,
+                                  hipStream_t st) {
+  if (S.el_start || h.blk_threads != kMemMaxThreads || threads != kMemMaxThreads)
+    return hipErrorInvalidValue;   // the kernel's compiled slot stride
+  const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
+  const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, false, true>
+                          : (const void*)k_pcg_solve<1, N1C, P, false, true>;
+  const unsigned grid = persistent_grid(k, threads, lds, S.total);
+  if (op == 0)
+    hipLaunchKernelGGL((k_pcg_solve<0, N1C, P, false, true>), dim3(grid), dim3(threads), lds, st,
+                       S.args, S.el_start, S.nprob);
+  else
+    hipLaunchKernelGGL((k_pcg_solve<1, N1C, P, false, true>), dim3(grid), dim3(threads), lds, st,
+                       S.args, S.el_start, S.nprob);
+  return hipGetLastError();
+}
+
 static hipError_t split_solve_key(int key, int op, const SplitSet& S, const PcgStageArgs& h,
                                   int threads, hipStream_t st) {
   switch (key) {
+    case GDW_MEM_KEY: return split_solve_mem<17, 7>(op, S, h, threads, st);
     case GDW_REG_KEY(9, 3): return split_solve<9, 3>(op, S, h, threads, st);
     case GDW_REG_KEY(9, 5): return split_solve<9, 5>(op, S, h, threads, st);
     case GDW_REG_KEY(9, 7): return split_solve<9, 7>(op, S, h, threads, st);

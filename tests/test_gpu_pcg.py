@@ -50,15 +50,17 @@ def _gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, mapped, variable, flux="upwind"
     return U.cpu().numpy(), V.cpu().numpy(), E, st
 
 
-# Kernel families covered: row layout (N = 6, 7) and the operator in registers for every
-# compiled (N + 1, p) pair (9: p = 3, 5, 7; 13: p = 3, 5, 7; 17: p = 3, 5).  N = 12, p = 7
-# also covers nodes that lie in more than 8 cell windows of the closure (lifts).
+# Kernel families covered: row layout (N = 6, 7), the operator in registers for every
+# compiled (N + 1, p) pair (9: p = 3, 5, 7; 13: p = 3, 5, 7; 17: p = 3, 5) and the streamed
+# operator (17: p = 7, mapped and Cartesian).  N = 12, p = 7 also covers nodes that lie in
+# more than 8 cell windows of the closure (lifts).
 @pytest.mark.parametrize("n,N,p,mapped,variable", [(3, 6, 3, True, True), (3, 12, 5, True, True),
                                                    (3, 12, 5, False, True), (2, 8, 7, True, True),
                                                    (3, 7, 5, True, False), (2, 8, 3, True, True),
                                                    (2, 8, 5, True, True), (2, 12, 3, True, True),
                                                    (2, 12, 7, True, True), (2, 16, 3, True, True),
-                                                   (2, 16, 5, True, True)])
+                                                   (2, 16, 5, True, True), (2, 16, 7, True, True),
+                                                   (2, 16, 7, False, True)])
 def test_pcg_matches_dense_oracle(n, N, p, mapped, variable):
     _say("case: pcg vs dense", n, N, p, mapped, variable)
     Xm, Ym, c2, U0, V0 = _problem(n, N, p, mapped, variable)
