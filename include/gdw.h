@@ -126,9 +126,11 @@ const char* gdw_last_error(void);
  * coefficient or a mapped mesh, a direction periodic on one side only, dim not 0, 2 or
  * 3, or in 3D nz < 1 or Lz <= 0; EUNSUPPORTED in 3D for (N + 1)^3 > 1024 (one thread per
  * modal index of an element) or anything but the constant-coefficient Cartesian path, and
- * for the PCG path with p > 7 or an element operator that does not fit the 160 KiB of
- * LDS of a workgroup, and for the PCG path in GDW_MIXED_FP32 with N + 1 outside
- * {9, 13, 17}; ENOMEM / EHIP from the device.  Uses the current HIP device;
+ * for the PCG path with p > 7 or, outside the FP64 families whose solves keep no operator
+ * in LDS (N + 1 = 9, 13 with p = 3, 5, 7; N + 1 = 17 with p = 3, 5, 7), an element operator
+ * that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path in
+ * GDW_MIXED_FP32 with N + 1 outside {9, 13, 17}; ENOMEM / EHIP from the device.  Uses the
+ * current HIP device;
  * synchronous. */
 gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out);
 
