@@ -409,14 +409,15 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
   }
   {
     // column-block layout of the faster stage kernel, where it applies
-    std::vector<int> boff, bdst, jc, gidx;
+    std::vector<int> boff, bdst, jc, gidx, unit;
     const int mixed = d->precision == GDW_MIXED_FP32;
-    if (pcg_block_tables(g, rowoff, boff, bdst, jc, gidx, &c->blk_K, &c->blk_CH, &c->blk_WB,
-                         &c->blk_nnz, &c->blk_threads, mixed)) {
+    if (pcg_block_tables(g, rowoff, boff, bdst, jc, gidx, unit, &c->blk_K, &c->blk_CH,
+                         &c->blk_WB, &c->blk_nnz, &c->blk_threads, mixed)) {
       if ((s = own_upload<int>(c, 15, boff, &c->blk_off)) != GDW_OK) return s;
       if ((s = own_upload<int>(c, 16, bdst, &c->blk_dst)) != GDW_OK) return s;
       if ((s = own_upload<int>(c, 17, jc, &c->blk_jc)) != GDW_OK) return s;
       if (!gidx.empty() && (s = own_upload<int>(c, 18, gidx, &c->blk_gidx)) != GDW_OK) return s;
+      if (!unit.empty() && (s = own_upload<int>(c, 19, unit, &c->blk_unit)) != GDW_OK) return s;
       c->blk_v2 = 1;
     } else if (mixed) {
       set_error("mixed-precision PCG needs N + 1 in {9, 13, 17} and an FP32 element operator "
@@ -792,6 +793,7 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
     a.blk_dst = c->blk_dst;
     a.blk_jc = c->blk_jc;
     a.blk_gidx = c->blk_gidx;
+    a.blk_unit = c->blk_unit;
     a.blk_K = c->blk_K;
     a.blk_CH = c->blk_CH;
     a.blk_WB = c->blk_WB;

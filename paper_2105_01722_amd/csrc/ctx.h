@@ -86,6 +86,7 @@ struct gdw_ctx {
   const int* blk_dst = nullptr;
   const int* blk_jc = nullptr;
   const int* blk_gidx = nullptr;
+  const int* blk_unit = nullptr;
   int blk_K = 0, blk_CH = 0, blk_WB = 0, blk_nnz = 0, blk_threads = 0;
   // stage arguments of the PCG time loop in device memory (the grouped kernel, one problem)
   gdw::PcgStageArgs* d_pargs = nullptr;   // [4]

@@ -84,6 +84,8 @@ struct PcgStageArgs {
   const int* blk_jc;    // [blk_K] work units jy | (c << 8)
   const int* blk_gidx;  // register kernels: [CH * W][blk_threads] upper-half index of each
                         // unit entry (-1: padding)
+  const int* blk_unit;  // streamed family: unit k * (N + 1) + ix of each thread (threads in
+                        // order of the units' widths); nullptr: thread t is unit t
   int blk_K, blk_CH, blk_WB, blk_threads;
   // source term: nf nodal fields g_k at frc + k * frc_stride; dv/dt gains
   // sum_k f_w[4 (stage - 1) + k] g_k, the weights of the current step (written by
@@ -110,8 +112,9 @@ hipError_t launch_set_clock(double* t_dev, double t, hipStream_t st);
 // Column-block layout tables for one geometry; returns 0 when the layout does not apply
 // (N + 1 not in {9, 13, 17}, or LDS or block size exceeded).  rowoff: upper-half row starts.
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
-                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx, int* K, int* CH, int* WB,
-                     int* nnz, int* threads, int mixed);
+                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx,
+                     std::vector<int>& unit, int* K, int* CH, int* WB, int* nnz, int* threads,
+                     int mixed);
 // FP32 hi / lo split of the upper-half operators into the column-block layout.
 // Work-unit slots per thread (CH x W) of the register kernels, which load their entries from
 // a slot-ordered copy of the operator; 0 for the other kernel families.

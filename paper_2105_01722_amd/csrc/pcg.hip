@@ -1643,7 +1643,7 @@ struct MemUnit {
   static constexpr int CH = blk_ch_c(N1C, P, kMemMaxThreads, kMemMaxCh);
   static_assert(CH > 0, "no chunk height fits the thread limit");
   int xoff;          // jy * NP + lo(ix): first x value of the unit
-  int ni;            // rows of the unit (0: no unit)
+  int wx, ni;        // columns and rows of the unit (0 rows: no unit)
   int ix, jy, iy0;   // column, block row and first row of the unit
 };
 
@@ -1653,19 +1653,22 @@ static int pcg_unit_chmax(int n1, int p) { return n1 == 17 && p == 7 ? kMemMaxCh
 
 template <int N1C, int P>
 __device__ __forceinline__ void mem_unit(const BlockSolve<N1C, double, kMemMaxThreads>& W,
-                                         MemUnit<N1C, P>& G) {
+                                         const int* __restrict__ unit, MemUnit<N1C, P>& G) {
   constexpr int n1 = N1C, NP = N1C + 1, CH = MemUnit<N1C, P>::CH;
   const int t = threadIdx.x;
   G.xoff = 0;
+  G.wx = 0;
   G.ni = 0;
   G.ix = G.jy = G.iy0 = 0;
   if (t < n1 * W.K) {
-    const int k = t / n1, ix = t - k * n1;
+    const int tu = unit ? unit[t] : t;            // this thread's unit
+    const int k = tu / n1, ix = tu - k * n1;
     const int jcv = W.jc[k], jy = jcv & 0xff, c = jcv >> 8;
     const int lox = st_lo(ix, P);
     const int loy = st_lo(jy, P), wy = st_w(jy, P, N1C - 1);
     const int i0 = c * CH;
     G.xoff = jy * NP + lox;
+    G.wx = st_w(ix, P, N1C - 1);
     G.ni = min(CH, wy - i0);
     G.ix = ix;
     G.jy = jy;
@@ -1675,9 +1678,7 @@ __device__ __forceinline__ void mem_unit(const BlockSolve<N1C, double, kMemMaxTh
 
 // y_t = (A x)_t for owner threads, as reg_apply, with the entries read from `reg` (the
 // element's slot-ordered copy, kMemMaxThreads threads a slot), three rows of the unit at a
-// time.  The copy
-// holds zeros in the padding slots, so a row's W entries are read without a test (the x
-// values they meet lie inside the padded vector, whose entries are finite).
+// time; a thread reads only its unit's slots.
 template <int N1C, int P>
 __device__ __forceinline__ double mem_apply(const BlockSolve<N1C, double, kMemMaxThreads>& W,
                                             const MemUnit<N1C, P>& G,
@@ -1699,7 +1700,7 @@ __device__ __forceinline__ double mem_apply(const BlockSolve<N1C, double, kMemMa
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int q = 0; q < WM; ++q)
-          v[r][q] = i0 + r < G.ni ? rp[(r * WM + q) * rs] : 0.0;
+          v[r][q] = (i0 + r < G.ni && q < G.wx) ? rp[(r * WM + q) * rs] : 0.0;
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         double acc = 0.0;
@@ -2196,7 +2197,7 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
   const size_t per = (size_t)Unit::CH * Unit::W * T;
   Unit R;
   const double* opb = nullptr;   // MEM: the element's slot-ordered operator
-  if constexpr (MEM) mem_unit(W, R);
+  if constexpr (MEM) mem_unit(W, a0.blk_unit, R);
   auto apply = [&W, &R, &opb](const double* v) {
     if constexpr (MEM) return mem_apply(W, R, opb, v);
     else return reg_apply(W, R, v);
@@ -2926,8 +2927,9 @@ static size_t blk_lds_bytes(const PcgGeom& g, int nnz_full, int WB, int K, int m
 }
 
 int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vector<int>& boff,
-                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx, int* K,
-                     int* CH, int* WB, int* nnz, int* threads, int mixed) {
+                     std::vector<int>& dst, std::vector<int>& jc, std::vector<int>& gidx,
+                     std::vector<int>& unit, int* K, int* CH, int* WB, int* nnz, int* threads,
+                     int mixed) {
   const int n1 = g.n1, N = g.N, p = g.p, nn = g.nn;
   if (n1 != 9 && n1 != 13 && n1 != 17) return 0;
   // the register-operator kernels run on fewer threads with taller chunks
@@ -2971,6 +2973,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
   const int thr = ((std::max(n1 * kk, sp * nn) + 63) / 64) * 64;
   if (thr > maxt) return 0;
   gidx.clear();
+  unit.clear();
   if (reg) {
     // upper-half index of every (unit, row, column) slot: the inverse of dst
     std::vector<int> inv((size_t)off, -1);
@@ -2979,6 +2982,22 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
       inv[dst[2 * h + 1]] = h;
     }
     const int W = std::min(2 * p + 1, n1);
+    // thread of each unit: the unit itself, or for the streamed family the units in order of
+    // decreasing width and height, so that the threads that read a slot form a prefix and a
+    // wave skips the cache lines of padding slots
+    std::vector<int> pos(n1 * kk);
+    for (int t = 0; t < n1 * kk; ++t) pos[t] = t;
+    if (chmax == kMemMaxCh) {
+      std::vector<int> ord(n1 * kk);
+      for (int t = 0; t < n1 * kk; ++t) ord[t] = t;
+      auto wxy = [&](int t) {
+        const int k = t / n1, ix = t % n1, jy = jc[k] & 0xff, c = jc[k] >> 8;
+        return std::make_pair(st_w(ix, p, N), std::min(ch, st_w(jy, p, N) - c * ch));
+      };
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wxy(a) > wxy(b); });
+      unit = ord;
+      for (int i = 0; i < n1 * kk; ++i) pos[ord[i]] = i;
+    }
     gidx.assign((size_t)ch * W * thr, -1);
     for (int t = 0; t < n1 * kk; ++t) {
       const int k = t / n1, ix = t % n1;
@@ -2988,7 +3007,7 @@ int pcg_block_tables(const PcgGeom& g, const std::vector<int>& rowoff, std::vect
         for (int q = 0; q < wx; ++q) {
           const int h = inv[boff[jy * n1 + ix] + (c * ch + i) * wx + q];
           if (h < 0) return 0;                    // every block entry is an operator entry
-          gidx[((size_t)i * W + q) * thr + t] = h;
+          gidx[((size_t)i * W + q) * thr + pos[t]] = h;
         }
     }
   }
