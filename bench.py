@@ -479,7 +479,7 @@ def main():
     ap.add_argument("--pcg-only", action="store_true",
                     help="profiling aid: run only the PCG workload (prints its section only)")
     ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
-    ap.add_argument("--pcg-precision", default="fp64", choices=["fp64", "mixed"],
+    ap.add_argument("--pcg-precision", default="fp64", choices=["fp64", "mixed", "pc32"],
                     help="precision of the PCG solves under --pcg-only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (HBM counter "
@@ -589,6 +589,9 @@ def main():
         msm, itm, stm = _time_pcg(pw, ksteps, 1, precision="mixed")
         print("bench: pcg mixed %.3f ms/step" % (msm / ksteps), file=sys.stderr, flush=True)
         dmix = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(stm, st64))
+        msp, itp, stp = _time_pcg(pw, ksteps, 1, precision="pc32")
+        print("bench: pcg pc32 %.3f ms/step" % (msp / ksteps), file=sys.stderr, flush=True)
+        dpc = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(stp, st64))
         flops = _pcg_flops_per_step(its, pn * pn, pN, pw["p"]) * ksteps / (ms * 1e-3)
         pbytes = _pcg_alg_bytes_per_dof_update(pN, pw["p"])
         pach = pbytes * pdof * ksteps / (ms * 1e-3)
@@ -616,6 +619,12 @@ def main():
                       "rel_diff_vs_fp64_state": dmix,
                       "note": "FP32 operator for the inner CG iterations, FP64 residual refinement "
                               "to the same rtol; same final tolerance as the FP64 path"},
+            "mixed_pc32": {"ms_per_step": msp / ksteps, "value": pdof * ksteps / (msp * 1e-3),
+                           "speedup_vs_fp64": ms / msp, "mean_it_S": itp["mean_it_S"],
+                           "mean_it_M": itp["mean_it_M"], "rel_diff_vs_fp64_state": dpc,
+                           "note": "preconditioner transforms on the FP32 matrix cores inside the "
+                                   "FP64 recurrence (operator products, residuals and the stop "
+                                   "test FP64); same rtol as the FP64 path"},
         }
     if not args.no_learned:
         out["learned"] = _learned_section(max(1, min(args.steps, 3)))

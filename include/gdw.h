@@ -67,8 +67,13 @@ typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1, GDW_FLUX_ALTERNATING =
  * path: the state stays FP64; the element operator is split into FP32 parts
  * hi = fl32(A), lo = fl32(A - hi); the inner PCG iterations use hi, and every solve is
  * refined with FP64 residuals b - (hi + lo) x until the FP64 residual meets pcg_rtol
- * (requires N + 1 in {9, 13, 17}; else EUNSUPPORTED). */
-typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1 } gdw_precision;
+ * (requires N + 1 in {9, 13, 17}; else EUNSUPPORTED).  GDW_MIXED_PC32, PCG path only: the
+ * tensor-product preconditioner's four transforms (Sec. 7.1) run in FP32 on the matrix
+ * cores inside the FP64 recurrence; operator products, residuals, the stop test and the
+ * state stay FP64, so the solves meet pcg_rtol as in GDW_FP64 (requires N + 1 in {9, 13}
+ * with p in {5, 7}, or N + 1 = 13 with p = 3; else EUNSUPPORTED; problems in this mode are
+ * not batched). */
+typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1, GDW_MIXED_PC32 = 2 } gdw_precision;
 
 /* Local solve.  FDM: simultaneous diagonalisation (Sec. 3.2), constant c^2 on
  * Cartesian elements only.  PCG: preconditioned conjugate gradients per element

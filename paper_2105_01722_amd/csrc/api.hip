@@ -71,7 +71,10 @@ static gdw_status validate(const gdw_desc* d) {
   if (d->flux == GDW_FLUX_UPWIND && (!(d->xi > 0) || !std::isfinite(d->xi))) {
     set_error("xi must be finite and > 0 for the upwind flux"); return GDW_EINVAL;
   }
-  if (d->precision != GDW_FP64 && d->precision != GDW_MIXED_FP32) { set_error("unknown precision"); return GDW_EINVAL; }
+  if (d->precision != GDW_FP64 && d->precision != GDW_MIXED_FP32 && d->precision != GDW_MIXED_PC32) {
+    set_error("unknown precision");
+    return GDW_EINVAL;
+  }
   if (d->solver != GDW_SOLVE_AUTO && d->solver != GDW_SOLVE_FDM && d->solver != GDW_SOLVE_PCG) {
     set_error("unknown solver"); return GDW_EINVAL;
   }
@@ -113,6 +116,10 @@ static gdw_status validate(const gdw_desc* d) {
     }
   }
   if (pcg && d->p > 7) { set_error("the PCG path supports p <= 7"); return GDW_EUNSUPPORTED; }
+  if (!pcg && d->precision == GDW_MIXED_PC32) {
+    set_error("GDW_MIXED_PC32 applies to the PCG path only");
+    return GDW_EUNSUPPORTED;
+  }
   if (!std::isfinite(d->pcg_rtol)) { set_error("pcg_rtol must be finite"); return GDW_EINVAL; }
   const double nel = double(d->nx) * d->ny * (d->N + 1) * (d->N + 1);
   if (nel > 4.0e9) { set_error("problem too large"); return GDW_EINVAL; }
@@ -426,6 +433,11 @@ static gdw_status create_pcg(const gdw_desc* d, gdw_ctx* c) {
     }
   }
   // the split stage's solve kernels keep no operator in LDS; the fused stage kernel does
+  if (d->precision == GDW_MIXED_PC32 &&
+      !(c->blk_v2 && c->blk_gidx != nullptr && pcg_pc32_supported(g.n1, g.p, c->blk_threads))) {
+    set_error("GDW_MIXED_PC32 needs N + 1 in {9, 13} with p in {5, 7}, or N + 1 = 13 with p = 3");
+    return GDW_EUNSUPPORTED;
+  }
   const bool split_stage = c->blk_v2 && c->blk_gidx != nullptr &&
                            d->precision != GDW_MIXED_FP32 &&
                            pcg_split_key(pcg_family_key(g.n1, g.p, 1, 0));
@@ -512,7 +524,7 @@ static gdw_status create_impl(const gdw_desc* d, gdw_ctx* c) {
   c->dim = d->dim == 3 ? 3 : 2;
   c->nel = (long)d->nx * d->ny * (c->dim == 3 ? d->nz : 1);
   c->nn = c->n1 * c->n1 * (c->dim == 3 ? c->n1 : 1);
-  c->elem_bytes = d->precision == GDW_FP64 ? 8 : 4;
+  c->elem_bytes = d->precision == GDW_MIXED_FP32 ? 4 : 8;
   // alternating flux: v* from the element on the low-coordinate side of a face, (grad u)*
   // from the one on the high side, i.e. alpha = 1 on an element's E and N faces and 0 on
   // its W and S faces (wall faces take 1/2 in the kernels)
@@ -785,6 +797,7 @@ PcgStageArgs pcg_stage_args(const gdw_ctx* c, int stage, double dt) {
   a.rtol_inner = 1e-6;
   a.maxit = c->maxit;
   a.mixed = c->d.precision == GDW_MIXED_FP32 ? 1 : 0;
+  a.pc32 = c->d.precision == GDW_MIXED_PC32 ? 1 : 0;
   a.fo = c->fo;
   a.dst = c->dst;
   if (c->blk_v2) {

@@ -476,6 +476,11 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
       s = GDW_EUNSUPPORTED;
       break;
     }
+    if (descs[i].precision == GDW_MIXED_PC32) {
+      set_error("problem " + std::to_string(i) + ": GDW_MIXED_PC32 problems are not batched");
+      s = GDW_EUNSUPPORTED;
+      break;
+    }
     gdw_ctx* c = nullptr;
     s = gdw_create(&descs[i], &c);
     if (s == GDW_OK) b->ctx.push_back(c);

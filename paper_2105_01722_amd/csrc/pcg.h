@@ -74,6 +74,7 @@ struct PcgStageArgs {
   double alf[4];        // alpha of Sec. 2.2.1 on the E, W, N, S faces (1/2 on wall faces)
   int maxit;
   int mixed;            // 1: FP32 operator for the inner PCG, FP64 residual refinement
+  int pc32;             // 1: the preconditioner's transforms in FP32 inside the FP64 PCG
   const int* fo;        // [nn+1] row starts of the full stencil rectangles
   const int* dst;       // [nst][2] full-rectangle positions (i,j), (j,i) of upper entry h
   int full, Q, nnz_full;  // set by the launcher: LDS layout of the operator
@@ -161,6 +162,9 @@ hipError_t launch_pcg_split_group(int stage, int key, const PcgStageArgs* args,
                                   const long* h_el_start_m, int nprob_m, const PcgStageArgs& h,
                                   int threads, hipStream_t st);
 bool pcg_split_key(int key);
+// Families that offer the preconditioner's transforms in FP32 (GDW_MIXED_PC32): the FP64
+// register families on the wave-0 solve kernels (N + 1 <= 16, 64 + blk_threads <= 512).
+bool pcg_pc32_supported(int n1, int p, int blk_threads);
 // Persistent grid of the grouped kernel of family `key` for nel elements.
 unsigned pcg_group_grid(int stage, int key, int threads, size_t lds, long nel);
 size_t pcg_stage_lds_bytes(const PcgGeom& g, int mixed);

@@ -2389,22 +2389,72 @@ __device__ __forceinline__ void w0_pinv(const double (&psk)[4], const double (&p
 
 struct W0Pre {
   double psk[4], pks[4];   // Psi[4 s + g][c], Psi[c][4 s + g] (0 outside)
+  // FP32 chain: Psi[4 s + g][c], Psi[4 g + s][c], Psi[c][4 g + s] (0 outside)
+  float psk1[4], psk2[4], pks2[4];
 };
 
-// Wave 0: u = sc P^-1 (sc r) (sc = 1 when not scaled), written to W.U as well.
+typedef float pcg_f4 __attribute__((ext_vector_type(4)));
+
+// Node of the FP32 chain's output register s on lane (g, c): (c, 4 g + s).
 template <int N1C>
+__device__ __forceinline__ bool w0_ok2(const W0Lane<N1C>& L, int s) {
+  return L.c < N1C && 4 * L.g + s < N1C;
+}
+
+// Wave 0: u = sc P^-1 (sc r) (sc = 1 when not scaled), written to W.U as well.  P32: the
+// four transforms on the FP32 matrix cores (v_mfma_f32_16x16x4f32), whose output register r
+// holds row 4 g + r (the FP64 instruction's holds 4 r + g): the products after the first
+// take the K index 4 g + s, di comes in that layout (node (c, 4 g + s) in di[s]), and the
+// result reaches the vector layout through U (LDS, same wave).  The recurrence, the
+// operator products and the residuals stay FP64.
+template <int N1C, bool P32 = false>
 __device__ __forceinline__ void w0_precond(const BlockSolve<N1C, double, kRegMaxThreads>& W,
                                            const W0Lane<N1C>& L, const W0Pre& Pp,
                                            const double (&di)[4], const double (&sc)[4],
                                            bool scaled, const double (&r)[4], double (&u)[4]) {
-  double rs[4];
+  if constexpr (P32) {
+    float rs[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) rs[s] = L.ok(s) ? (scaled ? r[s] * sc[s] : r[s]) : 0.0;
-  w0_pinv(Pp.psk, Pp.pks, di, rs, u);
+    for (int s = 0; s < 4; ++s) rs[s] = L.ok(s) ? (float)(scaled ? r[s] * sc[s] : r[s]) : 0.f;
+    pcg_f4 a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (scaled) u[s] *= sc[s];
-    if (L.ok(s)) W.U[L.pad(s)] = u[s];
+    for (int s = 0; s < 4; ++s)
+      a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rs[s], Pp.psk1[s], a1, 0, 0, 0);
+    pcg_f4 a2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], Pp.psk2[s], a2, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a2[s] *= (float)di[s];
+    pcg_f4 a3 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      a3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[s], Pp.pks2[s], a3, 0, 0, 0);
+    pcg_f4 a4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[s], Pp.pks2[s], a4, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (w0_ok2(L, s)) W.U[(4 * L.g + s) * (N1C + 1) + L.c] = (double)a4[s];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      u[s] = L.ok(s) ? W.U[L.pad(s)] : 0.0;
+      if (scaled) {
+        u[s] *= sc[s];
+        if (L.ok(s)) W.U[L.pad(s)] = u[s];
+      }
+    }
+  } else {
+    double rs[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) rs[s] = L.ok(s) ? (scaled ? r[s] * sc[s] : r[s]) : 0.0;
+    w0_pinv(Pp.psk, Pp.pks, di, rs, u);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (scaled) u[s] *= sc[s];
+      if (L.ok(s)) W.U[L.pad(s)] = u[s];
+    }
   }
 }
 
@@ -2457,7 +2507,7 @@ __device__ __forceinline__ void unit_rounds(const BlockSolve<N1C, double, kRegMa
 // Wave 0: PCG on (A + cw w w^T) x = b with the single-reduction recurrence of blk_solve_g;
 // x, b, w, di, sc are wave 0's (entries outside the element 0), x is the warm start on entry
 // and the solution on return; returns the iteration count (maxit + 1: no convergence).
-template <int N1C, int P>
+template <int N1C, int P, bool P32 = false>
 __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const W0Lane<N1C>& L,
                         const W0Pre& Pp, int* ctl, double (&x)[4], const double (&b)[4],
                         const double (&w)[4], const double (&di)[4], const double (&sc)[4],
@@ -2476,7 +2526,7 @@ __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const 
   const double tol2 = rtol * rtol * bb;
 #pragma unroll
   for (int s = 0; s < 4; ++s) r[s] = L.ok(s) ? b[s] - q[s] - cw * wx * w[s] : 0.0;
-  w0_precond(W, L, Pp, di, sc, scaled, r, u);
+  w0_precond<N1C, P32>(W, L, Pp, di, sc, scaled, r, u);
   // The scalars are kept as 1/gamma and 1/alpha, so that an iteration needs the two
   // reciprocals 1/ru and 1/(dn - beta ru / alpha), which do not depend on each other,
   // instead of three divisions in sequence.
@@ -2513,12 +2563,12 @@ __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const 
       x[s] += alpha * pv[s];
       r[s] -= alpha * sv[s];
     }
-    w0_precond(W, L, Pp, di, sc, scaled, r, u);
+    w0_precond<N1C, P32>(W, L, Pp, di, sc, scaled, r, u);
   }
 }
 
 // Wave 0 of the solve kernels: everything but the products.
-template <int OP, int N1C, int P>
+template <int OP, int N1C, int P, bool P32 = false>
 __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
                                            const BlockSolve<N1C, double, kRegMaxThreads>& W,
                                            const W0Lane<N1C>& L, const W0Pre& Pp, int* ctl) {
@@ -2573,16 +2623,19 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
       double di[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int iy = 4 * s + L.g;
+        // node of di[s]: (c, 4 s + g), or (c, 4 g + s) for the FP32 chain
+        const int iy = P32 ? 4 * L.g + s : 4 * s + L.g;
+        const bool ok = P32 ? w0_ok2(L, s) : L.ok(s);
         double dS = 1.0;
-        if (L.ok(s)) {
+        if (ok) {
           dS = (L.c == 0 && iy == 0) ? d00 : kbr * g.lamr[L.c] + kbs * g.lamr[iy];
-          if (pass == 0 && a.el.dlog && !(L.c == 0 && iy == 0)) dS *= dl[s];
+          if (pass == 0 && a.el.dlog && !(L.c == 0 && iy == 0))
+            dS *= P32 ? a.el.dscale[e0 + iy * N1C + L.c] : dl[s];
         }
-        di[s] = L.ok(s) ? 1.0 / dS : 0.0;
+        di[s] = ok ? 1.0 / dS : 0.0;
         y[s] = x0[s];
       }
-      itS = w0_solve<N1C, P>(W, L, Pp, ctl, y, fu, wt, di, one, false, cw, a.rtol, a.maxit);
+      itS = w0_solve<N1C, P, P32>(W, L, Pp, ctl, y, fu, wt, di, one, false, cw, a.rtol, a.maxit);
       if (!(a.el.dlog && itS > a.maxit)) break;
     }
     w0_end(ctl);
@@ -2604,8 +2657,8 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
       }
     const double area = scp[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) di[s] = L.ok(s) ? 1.0 / area : 0.0;
-    const int itM = w0_solve<N1C, P>(W, L, Pp, ctl, z, rv, zero, di, ms, a.el.msc != nullptr, 0.0,
+    for (int s = 0; s < 4; ++s) di[s] = (P32 ? w0_ok2(L, s) : L.ok(s)) ? 1.0 / area : 0.0;
+    const int itM = w0_solve<N1C, P, P32>(W, L, Pp, ctl, z, rv, zero, di, ms, a.el.msc != nullptr, 0.0,
                                      a.rtol, a.maxit);
     w0_end(ctl);
 #pragma unroll
@@ -2618,7 +2671,8 @@ __device__ __forceinline__ void w0_element(const PcgStageArgs& a, long e,
 // Solve kernels: wave 0 runs the recurrence (w0_element), waves 1.. hold the operator in
 // registers (unit u = threadIdx.x - 64 of the slot-ordered copy) and form the products.  The
 // two roles meet only at the barriers of the product rounds, so each keeps its own registers.
-template <int OP, int N1C, int P, bool GRP>
+// P32: the preconditioner's transforms on the FP32 matrix cores (w0_precond).
+template <int OP, int N1C, int P, bool GRP, bool P32 = false>
 __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(
     const PcgStageArgs* __restrict__ args, const long* __restrict__ el_start, int nprob) {
   static_assert(N1C <= 16, "one matrix-core tile");
@@ -2661,6 +2715,13 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(
         const bool in = L.c < n1 && q < n1;
         Pp.psk[s] = in ? g.Psi[q * n1 + L.c] : 0.0;
         Pp.pks[s] = in ? g.Psi[L.c * n1 + q] : 0.0;
+        if constexpr (P32) {
+          const int q2 = 4 * L.g + s;
+          const bool in2 = L.c < n1 && q2 < n1;
+          Pp.psk1[s] = (float)Pp.psk[s];
+          Pp.psk2[s] = in2 ? (float)g.Psi[q2 * n1 + L.c] : 0.f;
+          Pp.pks2[s] = in2 ? (float)g.Psi[L.c * n1 + q2] : 0.f;
+        }
       }
     };
     if constexpr (!GRP) load_pre(a0.g);
@@ -2675,7 +2736,7 @@ __global__ __launch_bounds__(kRegMaxThreads) void k_pcg_solve_w0(
           cur = k;
         }
       }
-      w0_element<OP, N1C, P>(a, b - rg.first(k), W, L, Pp, ctl);
+      w0_element<OP, N1C, P, P32>(a, b - rg.first(k), W, L, Pp, ctl);
     }
   } else {
     // two operator buffers: the next element's entries load while this element's rounds run
@@ -3148,6 +3209,11 @@ int pcg_group_key(const PcgStageArgs& a) { return pcg_family_key(a.g.n1, a.g.p, 
 // ---- split stage (host) ---------------------------------------------------------------
 bool pcg_split_key(int key) { return (key & 64) != 0 && pcg_key_known(key); }
 
+bool pcg_pc32_supported(int n1, int p, int blk_threads) {
+  return n1 <= 16 && pcg_split_key(pcg_family_key(n1, p, 1, 0)) &&
+         64 + blk_threads <= kRegMaxThreads;
+}
+
 static int split_threads(const PcgGeom& g) {
   const int b = ((g.nn + 63) / 64) * 64;
   return b < 128 ? 128 : b;
@@ -3163,27 +3229,41 @@ struct SplitSet {
   long total;
 };
 
+// Wave-0 solve launch (k_pcg_solve_w0), FP64 or FP32 preconditioner chain.
+template <int N1C, int P, bool GRP, bool P32>
+static hipError_t split_solve_w0(int op, const SplitSet& S, const PcgStageArgs& h,
+                                 hipStream_t st) {
+  const size_t lds = ((size_t)N1C * N1C * h.blk_WB + (N1C + 1) * (N1C + 1)) * sizeof(double) +
+                     (size_t)(h.blk_K + 1) * sizeof(int);
+  const int thr = 64 + h.blk_threads;
+  const void* k = op == 0 ? (const void*)k_pcg_solve_w0<0, N1C, P, GRP, P32>
+                          : (const void*)k_pcg_solve_w0<1, N1C, P, GRP, P32>;
+  const unsigned grid = persistent_grid(k, thr, lds, S.total);
+  if (op == 0)
+    hipLaunchKernelGGL((k_pcg_solve_w0<0, N1C, P, GRP, P32>), dim3(grid), dim3(thr), lds, st,
+                       S.args, S.el_start, S.nprob);
+  else
+    hipLaunchKernelGGL((k_pcg_solve_w0<1, N1C, P, GRP, P32>), dim3(grid), dim3(thr), lds, st,
+                       S.args, S.el_start, S.nprob);
+  return hipGetLastError();
+}
+
 template <int N1C, int P, bool GRP>
 static hipError_t split_solve_t(int op, const SplitSet& S, const PcgStageArgs& h, int threads,
                                 hipStream_t st) {
   if constexpr (N1C <= 16) {
     if (64 + h.blk_threads <= kRegMaxThreads) {
-      // vectors on wave 0, work units on the waves after it
-      const size_t lds = ((size_t)N1C * N1C * h.blk_WB + (N1C + 1) * (N1C + 1)) * sizeof(double) +
-                         (size_t)(h.blk_K + 1) * sizeof(int);
-      const int thr = 64 + h.blk_threads;
-      const void* k = op == 0 ? (const void*)k_pcg_solve_w0<0, N1C, P, GRP>
-                              : (const void*)k_pcg_solve_w0<1, N1C, P, GRP>;
-      const unsigned grid = persistent_grid(k, thr, lds, S.total);
-      if (op == 0)
-        hipLaunchKernelGGL((k_pcg_solve_w0<0, N1C, P, GRP>), dim3(grid), dim3(thr), lds, st,
-                           S.args, S.el_start, S.nprob);
-      else
-        hipLaunchKernelGGL((k_pcg_solve_w0<1, N1C, P, GRP>), dim3(grid), dim3(thr), lds, st,
-                           S.args, S.el_start, S.nprob);
-      return hipGetLastError();
+      // vectors on wave 0, work units on the waves after it (the FP32 preconditioner chain
+      // for single problems only)
+      if constexpr (!GRP) {
+        if (h.pc32) return split_solve_w0<N1C, P, GRP, true>(op, S, h, st);
+      } else {
+        if (h.pc32) return hipErrorInvalidValue;
+      }
+      return split_solve_w0<N1C, P, GRP, false>(op, S, h, st);
     }
   }
+  if (h.pc32) return hipErrorInvalidValue;     // no FP32 chain in the per-node kernels
   const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
   const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, GRP>
                           : (const void*)k_pcg_solve<1, N1C, P, GRP>;
@@ -3212,7 +3292,7 @@ static hipError_t split_solve(int op, const SplitSet& S, const PcgStageArgs& h, 
 template <int N1C, int P>
 static hipError_t split_solve_mem(int op, const SplitSet& S, const PcgStageArgs& h, int threads,
                                   hipStream_t st) {
-  if (S.el_start || h.blk_threads != kMemMaxThreads || threads != kMemMaxThreads)
+  if (S.el_start || h.pc32 || h.blk_threads != kMemMaxThreads || threads != kMemMaxThreads)
     return hipErrorInvalidValue;   // the kernel's compiled slot stride
   const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
   const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, false, true>

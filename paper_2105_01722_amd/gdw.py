@@ -14,7 +14,7 @@ LIB_PATH = os.environ.get("GDW_LIB") or os.path.join(_HERE, "libgdw.so")
 GDW_OK, GDW_EINVAL, GDW_ENOMEM, GDW_EHIP, GDW_ENOCONV, GDW_ENONFINITE, GDW_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 GDW_FLUX_CENTRAL, GDW_FLUX_UPWIND, GDW_FLUX_ALTERNATING = 0, 1, 2
-GDW_FP64, GDW_MIXED_FP32 = 0, 1
+GDW_FP64, GDW_MIXED_FP32, GDW_MIXED_PC32 = 0, 1, 2
 GDW_SOLVE_AUTO, GDW_SOLVE_FDM, GDW_SOLVE_PCG = 0, 1, 2
 GDW_BC_PERIODIC, GDW_BC_DIRICHLET, GDW_BC_NEUMANN = 0, 1, 2
 _BC = {"periodic": GDW_BC_PERIODIC, "dirichlet": GDW_BC_DIRICHLET, "neumann": GDW_BC_NEUMANN}
@@ -185,7 +185,8 @@ def make_desc(nx, ny, N, p, c2=1.0, flux="central", xi=1.0, precision="fp64", so
     d.flux = {"central": GDW_FLUX_CENTRAL, "upwind": GDW_FLUX_UPWIND,
               "alternating": GDW_FLUX_ALTERNATING}[flux]
     d.xi = xi
-    d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32}[precision]
+    d.precision = {"fp64": GDW_FP64, "fp32": GDW_MIXED_FP32, "mixed": GDW_MIXED_FP32,
+                   "pc32": GDW_MIXED_PC32}[precision]
     d.solver = {"auto": GDW_SOLVE_AUTO, "fdm": GDW_SOLVE_FDM, "pcg": GDW_SOLVE_PCG}[solver]
     d.coeff_variable = int(bool(coeff_variable))
     d.mapped = int(bool(mapped))

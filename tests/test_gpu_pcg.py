@@ -160,6 +160,83 @@ def test_pcg_mixed_matches_dense_oracle(n, N, p, mapped, variable):
     assert st["mean_refine"] >= 1.0
 
 
+@pytest.mark.parametrize("n,N,p,mapped,variable", [(3, 12, 5, True, True), (2, 8, 7, True, True),
+                                                   (3, 12, 3, False, True), (2, 8, 5, True, True),
+                                                   (2, 12, 7, True, True)])
+def test_pcg_pc32_matches_dense_oracle(n, N, p, mapped, variable):
+    """GDW_MIXED_PC32: the preconditioner's four transforms on the FP32 matrix cores inside
+    the FP64 recurrence.  Operator products, residuals and the stop test stay FP64, so the
+    solves meet the same rtol: the state meets the FP64 bar against the dense oracle
+    (1e-12 at pcg_rtol 1e-13), and the iteration means stay within 0.5 of the FP64 run's
+    (a preconditioner perturbed at 2^-24 changes the Krylov space only at that level)."""
+    _say("case: pcg pc32 vs dense", n, N, p, mapped, variable)
+    Xm, Ym, c2, U0, V0 = _problem(n, N, p, mapped, variable)
+    dt, steps = 0.1 / (n * N), 3
+    Ug, Vg, Eg, st = _gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, mapped, variable,
+                          precision="pc32")
+    _, _, _, sf = _gpu(n, N, p, Xm, Ym, c2, U0, V0, dt, steps, mapped, variable)
+    assert st["status"] == 0 and st["fail_elem"] == -1
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind"), Xm, Ym, c2)
+    Uo, Vo = general.run(U0, V0, ops, dt, steps)
+    _say("  rel U %.2e V %.2e  its S %.2f (fp64 %.2f) M %.2f (fp64 %.2f)"
+         % (_rel(Ug, Uo), _rel(Vg, Vo), st["mean_it_S"], sf["mean_it_S"], st["mean_it_M"],
+            sf["mean_it_M"]))
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
+    Eo = general.energy(Uo, Vo, ops)
+    assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
+    assert abs(st["mean_it_S"] - sf["mean_it_S"]) <= 0.5
+    assert abs(st["mean_it_M"] - sf["mean_it_M"]) <= 0.5
+
+
+def test_pcg_pc32_with_learned_correction():
+    """The corrected S_hat preconditioner (per-node log-scales of the modal diagonal) in the
+    FP32 chain's layout: with a random correction the state still matches the dense oracle
+    at the FP64 bar, and its iteration count equals the FP64 run's with the same correction
+    to within 0.5."""
+    from paper_2105_01722_amd import gdw
+    _say("case: pcg pc32 learned correction")
+    n, N, p = 3, 12, 5
+    Xm, Ym, c2, U0, V0 = _problem(n, N, p, True, True)
+    dt, steps = 0.1 / (n * N), 2
+    rng = np.random.default_rng(11)
+    corr = (0.2 * rng.standard_normal((n * n, (N + 1) ** 2 - 1))).astype(np.float32)
+    out = {}
+    for prec in ("pc32", "fp64"):
+        s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
+                       mapped=True, pcg_rtol=1e-13, pcg_maxit=200, precision=prec)
+        s.set_coeff(c2, Xm, Ym)
+        s.set_precond_log(corr)
+        s.set_state(U0, V0)
+        s.run(dt, steps)
+        U, V = s.get_state()
+        out[prec] = (U.cpu().numpy(), V.cpu().numpy(), s.stats(check=False))
+        s.close()
+    ops = general.GenOps(general.GenProblem(nx=n, ny=n, N=N, p=p, flux="upwind"), Xm, Ym, c2)
+    Uo, Vo = general.run(U0, V0, ops, dt, steps)
+    Ug, Vg, st = out["pc32"]
+    assert st["status"] == 0
+    assert_close(Ug, Uo, 1e-12)
+    assert_close(Vg, Vo, 1e-12)
+    assert abs(st["mean_it_S"] - out["fp64"][2]["mean_it_S"]) <= 0.5
+
+
+def test_pcg_pc32_unsupported():
+    """GDW_MIXED_PC32 is refused where no FP32 chain exists: the constant-coefficient path,
+    N + 1 = 17 and N + 1 = 9 with p = 3 (per-node solve kernels), and inside a batch."""
+    from paper_2105_01722_amd import gdw
+    for kw in (dict(nx=2, ny=2, N=8, p=3, solver="fdm"),
+               dict(nx=2, ny=2, N=16, p=5, solver="pcg", coeff_variable=True),
+               dict(nx=2, ny=2, N=8, p=3, solver="pcg", coeff_variable=True)):
+        with pytest.raises(gdw.GdwError) as ei:
+            gdw.Solver(flux="upwind", precision="pc32", **kw)
+        assert ei.value.status == gdw.GDW_EUNSUPPORTED
+    with pytest.raises(gdw.GdwError) as ei:
+        gdw.Batch([dict(nx=2, ny=2, N=12, p=5, flux="upwind", solver="pcg",
+                        coeff_variable=True, precision="pc32")])
+    assert ei.value.status == gdw.GDW_EUNSUPPORTED
+
+
 def test_pcg_mixed_unsupported_size():
     """Mixed precision needs N + 1 in {9, 13, 17}: other sizes are refused at creation."""
     from paper_2105_01722_amd import gdw
