@@ -133,9 +133,10 @@ const char* gdw_last_error(void);
  * modal index of an element) or anything but the constant-coefficient Cartesian path, and
  * for the PCG path with p > 7 or, outside the FP64 families whose solves keep no operator
  * in LDS (N + 1 = 9, 13 with p = 3, 5, 7; N + 1 = 17 with p = 3, 5, 7), an element operator
- * that does not fit the 160 KiB of LDS of a workgroup, and for the PCG path in
- * GDW_MIXED_FP32 with N + 1 outside {9, 13, 17}; ENOMEM / EHIP from the device.  Uses the
- * current HIP device;
+ * that does not fit the 160 KiB of LDS of a workgroup, for the PCG path in
+ * GDW_MIXED_FP32 with N + 1 outside {9, 13, 17}, and for GDW_MIXED_PC32 on the
+ * constant-coefficient path or outside the PCG families that offer it; ENOMEM / EHIP from
+ * the device.  Uses the current HIP device;
  * synchronous. */
 gdw_status gdw_create(const gdw_desc* desc, gdw_ctx** out);
 
@@ -310,8 +311,8 @@ gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* strea
 typedef struct gdw_batch gdw_batch;
 
 /* Create the batch; 1 <= nprob <= 4096.  Errors: those of gdw_create for a problem
- * (the message names it), EUNSUPPORTED for a 3D problem; nothing is left allocated on
- * error. */
+ * (the message names it), EUNSUPPORTED for a 3D problem or one in GDW_MIXED_PC32; nothing
+ * is left allocated on error. */
 gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_batch** out);
 
 /* Context of problem i, owned by the batch: set its coefficients and state, read its
