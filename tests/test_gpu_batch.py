@@ -41,6 +41,11 @@ PROBLEMS = [
          pcg_rtol=1e-13),
     dict(nx=2, ny=3, N=12, p=7, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
          pcg_rtol=1e-13),
+    # the streamed family (N+1 = 17, p = 7): a mapped and a Cartesian member, so that the
+    # class's M_J solves cover only one of them
+    dict(nx=2, ny=2, N=16, p=7, flux="upwind", solver="pcg", coeff_variable=True, mapped=True,
+         pcg_rtol=1e-13),
+    dict(nx=3, ny=2, N=16, p=7, flux="upwind", solver="pcg", coeff_variable=True, pcg_rtol=1e-13),
     # members with walls, grouped with periodic members of the same class
     dict(nx=3, ny=2, N=8, p=3, flux="upwind", precision="fp64", bc=("dirichlet",) * 4),
     dict(nx=4, ny=3, N=8, p=5, flux="upwind", precision="fp32",
