@@ -305,8 +305,10 @@ gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* strea
  * precision and N+1, PCG problems by N+1), and the four stages of one step are captured
  * once into a HIP graph that gdw_batch_run launches once per step.  Launch shapes
  * (elements per workgroup, block size, grid size) are chosen per class by timing the
- * candidates on the problems' own data (gdw_batch_tune).  Every problem advances exactly
- * as gdw_run would advance it alone.
+ * candidates on the problems' own data (gdw_batch_tune) and kept for the life of the
+ * process, keyed by the device architecture, path, arithmetic, kernel family and member
+ * sizes: a later class with the same key takes the stored shape untimed.  Every problem
+ * advances exactly as gdw_run would advance it alone.
  * --------------------------------------------------------------------------------- */
 typedef struct gdw_batch gdw_batch;
 

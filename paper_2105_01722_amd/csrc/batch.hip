@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -257,12 +258,61 @@ static gdw_status time_launch(F&& f, hipStream_t st, int reps, float* ms) {
   return GDW_OK;
 }
 
+// Launch shapes chosen by the tuner, kept for the life of the process and keyed by the
+// device architecture, the path, the arithmetic type, the kernel family and the sizes of the
+// class's members: a later batch with a class of the same key takes the shape untimed.
+struct TunedShape {
+  int a = 0;            // FDM: elements per tile; PCG: block size
+  unsigned grid = 0;
+  size_t lds = 0;
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, TunedShape> g_tuned;
+
+static std::string tune_key(const char* path, int elem_bytes, int family,
+                            const std::vector<int>& members, const std::vector<gdw_ctx*>& ctx) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string k = "?";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    k = prop.gcnArchName;
+  k += std::string("|") + path + "|" + std::to_string(elem_bytes) + "|" + std::to_string(family);
+  for (int i : members) k += "|" + std::to_string(ctx[i]->nel);
+  return k;
+}
+
+static bool tuned_lookup(const std::string& key, TunedShape* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+static void tuned_store(const std::string& key, const TunedShape& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = v;
+}
+
 static gdw_status tune_fdm(gdw_batch* b, FdmClass& c, const std::vector<double>& dt,
                            hipStream_t st, std::string& log) {
+  char buf[160];
+  const std::string key = tune_key("fdm", c.elem_bytes, c.n1, c.members, b->ctx);
+  TunedShape ts;
+  if (tuned_lookup(key, &ts)) {
+    (void)dt;
+    (void)st;
+    c.epb = ts.a;
+    c.grid = ts.grid;
+    std::snprintf(buf, sizeof buf, "  fdm n1=%d %s: epb=%d grid=%u (cached)\n", c.n1,
+                  c.elem_bytes == 8 ? "f64" : "f32", c.epb, c.grid);
+    log += buf;
+    return upload_fdm_tiles(c, b->ctx);
+  }
   float best = 1e30f;
   int best_epb = 0;
   unsigned best_grid = 0;
-  char buf[160];
   for (int epb : {1, 2, 4, 8}) {
     if (stage_lds_bytes(c.n1, epb) > 65536) continue;
     c.epb = epb;
@@ -292,6 +342,9 @@ static gdw_status tune_fdm(gdw_batch* b, FdmClass& c, const std::vector<double>&
   if (!best_epb) { set_error("no launch shape fits this class"); return GDW_EUNSUPPORTED; }
   c.epb = best_epb;
   c.grid = best_grid;
+  ts.a = best_epb;
+  ts.grid = best_grid;
+  tuned_store(key, ts);
   return upload_fdm_tiles(c, b->ctx);
 }
 
@@ -311,6 +364,20 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
     std::snprintf(buf, sizeof buf, "  pcg key=%d: split stage, %d of %zu members mapped\n", c.n1,
                   c.n_mapped, c.members.size());
     log += buf;
+    return GDW_OK;
+  }
+  const std::string key = tune_key("pcg", 8, c.n1, c.members, b->ctx);
+  TunedShape ts;
+  if (tuned_lookup(key, &ts)) {
+    gdw_status s2;
+    if ((s2 = upload_pcg_el(c, b->ctx)) != GDW_OK) return s2;
+    c.threads = ts.a;
+    c.grid = ts.grid;
+    c.lds = ts.lds;
+    char buf2[160];
+    std::snprintf(buf2, sizeof buf2, "  pcg key=%d: threads=%d grid=%u lds=%zu (cached)\n", c.n1,
+                  c.threads, c.grid, c.lds);
+    log += buf2;
     return GDW_OK;
   }
   // scratch warm starts / counters (copies of the real ones)
@@ -381,6 +448,10 @@ static gdw_status tune_pcg(gdw_batch* b, PcgClass& c, const std::vector<double>&
   c.threads = best_thr;
   c.grid = best_grid;
   c.lds = best_lds;
+  ts.a = best_thr;
+  ts.grid = best_grid;
+  ts.lds = best_lds;
+  tuned_store(key, ts);
   return GDW_OK;
 }
 

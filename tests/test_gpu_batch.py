@@ -157,3 +157,33 @@ def test_batch_pcg_member_matches_oracle():
     _say("  batch pcg member vs oracle: U %.2e V %.2e" % (eu, ev))
     assert_close(U.cpu().numpy(), Uo, 1e-12)
     assert_close(V.cpu().numpy(), Vo, 1e-12)
+
+
+def test_batch_reuses_tuned_shapes():
+    """The tuner's launch shapes are kept for the life of the process, keyed by architecture,
+    path, arithmetic, kernel family and member sizes: a second batch with the same classes
+    takes them untimed (its plan marks every tuned class cached) and advances its problems
+    bitwise as the first batch did."""
+    from paper_2105_01722_amd import gdw
+    probs = [PROBLEMS[0], PROBLEMS[3],
+             dict(nx=2, ny=2, N=12, p=5, flux="upwind", solver="pcg", coeff_variable=True,
+                  mapped=True, precision="mixed", pcg_rtol=1e-12)]
+    plans, states = [], []
+    for rep in range(2):
+        _say("case: tuned shapes, batch %d" % rep)
+        b = gdw.Batch(probs)
+        for i, kw in enumerate(probs):
+            _prepare(b.problems[i], 40 + i, kw)
+        dts = [_dt(kw) for kw in probs]
+        b.tune(dts)
+        plans.append(b.plan())
+        b.run(dts, 2)
+        states.append([tuple(x.cpu().numpy() for x in b.problems[i].get_state())
+                       for i in range(len(probs))])
+        b.close()
+    cand = plans[1].split("candidates:")[1]
+    _say(cand)
+    assert cand.count("(cached)") == 3 and " ms" not in cand
+    for (U0, V0), (U1, V1) in zip(states[0], states[1]):
+        np.testing.assert_array_equal(U0, U1)
+        np.testing.assert_array_equal(V0, V1)
