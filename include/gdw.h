@@ -71,8 +71,7 @@ typedef enum { GDW_FLUX_CENTRAL = 0, GDW_FLUX_UPWIND = 1, GDW_FLUX_ALTERNATING =
  * tensor-product preconditioner's four transforms (Sec. 7.1) run in FP32 on the matrix
  * cores inside the FP64 recurrence; operator products, residuals, the stop test and the
  * state stay FP64, so the solves meet pcg_rtol as in GDW_FP64 (requires N + 1 in {9, 13}
- * with p in {5, 7}, or N + 1 = 13 with p = 3; else EUNSUPPORTED; problems in this mode are
- * not batched). */
+ * with p in {5, 7}, or N + 1 = 13 with p = 3; else EUNSUPPORTED). */
 typedef enum { GDW_FP64 = 0, GDW_MIXED_FP32 = 1, GDW_MIXED_PC32 = 2 } gdw_precision;
 
 /* Local solve.  FDM: simultaneous diagonalisation (Sec. 3.2), constant c^2 on
@@ -313,8 +312,8 @@ gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* strea
 typedef struct gdw_batch gdw_batch;
 
 /* Create the batch; 1 <= nprob <= 4096.  Errors: those of gdw_create for a problem
- * (the message names it), EUNSUPPORTED for a 3D problem or one in GDW_MIXED_PC32; nothing
- * is left allocated on error. */
+ * (the message names it), EUNSUPPORTED for a 3D problem; nothing is left allocated on
+ * error. */
 gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_batch** out);
 
 /* Context of problem i, owned by the batch: set its coefficients and state, read its

@@ -517,7 +517,9 @@ static void make_plan(gdw_batch* b, const std::string& log) {
   for (auto& c : b->pcg) {
     char fam[48];
     if (c.n1 == 0) std::snprintf(fam, sizeof fam, "rows");
-    else if (c.n1 & 64) std::snprintf(fam, sizeof fam, "blocks n1=%d (registers, p=%d)", c.n1 & 31, c.n1 >> 7);
+    else if (c.n1 & 64)
+      std::snprintf(fam, sizeof fam, "blocks n1=%d (registers, p=%d%s)", c.n1 & 31, c.n1 >> 7,
+                    b->ctx[c.members[0]]->d.precision == GDW_MIXED_PC32 ? ", FP32 chain" : "");
     else if (c.n1 & 32) std::snprintf(fam, sizeof fam, "mixed n1=%d", c.n1 & 31);
     else std::snprintf(fam, sizeof fam, "blocks n1=%d", c.n1 & 31);
     if (c.split)
@@ -547,11 +549,6 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
       s = GDW_EUNSUPPORTED;
       break;
     }
-    if (descs[i].precision == GDW_MIXED_PC32) {
-      set_error("problem " + std::to_string(i) + ": GDW_MIXED_PC32 problems are not batched");
-      s = GDW_EUNSUPPORTED;
-      break;
-    }
     gdw_ctx* c = nullptr;
     s = gdw_create(&descs[i], &c);
     if (s == GDW_OK) b->ctx.push_back(c);
@@ -574,7 +571,8 @@ extern "C" gdw_status gdw_batch_create(int nprob, const gdw_desc* descs, gdw_bat
         // register-operator kernels, the degree
         const int fam = pcg_family_key(c->n1, c->d.p, c->blk_v2,
                                        c->d.precision == GDW_MIXED_FP32);
-        auto key = std::make_pair(fam, 0);
+        // (the FP32 preconditioner chain is a kernel variant of its family)
+        auto key = std::make_pair(fam, c->d.precision == GDW_MIXED_PC32 ? 1 : 0);
         if (!pk.count(key)) { pk[key] = b->pcg.size(); b->pcg.emplace_back(); b->pcg.back().n1 = fam; }
         b->pcg[pk[key]].members.push_back(i);
       } else {

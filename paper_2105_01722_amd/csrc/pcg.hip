@@ -3253,13 +3253,8 @@ static hipError_t split_solve_t(int op, const SplitSet& S, const PcgStageArgs& h
                                 hipStream_t st) {
   if constexpr (N1C <= 16) {
     if (64 + h.blk_threads <= kRegMaxThreads) {
-      // vectors on wave 0, work units on the waves after it (the FP32 preconditioner chain
-      // for single problems only)
-      if constexpr (!GRP) {
-        if (h.pc32) return split_solve_w0<N1C, P, GRP, true>(op, S, h, st);
-      } else {
-        if (h.pc32) return hipErrorInvalidValue;
-      }
+      // vectors on wave 0, work units on the waves after it
+      if (h.pc32) return split_solve_w0<N1C, P, GRP, true>(op, S, h, st);
       return split_solve_w0<N1C, P, GRP, false>(op, S, h, st);
     }
   }

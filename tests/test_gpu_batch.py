@@ -187,3 +187,33 @@ def test_batch_reuses_tuned_shapes():
     for (U0, V0), (U1, V1) in zip(states[0], states[1]):
         np.testing.assert_array_equal(U0, U1)
         np.testing.assert_array_equal(V0, V1)
+
+
+def test_batch_pc32_members_equal_solo_runs():
+    """Problems with the FP32 preconditioner chain (GDW_MIXED_PC32) form classes of their
+    own beside FP64 members of the same family; each advances as its solo run (1e-12, as the
+    other PCG members)."""
+    from paper_2105_01722_amd import gdw
+    base = dict(flux="upwind", solver="pcg", coeff_variable=True, pcg_rtol=1e-13)
+    probs = [dict(nx=2, ny=3, N=12, p=5, mapped=True, precision="pc32", **base),
+             dict(nx=3, ny=2, N=12, p=5, mapped=True, precision="fp64", **base),
+             dict(nx=3, ny=3, N=8, p=5, precision="pc32", **base),
+             dict(nx=2, ny=2, N=12, p=5, mapped=True, precision="pc32", **base)]
+    b = gdw.Batch(probs)
+    for i, kw in enumerate(probs):
+        _prepare(b.problems[i], 60 + i, kw)
+    dts = [_dt(kw) for kw in probs]
+    b.run(dts, 3)
+    plan = b.plan()
+    _say(plan.split("candidates:")[0])
+    assert plan.count("FP32 chain") == 2
+    got = [tuple(x.cpu().numpy() for x in b.problems[i].get_state()) for i in range(len(probs))]
+    b.close()
+    for i, kw in enumerate(probs):
+        s = gdw.Solver(**kw)
+        _prepare(s, 60 + i, kw)
+        s.run(dts[i], 3)
+        U, V = (x.cpu().numpy() for x in s.get_state())
+        s.close()
+        assert_close(got[i][0], U, 1e-12)
+        assert_close(got[i][1], V, 1e-12)

@@ -223,7 +223,7 @@ def test_pcg_pc32_with_learned_correction():
 
 def test_pcg_pc32_unsupported():
     """GDW_MIXED_PC32 is refused where no FP32 chain exists: the constant-coefficient path,
-    N + 1 = 17 and N + 1 = 9 with p = 3 (per-node solve kernels), and inside a batch."""
+    and N + 1 = 17 or N + 1 = 9 with p = 3 (per-node solve kernels), also inside a batch."""
     from paper_2105_01722_amd import gdw
     for kw in (dict(nx=2, ny=2, N=8, p=3, solver="fdm"),
                dict(nx=2, ny=2, N=16, p=5, solver="pcg", coeff_variable=True),
@@ -232,7 +232,7 @@ def test_pcg_pc32_unsupported():
             gdw.Solver(flux="upwind", precision="pc32", **kw)
         assert ei.value.status == gdw.GDW_EUNSUPPORTED
     with pytest.raises(gdw.GdwError) as ei:
-        gdw.Batch([dict(nx=2, ny=2, N=12, p=5, flux="upwind", solver="pcg",
+        gdw.Batch([dict(nx=2, ny=2, N=16, p=5, flux="upwind", solver="pcg",
                         coeff_variable=True, precision="pc32")])
     assert ei.value.status == gdw.GDW_EUNSUPPORTED
 
