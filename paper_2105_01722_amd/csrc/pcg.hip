@@ -2526,6 +2526,10 @@ __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const 
   const double tol2 = rtol * rtol * bb;
 #pragma unroll
   for (int s = 0; s < 4; ++s) r[s] = L.ok(s) ? b[s] - q[s] - cw * wx * w[s] : 0.0;
+  // The stop test reads |r|^2 as soon as r is updated (a wave reduction, no barrier), so a
+  // converged solve skips the preconditioning and the product that the single-reduction
+  // form would otherwise spend before the test; the counts and iterates are unchanged.
+  if (w0_dot(r, r) <= tol2) return 0;
   w0_precond<N1C, P32>(W, L, Pp, di, sc, scaled, r, u);
   // The scalars are kept as 1/gamma and 1/alpha, so that an iteration needs the two
   // reciprocals 1/ru and 1/(dn - beta ru / alpha), which do not depend on each other,
@@ -2533,8 +2537,7 @@ __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const 
   double alpha = 0.0, igam = 0.0, ialpha = 0.0;
   for (int it = 0;; ++it) {
     w0_product<N1C, P>(W, L, ctl, q);
-    const double ru = w0_dot(r, u), qu = w0_dot(q, u), wu = w0_dot(w, u), rr = w0_dot(r, r);
-    if (rr <= tol2) return it;
+    const double ru = w0_dot(r, u), qu = w0_dot(q, u), wu = w0_dot(w, u);
     const double dn = qu + cw * wu * wu;
     const double iru = 1.0 / ru;
     if (it == 0) {
@@ -2563,6 +2566,7 @@ __device__ int w0_solve(const BlockSolve<N1C, double, kRegMaxThreads>& W, const 
       x[s] += alpha * pv[s];
       r[s] -= alpha * sv[s];
     }
+    if (w0_dot(r, r) <= tol2) return it + 1;
     w0_precond<N1C, P32>(W, L, Pp, di, sc, scaled, r, u);
   }
 }
