@@ -1213,7 +1213,12 @@ __device__ __forceinline__ void blk_pinv(const BlockSolve<N1C, TA, MT>& W,
 // x = 0 on entry (the first product is skipped).  scaled (uniform over the block): the
 // preconditioner is P^-1 r -> sc P^-1 (sc r) with sc this owner's nodal scale; the scaled
 // vector is written back to W.U before the product reads it.
-template <int N1C, typename TA, int MT, typename App>
+// EARLY: the stop test reads |r|^2 (one more workgroup reduction, in red[64..79], apart from
+// the others' slots) as soon as r is updated, so a converged solve skips its last
+// preconditioning and product; worth it where a product costs far more than a reduction
+// (operators read from memory in every product).  The counts and iterates are those of the
+// plain form.
+template <int N1C, typename TA, int MT, typename App, bool EARLY = false>
 __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App&& apply, double* red,
                                            double& x, double bval, double cw, double wt,
                                            double rtol, int maxit, bool zero_start,
@@ -1239,6 +1244,15 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
     return 0;
   }
   double r = own ? bval - ax - cw * s2[0] * wt : 0.0;
+  const double tol2 = rtol * rtol * bb;
+  if constexpr (EARLY) {
+    double e1[1] = {r * r};
+    block_sum<1, false>(e1, red + 64, nn);
+    if (e1[0] <= tol2) {
+      __syncthreads();
+      return 0;
+    }
+  }
   if (own) W.R[pidx] = scaled ? r * sc : r;
   __syncthreads();
   blk_pinv(W, W.R, W.U);
@@ -1251,7 +1265,6 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
   double q = apply(W.U);
   double s4[4] = {r * u, q * u, wt * u, r * r};
   block_sum<4, false>(s4, red, nn);
-  const double tol2 = rtol * rtol * bb;
   if (s4[3] <= tol2) {
     __syncthreads();
     return 0;
@@ -1262,6 +1275,14 @@ __device__ __forceinline__ int blk_solve_g(const BlockSolve<N1C, TA, MT>& W, App
   for (int it = 1; it <= maxit; ++it) {
     x += alpha * pv;
     r -= alpha * sv;
+    if constexpr (EARLY) {
+      double e1[1] = {r * r};
+      block_sum<1, false>(e1, red + 64, nn);
+      if (e1[0] <= tol2) {
+        __syncthreads();
+        return it;
+      }
+    }
     if (own) W.R[pidx] = scaled ? r * sc : r;
     __syncthreads();
     blk_pinv(W, W.R, W.U);
@@ -2176,7 +2197,7 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
   W.Z = sp;    sp += NP * NP;
   W.DI = sp;   sp += NP * NP;
   W.Psi = sp;  sp += NP * NP;
-  double* red = sp;  sp += 64;
+  double* red = sp;  sp += MEM ? 80 : 64;   // MEM: the early stop test's slots
   double* lamr = sp; sp += NP;
   int* jc = reinterpret_cast<int*>(sp);
   W.boff = nullptr;
@@ -2262,14 +2283,17 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
         W.DI[pidx] = 1.0 / dS;
       }
       double y = x0;
-      int itS = blk_solve_g(W, apply, red, y, own ? fu : 0.0, cw, wt, a.rtol, a.maxit, false);
+      using App = decltype(apply)&;
+      int itS = blk_solve_g<N1C, double, MT, App, MEM>(W, apply, red, y, own ? fu : 0.0, cw, wt,
+                                                       a.rtol, a.maxit, false);
       if (itS > a.maxit && a.el.dlog) {
         if (own) {
           const int kx = t % n1, ky = t / n1;
           W.DI[pidx] = 1.0 / (t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky]);
         }
         y = x0;
-        itS = blk_solve_g(W, apply, red, y, own ? fu : 0.0, cw, wt, a.rtol, a.maxit, false);
+        itS = blk_solve_g<N1C, double, MT, App, MEM>(W, apply, red, y, own ? fu : 0.0, cw, wt,
+                                                     a.rtol, a.maxit, false);
       }
       if (own) a.xS[gi] = y;
       if (t == 0) split_count(a, e, 0, itS);
@@ -2283,7 +2307,7 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
         W.DI[pidx] = 1.0 / scp[4];
       }
       take(a, a.el.Mreg + e * per);
-      const int itM = blk_solve_g(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
+      const int itM = blk_solve_g<N1C, double, MT, decltype(apply)&, MEM>(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
                                   false, a.el.msc != nullptr, ms);
       if (own) a.xM[gi] = z;
       if (t == 0) split_count(a, e, 1, itM);
@@ -3293,7 +3317,8 @@ static hipError_t split_solve_mem(int op, const SplitSet& S, const PcgStageArgs&
                                   hipStream_t st) {
   if (S.el_start || h.pc32 || h.blk_threads != kMemMaxThreads || threads != kMemMaxThreads)
     return hipErrorInvalidValue;   // the kernel's compiled slot stride
-  const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
+  const size_t lds = (solve_lds_doubles<N1C>(h.blk_WB) + 16) * sizeof(double) +   // + early-test slots
+                     (size_t)h.blk_K * sizeof(int);
   const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, false, true>
                           : (const void*)k_pcg_solve<1, N1C, P, false, true>;
   const unsigned grid = persistent_grid(k, threads, lds, S.total);
