@@ -2197,7 +2197,10 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
   W.Z = sp;    sp += NP * NP;
   W.DI = sp;   sp += NP * NP;
   W.Psi = sp;  sp += NP * NP;
-  double* red = sp;  sp += MEM ? 80 : 64;   // MEM: the early stop test's slots
+  // the early stop test (its own slots) where a product costs more than a reduction: the
+  // streamed operators, and the M_J solves (few iterations, so the saved product weighs more)
+  constexpr bool EARLY = MEM || OP == 1;
+  double* red = sp;  sp += EARLY ? 80 : 64;
   double* lamr = sp; sp += NP;
   int* jc = reinterpret_cast<int*>(sp);
   W.boff = nullptr;
@@ -2284,16 +2287,16 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
       }
       double y = x0;
       using App = decltype(apply)&;
-      int itS = blk_solve_g<N1C, double, MT, App, MEM>(W, apply, red, y, own ? fu : 0.0, cw, wt,
-                                                       a.rtol, a.maxit, false);
+      int itS = blk_solve_g<N1C, double, MT, App, EARLY>(W, apply, red, y, own ? fu : 0.0, cw, wt,
+                                                         a.rtol, a.maxit, false);
       if (itS > a.maxit && a.el.dlog) {
         if (own) {
           const int kx = t % n1, ky = t / n1;
           W.DI[pidx] = 1.0 / (t == 0 ? d00 : kbr * lamr[kx] + kbs * lamr[ky]);
         }
         y = x0;
-        itS = blk_solve_g<N1C, double, MT, App, MEM>(W, apply, red, y, own ? fu : 0.0, cw, wt,
-                                                     a.rtol, a.maxit, false);
+        itS = blk_solve_g<N1C, double, MT, App, EARLY>(W, apply, red, y, own ? fu : 0.0, cw, wt,
+                                                       a.rtol, a.maxit, false);
       }
       if (own) a.xS[gi] = y;
       if (t == 0) split_count(a, e, 0, itS);
@@ -2307,7 +2310,7 @@ void k_pcg_solve(const PcgStageArgs* __restrict__ args, const long* __restrict__
         W.DI[pidx] = 1.0 / scp[4];
       }
       take(a, a.el.Mreg + e * per);
-      const int itM = blk_solve_g<N1C, double, MT, decltype(apply)&, MEM>(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
+      const int itM = blk_solve_g<N1C, double, MT, decltype(apply)&, EARLY>(W, apply, red, z, own ? rv : 0.0, 0.0, 0.0, a.rtol, a.maxit,
                                   false, a.el.msc != nullptr, ms);
       if (own) a.xM[gi] = z;
       if (t == 0) split_count(a, e, 1, itM);
@@ -3287,7 +3290,9 @@ static hipError_t split_solve_t(int op, const SplitSet& S, const PcgStageArgs& h
     }
   }
   if (h.pc32) return hipErrorInvalidValue;     // no FP32 chain in the per-node kernels
-  const size_t lds = solve_lds_doubles<N1C>(h.blk_WB) * sizeof(double) + (size_t)h.blk_K * sizeof(int);
+  // (+ 16 doubles: the M_J solve's early-test slots)
+  const size_t lds = (solve_lds_doubles<N1C>(h.blk_WB) + (op == 1 ? 16 : 0)) * sizeof(double) +
+                     (size_t)h.blk_K * sizeof(int);
   const void* k = op == 0 ? (const void*)k_pcg_solve<0, N1C, P, GRP>
                           : (const void*)k_pcg_solve<1, N1C, P, GRP>;
   const unsigned grid = persistent_grid(k, threads, lds, S.total);
