@@ -25,6 +25,8 @@ equations", arXiv:2105.01722, that it follows):
                  assembled by Gauss-Legendre quadrature, dense direct solves.
 * ``pcg``     -- preconditioned conjugate gradients for the element systems
                  (Sec. 7.1) with a tensor-product preconditioner.
+* ``ic0``     -- the zero-fill incomplete Cholesky factor of the element
+                 matrices (Sec. 7.1's preconditioner) and CG with it.
 * ``mlp``     -- FP64 reference of the small network that corrects that
                  preconditioner (not in the paper).
 """
