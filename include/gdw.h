@@ -295,6 +295,23 @@ gdw_status gdw_set_precond_mlp(gdw_ctx* ctx, gdw_mlp* mlp, void* stream);
  * here: a shorter buffer is an out-of-bounds device read. */
 gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* stream);
 
+/* IC(0) baseline (Sec. 7.1: the paper inverts the element matrices by PCG with an
+ * incomplete Cholesky preconditioner).  2D PCG path, after gdw_set_coeff.  For every
+ * element e: factor the element matrix by zero-fill incomplete Cholesky on the GD stencil
+ * (|jx - ix| <= p, |jy - iy| <= p; op 0 takes S_hat's entries on that stencil, the
+ * rank-one mean term being dense), then solve S_hat x_e = b_e (op 0, the dU/dt system) or
+ * M_J x_e = b_e (op 1, the dV/dt system) by CG with that preconditioner from x_e = 0,
+ * stopping when ||r||_2 <= rtol ||b_e||_2 (r the CG recurrence residual) or after maxit
+ * iterations.  b, x: device FP64 [n_el][(N+1)^2] (element e = ey * nx + ex, node
+ * iy * (N+1) + ix), its: device int [n_el] iteration counts; the caller owns all three.
+ * A baseline beside the time loop's tensor-product preconditioner, not part of gdw_run:
+ * it allocates two operator-sized workspaces per call and synchronises the stream.
+ * Errors: EINVAL (FDM path, 3D, before gdw_set_coeff, op not 0/1, maxit < 1),
+ * ENOCONV (a non-positive pivot, or maxit reached; gdw_last_error names the element),
+ * ENOMEM. */
+gdw_status gdw_ic0_solve(gdw_ctx* ctx, int op, const double* b, double* x, double rtol,
+                         int maxit, int* its, void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Batches of independent problems (an addition for throughput on one GPU).
  *

@@ -19,7 +19,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
-SOURCES = ["gd1d_host.cpp", "fdm.hip", "pcg.hip", "mlp.hip", "api.hip", "batch.hip"]
+SOURCES = ["gd1d_host.cpp", "fdm.hip", "pcg.hip", "ic0.hip", "mlp.hip", "api.hip", "batch.hip"]
 
 
 def _compile(src):

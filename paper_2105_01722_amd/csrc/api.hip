@@ -17,6 +17,7 @@
 #include "ctx.h"
 #include "fdm.h"
 #include "gdw_internal.h"
+#include "ic0.h"
 #include "mlp.h"
 #include "pcg.h"
 #include "stencil.h"
@@ -1251,6 +1252,56 @@ extern "C" gdw_status gdw_precond_data(gdw_ctx* c, float* samples, float* target
     set_error("gdw_precond_data needs the PCG path after gdw_set_coeff"); return GDW_EINVAL;
   }
   GDW_HIP(launch_precond_data(c->g, c->el, c->c2n, c->Bs, samples, targets, c->nel, (hipStream_t)stream));
+  return GDW_OK;
+}
+
+extern "C" gdw_status gdw_ic0_solve(gdw_ctx* c, int op, const double* b, double* x, double rtol,
+                                    int maxit, int* its, void* stream) {
+  if (!c || !b || !x || !its) { set_error("NULL argument"); return GDW_EINVAL; }
+  if (c->solver != GDW_SOLVE_PCG || !c->have_coeff || c->dim != 2) {
+    set_error("gdw_ic0_solve needs the 2D PCG path after gdw_set_coeff"); return GDW_EINVAL;
+  }
+  if (op != 0 && op != 1) { set_error("op must be 0 (S_hat) or 1 (M_J)"); return GDW_EINVAL; }
+  if (!(rtol >= 0.0) || maxit < 1) { set_error("rtol >= 0 and maxit >= 1 required"); return GDW_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  const long nel = c->nel;
+  std::vector<int> lv;
+  int nfw = 0, nbw = 0;
+  gdw::ic0_levels(c->g.N, c->g.p, lv, &nfw, &nbw);
+  double* A = nullptr;
+  double* U = nullptr;
+  int* dlv = nullptr;
+  int* flags = nullptr;
+  const size_t opb = (size_t)nel * c->g.nst * sizeof(double);
+  hipError_t e = hipMalloc(&A, opb);
+  if (e == hipSuccess) e = hipMalloc(&U, opb);
+  if (e == hipSuccess) e = hipMalloc(&dlv, lv.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&flags, 2 * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dlv, lv.data(), lv.size() * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0x7f, 2 * sizeof(int), st);
+  if (e == hipSuccess)
+    e = gdw::launch_ic0(c->g, c->el, op, nel, A, U, dlv, nfw, nbw, b, x, rtol, maxit, its, flags,
+                        flags + 1, st);
+  int hf[2] = {kFailNone, kFailNone};
+  if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(A);
+  (void)hipFree(U);
+  (void)hipFree(dlv);
+  (void)hipFree(flags);
+  if (e != hipSuccess) {
+    set_error(std::string("gdw_ic0_solve: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;
+  }
+  if (hf[0] != kFailNone) {
+    set_error("IC(0) breakdown (non-positive pivot) in element " + std::to_string(hf[0]));
+    return GDW_ENOCONV;
+  }
+  if (hf[1] != kFailNone) {
+    set_error("IC(0)-PCG reached maxit in element " + std::to_string(hf[1]));
+    return GDW_ENOCONV;
+  }
   return GDW_OK;
 }
 

@@ -84,6 +84,7 @@ def _load():
         "gdw_precond_data": (I, [P, P, P, P]),
         "gdw_set_precond_mlp": (I, [P, P, P]),
         "gdw_set_precond_log": (I, [P, P, P]),
+        "gdw_ic0_solve": (I, [P, I, P, P, D, I, P, P]),
         "gdw_batch_create": (I, [I, ctypes.POINTER(gdw_desc), ctypes.POINTER(P)]),
         "gdw_batch_ctx": (I, [P, I, ctypes.POINTER(P)]),
         "gdw_batch_tune": (I, [P, ctypes.POINTER(D), P]),
@@ -281,6 +282,20 @@ class Solver:
                                     ctypes.c_void_p(tgt.data_ptr()), _stream(stream)),
                "gdw_precond_data")
         return smp, tgt
+
+    def ic0_solve(self, op, b, rtol=1e-12, maxit=200, stream=None):
+        """IC(0)-PCG solve of every element system (op 0: S_hat, op 1: M_J) for the
+        right-hand sides b [n_el, (N+1)^2] (float64 CUDA tensor); returns (x, its)."""
+        import torch
+        d = self.desc
+        nel, nn = d.nx * d.ny, (d.N + 1) ** 2
+        bp = _dptr(b, nel * nn, "b")
+        x = torch.empty((nel, nn), dtype=torch.float64, device="cuda")
+        its = torch.empty(nel, dtype=torch.int32, device="cuda")
+        _check(lib.gdw_ic0_solve(self.ctx, int(op), bp, ctypes.c_void_p(x.data_ptr()),
+                                 float(rtol), int(maxit), ctypes.c_void_p(its.data_ptr()),
+                                 _stream(stream)), "gdw_ic0_solve")
+        return x, its
 
     def set_precond_log(self, o=None, stream=None):
         import torch
