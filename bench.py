@@ -12,7 +12,8 @@ Printed: ONE JSON line.  `value` = DOF-updates/s in FP64 (nx*ny*(N+1)^2 * steps 
 time; inputs resident in HBM).  Also reported: the FP32-storage mode, the error of
 both against the exact solution, the roofline of the stage kernel (algorithmic HBM
 bytes per launch / measured average launch time), the variable-coefficient mapped PCG
-workload in FP64 and in mixed precision (`pcg`), the same grid as the headline with
+workload in FP64 and in mixed precision (`pcg`) with the IC(0) baseline solves of its
+element systems (`pcg.ic0_baseline`), the same grid as the headline with
 Dirichlet walls (`walls`), box elements in 3D (`fdm3d`), the learned preconditioner
 (`learned`),
 the 64-problem batch (`batch`) and the FP64 CPU oracle timed on a bounded sample on the
@@ -263,6 +264,34 @@ def _time_pcg(w, steps, warmup, rtol=1e-12, precision="fp64"):
                 "max_it_M": st["max_it_M"], "mean_refine": mR}, (U, V)
 
 
+def _ic0_section(w, reps=2, seed=21, rtol=1e-12):
+    """IC(0) baseline (Sec. 7.1's preconditioner) on the PCG workload's element systems: one
+    IC(0)-PCG solve of every element's S_hat and M_J system from x = 0 for a seeded random
+    right-hand side (N(0, 1) entries).  The entry point factors and solves in one synchronous
+    call; the time is the host clock around the last of `reps` calls, so it includes the
+    call's workspace allocation."""
+    import time
+    import torch
+    from paper_2105_01722_amd import gdw
+    n, N, p = w["n"], w["N"], w["p"]
+    s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
+                   mapped=True, pcg_rtol=rtol)
+    s.set_coeff(w["c2"], w["X"], w["Y"])
+    b = torch.from_numpy(np.random.default_rng(seed).standard_normal((n * n, (N + 1) ** 2))).cuda()
+    res = {"rhs": "seeded N(0, 1) entries, x0 = 0, rtol %g" % rtol}
+    for op, name in ((0, "S_hat"), (1, "M_J")):
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, its = s.ic0_solve(op, b, rtol=rtol, maxit=500)
+            t1 = time.perf_counter()
+        its = its.cpu().numpy()
+        res[name] = {"ms_all_elements": (t1 - t0) * 1e3, "mean_it": float(its.mean()),
+                     "max_it": int(its.max())}
+    s.close()
+    return res
+
+
 def _learned_section(steps, epochs=60, n_train=20000, seed_train=5000, seed_test=6):
     """Learned correction of the tensor-product preconditioner on the 256 x 256 Cartesian
     variable-coefficient workload (N=12, p=5, upwind, rtol 1e-10): train on the solver's
@@ -476,6 +505,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems section")
     ap.add_argument("--batch-only", action="store_true",
                     help="profiling aid: run only the batched-problems section")
+    ap.add_argument("--ic0-only", action="store_true",
+                    help="only the IC(0) baseline solves on the PCG workload")
     ap.add_argument("--pcg-only", action="store_true",
                     help="profiling aid: run only the PCG workload (prints its section only)")
     ap.add_argument("--pcg-steps", type=int, default=5, help="timed RK4 steps of the PCG workload")
@@ -506,6 +537,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps({"batch": _batch_section(max(1, min(args.steps, 5)))}))
+        return
+    if args.ic0_only:
+        print(json.dumps({"ic0": _ic0_section(_pcg_workload())}))
         return
     if args.pcg_only:
         pw = _pcg_workload()
@@ -592,6 +626,11 @@ def main():
         msp, itp, stp = _time_pcg(pw, ksteps, 1, precision="pc32")
         print("bench: pcg pc32 %.3f ms/step" % (msp / ksteps), file=sys.stderr, flush=True)
         dpc = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(stp, st64))
+        ic0r = _ic0_section(pw)
+        print("bench: pcg ic0 baseline S %.1f its %.1f ms, M %.1f its %.1f ms"
+              % (ic0r["S_hat"]["mean_it"], ic0r["S_hat"]["ms_all_elements"],
+                 ic0r["M_J"]["mean_it"], ic0r["M_J"]["ms_all_elements"]), file=sys.stderr,
+              flush=True)
         flops = _pcg_flops_per_step(its, pn * pn, pN, pw["p"]) * ksteps / (ms * 1e-3)
         pbytes = _pcg_alg_bytes_per_dof_update(pN, pw["p"])
         pach = pbytes * pdof * ksteps / (ms * 1e-3)
@@ -625,6 +664,7 @@ def main():
                            "note": "preconditioner transforms on the FP32 matrix cores inside the "
                                    "FP64 recurrence (operator products, residuals and the stop "
                                    "test FP64); same rtol as the FP64 path"},
+            "ic0_baseline": ic0r,
         }
     if not args.no_learned:
         out["learned"] = _learned_section(max(1, min(args.steps, 3)))

@@ -81,3 +81,23 @@ def test_breakdown_raises():
     A = np.array([[1.0, 2.0], [2.0, 1.0]])
     with pytest.raises(np.linalg.LinAlgError):
         ic0.ic0(A, np.ones((2, 2), dtype=bool))
+
+
+def test_kronecker_mass_is_factored_exactly():
+    """On a Cartesian element M_J = |Omega| Mref (x) Mref; the Cholesky factor of a Kronecker
+    product is the Kronecker product of the factors, whose band stays inside the GD stencil,
+    so IC(0) is exact and PCG on the dV/dt system takes one iteration (the paper's count of 1
+    for dV/dt with its Kronecker mass matrix, Table 5)."""
+    from oracle import gd1d
+    N, p = 10, 3
+    Mh, _ = gd1d.matrices_unit(N, p)
+    Mref = Mh / N
+    area = 0.37
+    A = area * np.kron(Mref, Mref)
+    U = ic0.ic0(A, ic0.stencil(N, p))
+    Lr = np.linalg.cholesky(Mref)
+    np.testing.assert_allclose(U, np.sqrt(area) * np.kron(Lr, Lr).T, rtol=1e-12,
+                               atol=1e-13 * abs(U).max())
+    b = np.random.default_rng(7).standard_normal(A.shape[0])
+    _, its, _ = ic0.ic0_pcg(A, b, ic0.stencil(N, p), 1e-12, 10)
+    assert its == 1
