@@ -68,3 +68,46 @@ def test_ic0_maxit_and_zero_rhs():
     x, its = s.ic0_solve(1, torch.zeros_like(bg))
     assert (its.cpu() == 0).all() and (x.cpu() == 0).all()
     s.close()
+
+
+def test_ic0_full_size_sampled():
+    """The bench's IC(0) launch at full size: 128 x 128 mapped elements, N = 12, p = 5,
+    c^2 field seed 3, right-hand side seed 21.  On five sampled elements (corners, interior)
+    the iteration counts are within one of the oracle's and the true residual
+    ||b - A x|| / ||b|| is at most ten times the oracle's own (or 10 rtol).  A sampled
+    element's matrices come from a one-element oracle problem on its own nodes (element
+    matrices depend on nothing else).  rtol is 1e-10 here: cond(S_hat) is about 2e8 at this
+    element size, and the true residual of CG stalls near 1e-9 while the recurrence one
+    keeps falling, so at 1e-12 the count depends on rounding (the oracle itself gives 12 or
+    16 iterations for one element whose matrix is assembled in two orders)."""
+    import torch
+    from paper_2105_01722_amd import gdw
+    n, N, p, rtol = 128, 12, 5, 1e-10
+    _say("case: ic0 full size 128x128 N12 p5")
+    X, Y = inputs.node_coords(n, n, N)
+    c2 = inputs.c2_field(3, X, Y)
+    Xm, Ym = inputs.mapped_coords(X, Y)
+    s = gdw.Solver(n, n, N, p, flux="upwind", xi=1.0, solver="pcg", coeff_variable=True,
+                   mapped=True, pcg_rtol=rtol)
+    s.set_coeff(c2, Xm, Ym)
+    nn = (N + 1) ** 2
+    b = np.random.default_rng(21).standard_normal((n * n, nn))
+    bg = torch.from_numpy(b).cuda()
+    P = ic0.stencil(N, p)
+    samples = [(0, 0), (n - 1, n - 1), (0, n - 1), (n // 2, n // 3), (n // 5, 3 * n // 4)]
+    for op in (0, 1):
+        x, its = s.ic0_solve(op, bg, rtol=rtol, maxit=500)
+        x, its = x.cpu().numpy(), its.cpu().numpy()
+        _say("  op %d: mean its %.2f max %d" % (op, its.mean(), its.max()))
+        for cy, cx in samples:
+            sl = (slice(cy, cy + 1), slice(cx, cx + 1))
+            ops = general.GenOps(general.GenProblem(nx=1, ny=1, N=N, p=p), Xm[sl], Ym[sl], c2[sl])
+            A = ic0.element_systems(ops, op)[0]
+            e = cy * n + cx
+            xo, ito, _ = ic0.ic0_pcg(A, b[e], P, rtol, 500)
+            assert abs(int(its[e]) - ito) <= 1, (op, e, its[e], ito)
+            nb = np.linalg.norm(b[e])
+            res_o = np.linalg.norm(b[e] - A @ xo) / nb
+            res_g = np.linalg.norm(b[e] - A @ x[e]) / nb
+            assert res_g <= max(10 * res_o, 10 * rtol), (op, e, res_g, res_o)
+    s.close()
