@@ -268,8 +268,8 @@ def _ic0_section(w, reps=2, seed=21, rtol=1e-12):
     """IC(0) baseline (Sec. 7.1's preconditioner) on the PCG workload's element systems: one
     IC(0)-PCG solve of every element's S_hat and M_J system from x = 0 for a seeded random
     right-hand side (N(0, 1) entries).  The entry point factors and solves in one synchronous
-    call; the time is the host clock around the last of `reps` calls, so it includes the
-    call's workspace allocation."""
+    call; the time is the host clock around the last of `reps` calls (the first one
+    allocates the context's workspace, which the later ones reuse)."""
     import time
     import torch
     from paper_2105_01722_amd import gdw

@@ -305,7 +305,8 @@ gdw_status gdw_set_precond_log(gdw_ctx* ctx, const float* log_scale, void* strea
  * iterations.  b, x: device FP64 [n_el][(N+1)^2] (element e = ey * nx + ex, node
  * iy * (N+1) + ix), its: device int [n_el] iteration counts; the caller owns all three.
  * A baseline beside the time loop's tensor-product preconditioner, not part of gdw_run:
- * it allocates two operator-sized workspaces per call and synchronises the stream.
+ * the first call allocates two operator-sized workspaces (2 n_el nst doubles, nst the
+ * upper-half stencil size), kept until gdw_destroy; every call synchronises the stream.
  * Errors: EINVAL (FDM path, 3D, before gdw_set_coeff, op not 0/1, maxit < 1),
  * ENOCONV (a non-positive pivot, or maxit reached; gdw_last_error names the element),
  * ENOMEM. */

@@ -43,6 +43,7 @@ static void free_all(gdw_ctx* c) {
   F(c->el.w); F(c->el.sc); F(c->el.face);
   F(c->el.dlog); F(c->el.dscale); F(c->xS); F(c->xM); F(c->Fu); F(c->Fv); F(c->its); F(c->fail); F(c->coords); F(c->c2n);
   F(c->d_pargs); F(c->d_pel);
+  F(c->ic0_A); F(c->ic0_U); F(c->ic0_lv); F(c->ic0_flags);
 }
 
 // The stage arguments derived from the context (pointers of the element data) changed.
@@ -1265,34 +1266,36 @@ extern "C" gdw_status gdw_ic0_solve(gdw_ctx* c, int op, const double* b, double*
   if (!(rtol >= 0.0) || maxit < 1) { set_error("rtol >= 0 and maxit >= 1 required"); return GDW_EINVAL; }
   hipStream_t st = (hipStream_t)stream;
   const long nel = c->nel;
-  std::vector<int> lv;
-  int nfw = 0, nbw = 0;
-  gdw::ic0_levels(c->g.N, c->g.p, lv, &nfw, &nbw);
-  double* A = nullptr;
-  double* U = nullptr;
-  int* dlv = nullptr;
-  int* flags = nullptr;
-  const size_t opb = (size_t)nel * c->g.nst * sizeof(double);
-  hipError_t e = hipMalloc(&A, opb);
-  if (e == hipSuccess) e = hipMalloc(&U, opb);
-  if (e == hipSuccess) e = hipMalloc(&dlv, lv.size() * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&flags, 2 * sizeof(int));
+  if (!c->ic0_flags) {  // workspace of the first call, kept until gdw_destroy
+    std::vector<int> lv;
+    gdw::ic0_levels(c->g.N, c->g.p, lv, &c->ic0_nfw, &c->ic0_nbw);
+    const size_t opb = (size_t)nel * c->g.nst * sizeof(double);
+    hipError_t ea = hipMalloc(&c->ic0_A, opb);
+    if (ea == hipSuccess) ea = hipMalloc(&c->ic0_U, opb);
+    if (ea == hipSuccess) ea = hipMalloc(&c->ic0_lv, lv.size() * sizeof(int));
+    if (ea == hipSuccess)
+      ea = hipMemcpy(c->ic0_lv, lv.data(), lv.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (ea == hipSuccess) ea = hipMalloc(&c->ic0_flags, 2 * sizeof(int));
+    if (ea != hipSuccess) {  // leave no half-made workspace behind
+      for (void* q : {(void*)c->ic0_A, (void*)c->ic0_U, (void*)c->ic0_lv, (void*)c->ic0_flags})
+        if (q) (void)hipFree(q);
+      c->ic0_A = c->ic0_U = nullptr;
+      c->ic0_lv = c->ic0_flags = nullptr;
+      set_error(std::string("gdw_ic0_solve workspace: ") + hipGetErrorString(ea));
+      return ea == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;
+    }
+  }
+  int* flags = c->ic0_flags;
+  hipError_t e = hipMemsetAsync(flags, 0x7f, 2 * sizeof(int), st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(dlv, lv.data(), lv.size() * sizeof(int), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(flags, 0x7f, 2 * sizeof(int), st);
-  if (e == hipSuccess)
-    e = gdw::launch_ic0(c->g, c->el, op, nel, A, U, dlv, nfw, nbw, b, x, rtol, maxit, its, flags,
-                        flags + 1, st);
+    e = gdw::launch_ic0(c->g, c->el, op, nel, c->ic0_A, c->ic0_U, c->ic0_lv, c->ic0_nfw,
+                        c->ic0_nbw, b, x, rtol, maxit, its, flags, flags + 1, st);
   int hf[2] = {kFailNone, kFailNone};
   if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(A);
-  (void)hipFree(U);
-  (void)hipFree(dlv);
-  (void)hipFree(flags);
   if (e != hipSuccess) {
     set_error(std::string("gdw_ic0_solve: ") + hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? GDW_ENOMEM : GDW_EHIP;
+    return GDW_EHIP;
   }
   if (hf[0] != kFailNone) {
     set_error("IC(0) breakdown (non-positive pivot) in element " + std::to_string(hf[0]));

@@ -98,6 +98,13 @@ struct gdw_ctx {
   int args_epoch = 0;                     // bumped whenever stage arguments change
   int p_threads = 0;
   size_t p_lds = 0;
+  // IC(0) baseline workspace (first gdw_ic0_solve call): operator entries and factor
+  // [nel][nst], level tables of the triangular solves, breakdown / maxit flags
+  double* ic0_A = nullptr;
+  double* ic0_U = nullptr;
+  int* ic0_lv = nullptr;
+  int* ic0_flags = nullptr;
+  int ic0_nfw = 0, ic0_nbw = 0;
 };
 
 
