@@ -186,11 +186,17 @@ __global__ __launch_bounds__(64) void k_ic0_pcg(PcgGeom g, PcgElem el, int op, l
                                                  const double* A, const double* U, const int* lv,
                                                  int nfw, int nbw, const double* b, double* x,
                                                  double rtol, int maxit, int* its, int* fail) {
-  __shared__ double sx[kIc0MaxNodes], sr[kIc0MaxNodes], sz[kIc0MaxNodes], sd[kIc0MaxNodes],
-      sq[kIc0MaxNodes], sy[kIc0MaxNodes];
+  // six vectors of nn doubles in LDS, sized to the element so that more elements fit a CU
+  extern __shared__ double ic0_lds[];
+  const int nn = g.nn;
+  double* sx = ic0_lds;
+  double* sr = sx + nn;
+  double* sz = sr + nn;
+  double* sd = sz + nn;
+  double* sq = sd + nn;
+  double* sy = sq + nn;
   const long e = blockIdx.x;
   if (e >= nel) return;
-  const int nn = g.nn;
   // level tables: forward rows [nn], forward starts [nfw + 1], backward rows, starts
   const int* fw = lv;
   const int* fws = lv + nn;
@@ -288,8 +294,8 @@ hipError_t launch_ic0(const PcgGeom& g, const PcgElem& el, int op, long nel, dou
   hipLaunchKernelGGL(k_ic0_factor, dim3((unsigned)nel), dim3(256), 0, st, g, nel, U, bad);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_ic0_pcg, dim3((unsigned)nel), dim3(64), 0, st, g, el, op, nel, A, U, lv, nfw,
-                     nbw, b, x, rtol, maxit, its, fail);
+  hipLaunchKernelGGL(k_ic0_pcg, dim3((unsigned)nel), dim3(64), 6 * (size_t)g.nn * sizeof(double), st,
+                     g, el, op, nel, A, U, lv, nfw, nbw, b, x, rtol, maxit, its, fail);
   return hipGetLastError();
 }
 
