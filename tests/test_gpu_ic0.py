@@ -37,7 +37,9 @@ def _setup(n, N, p, mapped):
 
 @pytest.mark.parametrize("n,N,p,mapped,op", [(2, 8, 3, True, 0), (2, 8, 3, True, 1),
                                              (3, 12, 5, True, 0), (2, 12, 5, True, 1),
-                                             (2, 12, 5, False, 1), (2, 16, 7, True, 0)])
+                                             (2, 12, 5, False, 1), (2, 16, 7, True, 0),
+                                             (2, 16, 7, True, 1), (2, 16, 5, True, 0),
+                                             (2, 8, 3, False, 0), (3, 6, 3, True, 0)])
 def test_ic0_matches_oracle(n, N, p, mapped, op):
     _say("case: ic0", n, N, p, mapped, op)
     s, ops, b, bg = _setup(n, N, p, mapped)
